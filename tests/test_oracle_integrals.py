@@ -1,0 +1,227 @@
+"""Pins of the oracle's integrals against results fixed outside it.
+
+* s-s closed form (2 pi/p) exp(-mu R^2) F_0(T), F_0 via erf.
+* The one-center Coulomb integral at P: the printed Eq. 12 when l2 = 0, the closed form at
+  c = P (where the printed Eq. 12 gives 0), and complete blocks against an independent
+  Gaussian-transform quadrature and an independent Cartesian McMurchie-Davidson route.
+* The sign of the shift (Eq. 7): the p_z-s overlap closed form.
+* Unit self-overlap (normalisation, Eq. 10) and two-center overlaps against polynomial moments.
+* Invariants: rotation covariance with real Wigner-D matrices, translation invariance,
+  symmetry of V, and the double oracle's rounding error measured with __float128.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import xcheck
+from paper_2404_16245_amd import synth
+
+
+def two_shells(la, lb, A, B, ea, eb, da=None, db=None):
+    ea, eb = np.atleast_1d(np.asarray(ea, float)), np.atleast_1d(np.asarray(eb, float))
+    da = np.ones_like(ea) if da is None else np.asarray(da, float)
+    db = np.ones_like(eb) if db is None else np.asarray(db, float)
+    return synth.Basis(np.array([A, B], float), np.array([la, lb], np.int32),
+                       np.array([len(ea), len(eb)], np.int32), np.array([0, len(ea)], np.int64),
+                       np.concatenate([ea, eb]), np.concatenate([da, db]))
+
+
+def block(basis, nuclei, a=0, b=1, precision=0):
+    flat = oracle.nuc_blocks(basis, nuclei, [a], [b], precision=precision)
+    return flat.reshape(2 * basis.l[a] + 1, 2 * basis.l[b] + 1)
+
+
+def test_ss_closed_form():
+    A, B, c = np.array([0.1, 0.5, -0.2]), np.array([1.3, -0.4, 0.8]), np.array([0.7, 0.2, 1.9])
+    a, b, Z = 0.9, 2.3, 3.0
+    bs = two_shells(0, 0, A, B, a, b)
+    V = block(bs, synth.Nuclei(c[None], np.array([Z])))[0, 0]
+    p = a + b
+    P = (a * A + b * B) / p
+    T = p * float((c - P) @ (c - P))
+    F0 = 0.5 * math.sqrt(math.pi / T) * math.erf(math.sqrt(T))
+    K = math.exp(-a * b / p * float((A - B) @ (A - B)))
+    N = lambda e: (2 * e / math.pi) ** 0.75
+    assert V == pytest.approx(-Z * 2 * math.pi / p * K * F0 * N(a) * N(b), rel=1e-14)
+
+
+def test_one_center_reduces_to_printed_eq12_when_l2_is_zero():
+    rng = np.random.default_rng(21)
+    for _ in range(4):
+        p = float(rng.uniform(0.3, 4.0))
+        C = rng.normal(size=3)
+        T = p * float(C @ C)
+        I = oracle.one_center(6, 0, p, C)
+        Y = oracle.solid_complex(6, *C)
+        for l1 in range(7):
+            F = xcheck.boys_mp(l1, T)
+            for m1 in range(-l1, l1 + 1):
+                ref = 2 * math.pi / p * Y[l1 * l1 + m1 + l1] * F
+                assert abs(I[l1 * l1 + m1 + l1, 0] - ref) <= 1e-13 * max(1.0, abs(ref))
+
+
+def test_one_center_at_nucleus_closed_form():
+    # C = 0: int z^2 exp(-p r^2)/r = 2 pi/(3 p^2); the printed Eq. 12 would give 0 here
+    p = 1.3
+    I = oracle.one_center(1, 1, p, [0.0, 0.0, 0.0])
+    assert I[2, 2].real == pytest.approx(2 * math.pi / (3 * p * p), rel=1e-14)
+    # and int (x^2+y^2+z^2) r^2-free part: Y^2_0 Y^0_0 gives zero at C = 0
+    I2 = oracle.one_center(2, 0, p, [0.0, 0.0, 0.0])
+    assert abs(I2[6, 0]) < 1e-15
+
+
+def test_one_center_against_quadrature():
+    # real combinations of the complex table against the Gaussian-transform quadrature
+    p, C = 1.3, np.array([0.4, -0.7, 0.9])
+    I = oracle.one_center(2, 2, p, C)
+    # z^2 = Y^1_0 Y^1_0 ; xy is (sqrt3)^-1 S^2_-2 -> check via a primitive block with A = B = 0
+    bs = two_shells(1, 1, np.zeros(3), np.zeros(3), p / 2, p / 2)
+    nuc = synth.Nuclei(C[None], np.array([-1.0]))   # V = -Z int -> +int
+    Vq = xcheck.contracted_block(xcheck.quad_nuclear_prim, bs, nuc, 0, 1)
+    Vo = block(bs, nuc)
+    assert np.allclose(Vo, Vq, rtol=1e-11, atol=1e-13)
+    N = xcheck.prim_norm(1, p / 2) ** 2
+    assert I[2, 2].real == pytest.approx(Vo[1, 1] / N, rel=1e-13)
+
+
+def test_pz_s_overlap_sign():
+    # unnormalised int z e^{-a r^2} e^{-b |r - B|^2} = K P_z (pi/p)^{3/2} > 0 for B = (0, 0, 1.1)
+    a, b, R = 0.8, 1.7, 1.1
+    bs = two_shells(1, 0, np.zeros(3), [0.0, 0.0, R], a, b)
+    S = oracle.overlap_blocks(bs, [0], [1]).reshape(3, 1)
+    p = a + b
+    ref = math.exp(-a * b / p * R * R) * (b * R / p) * (math.pi / p) ** 1.5
+    Np, Ns = xcheck.prim_norm(1, a), xcheck.prim_norm(0, b)
+    assert S[1, 0] / (Np * Ns) == pytest.approx(ref, rel=1e-14)
+    assert ref == pytest.approx(0.545564865805146, rel=1e-13)
+    assert abs(S[0, 0]) < 1e-16 and abs(S[2, 0]) < 1e-16
+
+
+def test_primitive_normalisation_by_polynomial_moments():
+    for l in range(7):
+        for a in [0.07, 1.0, 31.0]:
+            C = xcheck.real_solid_poly(l)
+            N = xcheck.prim_norm(l, a)
+            for m in range(2 * l + 1):
+                s = xcheck.cart_overlap_poly(C[m], l, np.zeros(3), a, C[m], l, np.zeros(3), a)
+                assert N * N * s == pytest.approx(1.0, rel=1e-12)
+
+
+def test_contracted_self_overlap_is_unity():
+    bs, _ = synth.small_molecule(seed=1)
+    hi, _ = synth.molecule(seed=4, n_atoms=2, box=3.0, ls=(3, 4, 5, 6), kmax=5)
+    for basis in (bs, hi):
+        idx = np.arange(basis.n_shells)
+        for B in oracle.split_blocks(oracle.overlap_blocks(basis, idx, idx), basis, idx, idx):
+            assert np.abs(B - np.eye(B.shape[0])).max() < 1e-13
+
+
+@pytest.mark.parametrize("la,lb", [(1, 0), (2, 1), (3, 3), (4, 2), (6, 5)])
+def test_two_center_overlap_against_polynomial_moments(la, lb):
+    rng = np.random.default_rng(100 + 10 * la + lb)
+    A, B = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+    a, b = 0.6, 1.4
+    bs = two_shells(la, lb, A, B, a, b)
+    S = oracle.overlap_blocks(bs, [0], [1]).reshape(2 * la + 1, 2 * lb + 1)
+    Ca, Cb = xcheck.real_solid_poly(la), xcheck.real_solid_poly(lb)
+    Na, Nb = xcheck.prim_norm(la, a), xcheck.prim_norm(lb, b)
+    ref = np.array([[xcheck.cart_overlap_poly(Ca[i], la, A, a, Cb[j], lb, B, b) for j in range(2 * lb + 1)]
+                    for i in range(2 * la + 1)]) * Na * Nb
+    assert np.allclose(S, ref, rtol=1e-11, atol=1e-14)
+
+
+CLASSES = [(la, lb) for la in range(7) for lb in range(la + 1)] + [(0, 3), (2, 6), (1, 4)]
+
+
+@pytest.mark.parametrize("la,lb", CLASSES)
+def test_blocks_against_mcmurchie_davidson(la, lb):
+    rng = np.random.default_rng(1000 + 10 * la + lb)
+    A, B = rng.uniform(0, 3, 3), rng.uniform(0, 3, 3)
+    ea, eb = np.exp(rng.uniform(np.log(0.1), np.log(20), 2)), np.exp(rng.uniform(np.log(0.1), np.log(20), 2))
+    da, db = rng.uniform(0.1, 1, 2), rng.uniform(0.1, 1, 2)
+    bs = two_shells(la, lb, A, B, ea, eb, da, db)
+    nuc = synth.Nuclei(rng.uniform(0, 3, (2, 3)), np.array([3.0, 7.0]))
+    V = block(bs, nuc)
+    ref = xcheck.contracted_block(xcheck.md_nuclear_prim, bs, nuc, 0, 1)
+    scale = np.abs(ref).max()
+    assert np.abs(V - ref).max() <= 1e-12 * scale, np.abs(V - ref).max() / scale
+
+
+@pytest.mark.parametrize("la,lb", [(0, 0), (1, 0), (1, 1), (2, 1), (2, 2), (3, 1)])
+def test_blocks_against_quadrature(la, lb):
+    rng = np.random.default_rng(2000 + 10 * la + lb)
+    A, B = rng.uniform(0, 2, 3), rng.uniform(0, 2, 3)
+    bs = two_shells(la, lb, A, B, [0.5, 2.0], [0.9], [0.6, 0.4], [1.0])
+    nuc = synth.Nuclei(rng.uniform(0, 2, (1, 3)), np.array([2.0]))
+    V = block(bs, nuc)
+    ref = xcheck.contracted_block(xcheck.quad_nuclear_prim, bs, nuc, 0, 1)
+    assert np.allclose(V, ref, rtol=1e-10, atol=1e-12)
+
+
+def real_wigner_d(l, Q):
+    """D^l with S^l(Q x) = D^l S^l(x), by least squares over random points."""
+    rng = np.random.default_rng(77 + l)
+    X = rng.normal(size=(4 * (2 * l + 1) + 5, 3))
+    Sx = np.array([xcheck.eval_real_solid(l, *x) for x in X])
+    SQx = np.array([xcheck.eval_real_solid(l, *(Q @ x)) for x in X])
+    Dt, *_ = np.linalg.lstsq(Sx, SQx, rcond=None)
+    return Dt.T
+
+
+def test_rotation_covariance():
+    bs, nuc = synth.molecule(seed=31, n_atoms=3, box=3.0, ls=(0, 1, 2, 3, 4, 5, 6), kmax=2)
+    Q = synth.random_rotation(5)
+    rot = synth.Basis(bs.center @ Q.T, bs.l, bs.nprim, bs.prim_off, bs.expo, bs.coef)
+    nuc_r = synth.Nuclei(nuc.pos @ Q.T, nuc.Z)
+    pa, pb = synth.all_pairs(bs.n_shells)
+    sel = np.arange(0, len(pa), 7)
+    pa, pb = pa[sel], pb[sel]
+    B0 = oracle.split_blocks(oracle.nuc_blocks(bs, nuc, pa, pb), bs, pa, pb)
+    B1 = oracle.split_blocks(oracle.nuc_blocks(rot, nuc_r, pa, pb), bs, pa, pb)
+    D = [real_wigner_d(l, Q) for l in range(7)]
+    for i in range(len(pa)):
+        la, lb = bs.l[pa[i]], bs.l[pb[i]]
+        ref = D[la] @ B0[i] @ D[lb].T
+        assert np.allclose(B1[i], ref, rtol=1e-9, atol=1e-11 * max(1.0, np.abs(ref).max()))
+
+
+def test_translation_invariance_and_symmetry():
+    bs, nuc = synth.small_molecule(seed=1)
+    V = oracle.nuc_matrix(bs, nuc)
+    shift = np.array([3.3, -1.7, 12.0])
+    bs2 = synth.Basis(bs.center + shift, bs.l, bs.nprim, bs.prim_off, bs.expo, bs.coef)
+    V2 = oracle.nuc_matrix(bs2, synth.Nuclei(nuc.pos + shift, nuc.Z))
+    assert np.allclose(V, V2, rtol=1e-12, atol=1e-13)
+    pa, pb = synth.all_pairs(bs.n_shells)
+    Bab = oracle.split_blocks(oracle.nuc_blocks(bs, nuc, pa, pb), bs, pa, pb)
+    Bba = oracle.split_blocks(oracle.nuc_blocks(bs, nuc, pb, pa), bs, pb, pa)
+    for x, y in zip(Bab, Bba):
+        assert np.allclose(x, y.T, rtol=1e-13, atol=1e-14)
+
+
+def test_no_nuclei_and_screening_edges():
+    bs, nuc = synth.small_molecule(seed=1)
+    empty = synth.Nuclei(np.zeros((0, 3)), np.zeros(0))
+    assert np.all(oracle.nuc_matrix(bs, empty) == 0.0)
+    # a threshold above 1 drops every primitive pair
+    assert np.all(oracle.nuc_matrix(bs, nuc, screen=1.5) == 0.0)
+    # a threshold that keeps all pairs leaves V unchanged
+    assert np.array_equal(oracle.nuc_matrix(bs, nuc, screen=1e-300), oracle.nuc_matrix(bs, nuc))
+
+
+def test_double_oracle_rounding_error():
+    # the double oracle against its __float128 instantiation (same code, 113-bit mantissa):
+    # its own error must sit ten times inside the GPU parity bar (1e-13 abs + 1e-11 rel)
+    bs, nuc = synth.small_molecule(seed=1)
+    V = oracle.nuc_matrix(bs, nuc)
+    Vq = oracle.nuc_matrix(bs, nuc, precision=2)
+    assert np.all(np.abs(V - Vq) <= 1e-14 + 1e-12 * np.abs(Vq))
+    assert np.abs(V - Vq).max() <= 1e-15 * np.abs(Vq).max()
+    # a high-l sample of the sweep workload
+    hb, hn, pa, pb = synth.high_l_sweep(seed=2, pairs_per_class=2, classes=[(6, 6), (5, 3), (0, 6), (4, 4)])
+    B = oracle.nuc_blocks(hb, hn, pa, pb)
+    Bq = oracle.nuc_blocks(hb, hn, pa, pb, precision=2)
+    assert np.all(np.abs(B - Bq) <= 1e-14 + 1e-12 * np.abs(Bq))
+    assert np.abs(B - Bq).max() <= 1e-14 * np.abs(Bq).max()
