@@ -1,0 +1,138 @@
+/* shgo.h -- C ABI of the MI355X (gfx950) library for one-electron nuclear-attraction integrals
+ * over contracted solid-harmonic Gaussian orbitals (SHGOs).
+ *
+ * Method: Hu, Peslherbe, Ooi and Hu, "Computationally Efficient Molecular Integrals of Solid
+ * Harmonic Gaussian Orbitals Using Quantum Entanglement of Angular Momentum" (arXiv:2404.16245).
+ * A shell is a center, an angular momentum l and K primitives (exponents, contraction
+ * coefficients) as in Eq. 1; nuclei are point charges at positions c (the operator of Eq. 11).
+ * The result is V_{(a,ma),(b,mb)} = -sum_c Z_c int chi_{a,ma}(r) chi_{b,mb}(r) / |r - c| d^3r
+ * in the real solid-harmonic basis (Eq. 2 normalisation, order m = -l..l; l = 1 is y, z, x).
+ * Every step of the evaluation -- primitive normalisation, shell-pair enumeration, screening,
+ * class sort, Gaussian product (Eq. 5), shift to P (Eqs. 7-8), product rule (supplement Eq. 4),
+ * one-center integral with the Boys function (Eqs. 11-12), sum over nuclei, contraction and
+ * scatter -- runs in device kernels; the host only validates and copies inputs at plan time.
+ *
+ * Conventions
+ *   - Units are atomic (bohr, hartree).
+ *   - Basis functions are numbered shell by shell: index = offset(shell) + m + l.
+ *   - Primitive normalisation N(l,a)^2 = 2^l (2a)^{l+3/2} / ((2l-1)!! pi^{3/2}); the caller's
+ *     contraction coefficients multiply normalised primitives and the contracted shell is
+ *     renormalised to unit self-overlap (the paper names N in Eq. 1 but does not give it).
+ *   - Ownership: the caller owns every buffer passed in. Plan creation copies the host inputs
+ *     to device memory owned by the plan; nothing passed in is retained.
+ *   - Streams: stream arguments are hipStream_t values (NULL = the null stream). Work is
+ *     enqueued asynchronously; the caller synchronises.
+ *   - Errors: every call that can fail returns shgo_status (SHGO_OK == 0); the context keeps a
+ *     message for the last failure (shgo_last_error). Validation happens on the host before any
+ *     device work and nothing is written on a validation error. After SHGO_ERR_DEVICE the
+ *     output contents are unspecified.
+ *   - A context or plan is not thread-safe; use one per host thread.
+ */
+#ifndef SHGO_H
+#define SHGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHGO_LMAX 6 /* highest supported angular momentum of a shell */
+#define SHGO_NUM_CLASSES 28 /* (la, lb) classes with SHGO_LMAX >= la >= lb >= 0 */
+
+typedef enum {
+  SHGO_OK = 0,
+  SHGO_ERR_INVALID_ARG = 1,   /* null pointer, negative count, exponent <= 0, bad index */
+  SHGO_ERR_UNSUPPORTED_L = 2, /* l < 0 or l > SHGO_LMAX */
+  SHGO_ERR_NOT_FINITE = 3,    /* NaN or Inf in a coordinate, exponent, coefficient or charge */
+  SHGO_ERR_OUT_OF_MEMORY = 4, /* device allocation failed */
+  SHGO_ERR_DEVICE = 5,        /* HIP runtime or kernel launch error */
+  SHGO_ERR_INTERNAL = 6
+} shgo_status;
+
+typedef struct shgo_context shgo_context; /* device tables (Boys interpolation table) */
+typedef struct shgo_plan shgo_plan;       /* device copies of one basis + nuclei + workspace */
+
+/* Basis set in host memory (read during plan creation only). */
+typedef struct {
+  int32_t n_shells;
+  const double* center;       /* [n_shells][3] */
+  const int32_t* l;           /* [n_shells], 0..SHGO_LMAX */
+  const int32_t* n_prim;      /* [n_shells], >= 1 */
+  const int64_t* prim_offset; /* [n_shells], first primitive of each shell in exponent/coef */
+  const double* exponent;     /* [total primitives], > 0 */
+  const double* coef;         /* [total primitives], coefficients of normalised primitives */
+} shgo_basis;
+
+/* Point nuclei in host memory (read during plan creation only). */
+typedef struct {
+  int32_t n_nuclei;        /* >= 0; zero nuclei gives V = 0 */
+  const double* position;  /* [n_nuclei][3] */
+  const double* charge;    /* [n_nuclei] (Z) */
+} shgo_nuclei;
+
+/* Create a context on HIP device `device` (tables are built on the host and uploaded).
+ * Returns SHGO_ERR_DEVICE if the device cannot be used. */
+shgo_status shgo_create(int device, shgo_context** ctx);
+void shgo_destroy(shgo_context* ctx);
+
+const char* shgo_status_string(shgo_status s);
+const char* shgo_last_error(const shgo_context* ctx);
+
+/* Number of basis functions sum_s (2 l_s + 1); -1 on invalid input. Host only. */
+int64_t shgo_nbf(const shgo_basis* basis);
+
+/* The host-side validation that plan creation performs, without touching a device.
+ * Returns the status plan creation would return for these inputs and, when msg is not NULL,
+ * copies a NUL-terminated message of at most msg_len bytes into it. */
+shgo_status shgo_validate(const shgo_basis* basis, const shgo_nuclei* nuclei, double screen, char* msg,
+                          size_t msg_len);
+
+/* Plan for the full symmetric matrix V (nbf x nbf, row-major) over every shell pair a <= b.
+ * screen > 0 drops primitive pairs with exp(-ab/(a+b) |A-B|^2) <= screen (0 keeps all; a pair
+ * whose primitive pairs are all dropped gives a zero block).  Validates the inputs, copies them
+ * to the device and allocates the plan's workspace. */
+shgo_status shgo_plan_matrix(shgo_context* ctx, const shgo_basis* basis, const shgo_nuclei* nuclei,
+                             double screen, shgo_plan** plan);
+
+/* Plan for an explicit list of shell pairs (pair_a[i], pair_b[i]), host arrays of n_pairs
+ * shell indices. The output holds the blocks back to back in list order, block i being
+ * (2 l_a + 1) x (2 l_b + 1) row-major (rows follow shell pair_a[i]). */
+shgo_status shgo_plan_pairs(shgo_context* ctx, const shgo_basis* basis, const shgo_nuclei* nuclei,
+                            int64_t n_pairs, const int32_t* pair_a, const int32_t* pair_b, double screen,
+                            shgo_plan** plan);
+
+void shgo_plan_destroy(shgo_plan* plan);
+
+/* Number of doubles the plan writes (nbf*nbf for a matrix plan, sum of block sizes otherwise). */
+int64_t shgo_plan_output_size(const shgo_plan* plan);
+
+/* Number of integrals one execution computes: sum over the plan's shell pairs of
+ * (2 l_a + 1)(2 l_b + 1) (unique pairs a <= b for a matrix plan). */
+int64_t shgo_plan_integrals(const shgo_plan* plan);
+
+/* Run the whole evaluation on `stream`, writing the plan's output into the device buffer `out`
+ * (shgo_plan_output_size doubles; every element is written). Allocates nothing. */
+shgo_status shgo_execute(shgo_plan* plan, double* out, void* stream);
+
+/* Per-kernel timing. With n_slots > 0, every later shgo_execute records a pair of HIP events
+ * around each class kernel (class id = la(la+1)/2 + lb for la >= lb), cycling through n_slots
+ * sets of events; n_slots = 0 turns recording off. */
+shgo_status shgo_plan_set_timing(shgo_plan* plan, int32_t n_slots);
+
+/* After the caller has synchronised the stream: for each of the SHGO_NUM_CLASSES classes, the
+ * summed kernel milliseconds over the recorded executions still held in the slots (ms[c]) and
+ * the number of those executions (count, the same for every class). */
+shgo_status shgo_plan_class_ms(shgo_plan* plan, double* ms, int32_t* count);
+
+/* Boys function F_m(t) = int_0^1 u^{2m} exp(-t u^2) du for m = 0..mmax (the radial factor of
+ * Eq. 12), evaluated by the device routine the integral kernels use.  T: device array of n
+ * values t >= 0; F: device array [n][mmax+1].  mmax <= 13. */
+shgo_status shgo_boys(shgo_context* ctx, int64_t n, const double* T, int32_t mmax, double* F, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHGO_H */

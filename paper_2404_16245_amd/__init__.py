@@ -1,0 +1,294 @@
+"""MI355X (gfx950) nuclear-attraction integrals over contracted solid-harmonic Gaussian orbitals.
+
+Thin ctypes binding of the C ABI in ``include/shgo.h`` (``libshgo.so`` next to this file,
+built by ``build.py``). Functions named ``shgo_*`` marshal arguments to the C entry points of
+the same name; PyTorch only supplies device memory and the current HIP stream. There is no CPU
+fallback: importing the binding on a machine without the built library raises, and every call
+that reaches the device needs a GPU.
+
+Method: arXiv:2404.16245 (Gaussian product Eq. 5, shift to the product center Eqs. 7-8,
+product rule of solid harmonics supplement Eq. 4, one-center integral Eqs. 11-12).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshgo.so")
+
+SHGO_OK = 0
+SHGO_ERR_INVALID_ARG = 1
+SHGO_ERR_UNSUPPORTED_L = 2
+SHGO_ERR_NOT_FINITE = 3
+SHGO_ERR_OUT_OF_MEMORY = 4
+SHGO_ERR_DEVICE = 5
+SHGO_ERR_INTERNAL = 6
+SHGO_LMAX = 6
+
+EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
+            "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
+            "shgo_plan_integrals", "shgo_execute", "shgo_boys", "shgo_plan_set_timing", "shgo_plan_class_ms"]
+SHGO_NUM_CLASSES = 28
+
+
+class ShgoError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class _Basis(ctypes.Structure):
+    _fields_ = [("n_shells", ctypes.c_int32), ("center", ctypes.c_void_p), ("l", ctypes.c_void_p),
+                ("n_prim", ctypes.c_void_p), ("prim_offset", ctypes.c_void_p), ("exponent", ctypes.c_void_p),
+                ("coef", ctypes.c_void_p)]
+
+
+class _Nuclei(ctypes.Structure):
+    _fields_ = [("n_nuclei", ctypes.c_int32), ("position", ctypes.c_void_p), ("charge", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libshgo.so (torch is imported first so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2404_16245_amd/build.py (no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.shgo_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.shgo_create.restype = ctypes.c_int
+    lib.shgo_destroy.argtypes = [vp]
+    lib.shgo_destroy.restype = None
+    lib.shgo_status_string.argtypes = [ctypes.c_int]
+    lib.shgo_status_string.restype = ctypes.c_char_p
+    lib.shgo_last_error.argtypes = [vp]
+    lib.shgo_last_error.restype = ctypes.c_char_p
+    lib.shgo_nbf.argtypes = [ctypes.POINTER(_Basis)]
+    lib.shgo_nbf.restype = i64
+    lib.shgo_validate.argtypes = [ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei), dbl, ctypes.c_char_p, ctypes.c_size_t]
+    lib.shgo_validate.restype = ctypes.c_int
+    lib.shgo_plan_matrix.argtypes = [vp, ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei), dbl, ctypes.POINTER(vp)]
+    lib.shgo_plan_matrix.restype = ctypes.c_int
+    lib.shgo_plan_pairs.argtypes = [vp, ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei), i64, vp, vp, dbl,
+                                    ctypes.POINTER(vp)]
+    lib.shgo_plan_pairs.restype = ctypes.c_int
+    lib.shgo_plan_destroy.argtypes = [vp]
+    lib.shgo_plan_destroy.restype = None
+    lib.shgo_plan_output_size.argtypes = [vp]
+    lib.shgo_plan_output_size.restype = i64
+    lib.shgo_plan_integrals.argtypes = [vp]
+    lib.shgo_plan_integrals.restype = i64
+    lib.shgo_execute.argtypes = [vp, vp, vp]
+    lib.shgo_execute.restype = ctypes.c_int
+    lib.shgo_boys.argtypes = [vp, i64, vp, i32, vp, vp]
+    lib.shgo_boys.restype = ctypes.c_int
+    lib.shgo_plan_set_timing.argtypes = [vp, i32]
+    lib.shgo_plan_set_timing.restype = ctypes.c_int
+    lib.shgo_plan_class_ms.argtypes = [vp, vp, vp]
+    lib.shgo_plan_class_ms.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+# ----------------------------------------------------------------------------------------------
+# argument marshalling
+# ----------------------------------------------------------------------------------------------
+class _HostBasis:
+    """Keeps contiguous host copies alive while the C call reads them."""
+
+    def __init__(self, basis):
+        self.center = np.ascontiguousarray(basis.center, dtype=np.float64).reshape(-1, 3)
+        self.l = np.ascontiguousarray(basis.l, dtype=np.int32)
+        self.nprim = np.ascontiguousarray(basis.nprim, dtype=np.int32)
+        self.prim_off = np.ascontiguousarray(basis.prim_off, dtype=np.int64)
+        self.expo = np.ascontiguousarray(basis.expo, dtype=np.float64)
+        self.coef = np.ascontiguousarray(basis.coef, dtype=np.float64)
+        self.struct = _Basis(int(self.l.shape[0]), self.center.ctypes.data, self.l.ctypes.data,
+                             self.nprim.ctypes.data, self.prim_off.ctypes.data, self.expo.ctypes.data,
+                             self.coef.ctypes.data)
+
+
+class _HostNuclei:
+    def __init__(self, nuclei):
+        self.pos = np.ascontiguousarray(nuclei.pos, dtype=np.float64).reshape(-1, 3)
+        self.Z = np.ascontiguousarray(nuclei.Z, dtype=np.float64)
+        self.struct = _Nuclei(int(self.Z.shape[0]), self.pos.ctypes.data, self.Z.ctypes.data)
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(lib, ctx, status):
+    if status != SHGO_OK:
+        msg = lib.shgo_last_error(ctx).decode() if ctx else lib.shgo_status_string(status).decode()
+        raise ShgoError(status, msg or lib.shgo_status_string(status).decode())
+
+
+# ----------------------------------------------------------------------------------------------
+# entry points with the C names
+# ----------------------------------------------------------------------------------------------
+def shgo_create(device=0):
+    lib = load_library()
+    h = ctypes.c_void_p()
+    st = lib.shgo_create(int(device), ctypes.byref(h))
+    if st != SHGO_OK:
+        raise ShgoError(st, "shgo_create: " + lib.shgo_status_string(st).decode())
+    return h
+
+
+def shgo_destroy(ctx):
+    load_library().shgo_destroy(ctx)
+
+
+def shgo_status_string(status):
+    return load_library().shgo_status_string(int(status)).decode()
+
+
+def shgo_last_error(ctx):
+    return load_library().shgo_last_error(ctx).decode()
+
+
+def shgo_nbf(basis):
+    hb = _HostBasis(basis)
+    return int(load_library().shgo_nbf(ctypes.byref(hb.struct)))
+
+
+def shgo_validate(basis, nuclei, screen=0.0):
+    """(status, message) of the host-side validation."""
+    hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
+    buf = ctypes.create_string_buffer(256)
+    st = load_library().shgo_validate(ctypes.byref(hb.struct), ctypes.byref(hn.struct), float(screen), buf, 256)
+    return int(st), buf.value.decode()
+
+
+class Plan:
+    """A device-resident plan (owns the C plan handle)."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self.handle = handle
+        lib = load_library()
+        self.output_size = int(lib.shgo_plan_output_size(handle))
+        self.integrals = int(lib.shgo_plan_integrals(handle))
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.shgo_plan_destroy(self.handle)
+            self.handle = None
+
+
+def shgo_plan_matrix(ctx, basis, nuclei, screen=0.0):
+    lib = load_library()
+    hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
+    h = ctypes.c_void_p()
+    _check(lib, ctx, lib.shgo_plan_matrix(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct), float(screen),
+                                          ctypes.byref(h)))
+    return Plan(ctx, h)
+
+
+def shgo_plan_pairs(ctx, basis, nuclei, pair_a, pair_b, screen=0.0):
+    lib = load_library()
+    hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
+    pa = np.ascontiguousarray(pair_a, dtype=np.int32)
+    pb = np.ascontiguousarray(pair_b, dtype=np.int32)
+    if pa.shape != pb.shape:
+        raise ValueError("pair_a and pair_b differ in length")
+    h = ctypes.c_void_p()
+    _check(lib, ctx, lib.shgo_plan_pairs(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct), int(pa.shape[0]),
+                                         pa.ctypes.data, pb.ctypes.data, float(screen), ctypes.byref(h)))
+    return Plan(ctx, h)
+
+
+def shgo_plan_destroy(plan):
+    if plan.handle is not None:
+        load_library().shgo_plan_destroy(plan.handle)
+        plan.handle = None
+
+
+def shgo_plan_output_size(plan):
+    return plan.output_size
+
+
+def shgo_plan_integrals(plan):
+    return plan.integrals
+
+
+def shgo_execute(plan, out, stream=None):
+    """Enqueue the whole evaluation; ``out`` is a float64 CUDA tensor of plan.output_size."""
+    lib = load_library()
+    if out.dtype.__str__() != "torch.float64" or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 device tensor")
+    if out.numel() < plan.output_size:
+        raise ValueError("out is smaller than the plan's output")
+    _check(lib, plan.ctx, lib.shgo_execute(plan.handle, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def shgo_plan_set_timing(plan, n_slots):
+    lib = load_library()
+    _check(lib, plan.ctx, lib.shgo_plan_set_timing(plan.handle, int(n_slots)))
+
+
+def shgo_plan_class_ms(plan):
+    """(ms[SHGO_NUM_CLASSES] summed over the recorded executions, number of executions)."""
+    lib = load_library()
+    ms = np.zeros(SHGO_NUM_CLASSES)
+    cnt = np.zeros(1, dtype=np.int32)
+    _check(lib, plan.ctx, lib.shgo_plan_class_ms(plan.handle, ms.ctypes.data, cnt.ctypes.data))
+    return ms, int(cnt[0])
+
+
+def shgo_boys(ctx, T, mmax, F=None, stream=None):
+    """Device Boys function: T float64 CUDA tensor [n] -> F [n, mmax+1]."""
+    import torch
+    lib = load_library()
+    T = T.contiguous()
+    if F is None:
+        F = torch.empty((T.numel(), mmax + 1), dtype=torch.float64, device=T.device)
+    _check(lib, ctx, lib.shgo_boys(ctx, int(T.numel()), ctypes.c_void_p(T.data_ptr()), int(mmax),
+                                   ctypes.c_void_p(F.data_ptr()), _stream_handle(stream)))
+    return F
+
+
+# ----------------------------------------------------------------------------------------------
+# convenience (still only marshalling)
+# ----------------------------------------------------------------------------------------------
+_ctx = {}
+
+
+def context(device=0):
+    if device not in _ctx:
+        _ctx[device] = shgo_create(device)
+    return _ctx[device]
+
+
+def nuclear_attraction(basis, nuclei, screen=0.0, device=0):
+    """Full nbf x nbf nuclear-attraction matrix as a float64 CUDA tensor."""
+    import torch
+    ctx = context(device)
+    plan = shgo_plan_matrix(ctx, basis, nuclei, screen)
+    nbf = shgo_nbf(basis)
+    out = torch.empty((nbf, nbf), dtype=torch.float64, device=f"cuda:{device}")
+    shgo_execute(plan, out)
+    torch.cuda.current_stream().synchronize()
+    return out
+
+
+def nuclear_attraction_pairs(basis, nuclei, pair_a, pair_b, screen=0.0, device=0):
+    """Blocks of the listed shell pairs, back to back, as a flat float64 CUDA tensor."""
+    import torch
+    ctx = context(device)
+    plan = shgo_plan_pairs(ctx, basis, nuclei, pair_a, pair_b, screen)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device=f"cuda:{device}")
+    shgo_execute(plan, out)
+    torch.cuda.current_stream().synchronize()
+    return out

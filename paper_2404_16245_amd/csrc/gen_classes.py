@@ -1,0 +1,492 @@
+"""Generator of the class-specific device code of the nuclear-attraction kernel.
+
+For every class (LA, LB) with LA >= LB it emits straight-line HIP code for
+
+* the nucleus step: real solid harmonics S^L_M(C) of the nucleus position relative to the
+  Gaussian-product center P, in the frame whose z axis is the A->B axis (Eq. 2 normalisation,
+  built with the standard sectoral and vertical recurrences), times
+  G_{L,k}(T) = sum_{j<=k} T^j/j! Z F_{L+j}(T), accumulated into W(L, M, k) (the one-center
+  Coulomb integral of Eq. 11's last line, completed with the product rule; Eq. 12 is the k = 0
+  case);
+* the coupling: the product rule of real solid harmonics (the supplement's Eq. 4 in the real
+  basis) and the shift of both harmonics to P (Eq. 7, Eq. 8's coefficients). Along the A->B axis
+  the shift keeps m, so the block is
+    V'(ma, mb) = sum_{l1, l2} c(LA, l1, |ma|) t_a^{LA-l1} c(LB, l2, |mb|) t_b^{LB-l2}
+                 sum_{L, M} g(l1 ma, l2 mb; L M) W_s(L, M, (l1 + l2 - L)/2)
+  with t_a = beta R/p, t_b = -alpha R/p and c(l, l1, m) = sqrt(C(l+m, l1+m) C(l-m, l1-m));
+* the rotation back to the laboratory frame, D^l(Q)^T = Z(phi) J^T Z(theta) J with the constant
+  matrix J = D^l(rotation by +pi/2 about x) and z rotations Z.
+
+The W entries of one class are split by |M| ("families") into groups that each fit a register
+budget; one wavefront of the kernel runs one group for 64 shell pairs.
+
+The tables (real Gaunt coefficients g, the J matrices) are computed here by exact quadrature on
+the unit sphere of polynomials evaluated with the same recurrences the kernel uses. The module
+also offers ``emulate_block``, a numpy execution of exactly the emitted term lists, used by the
+CPU tests to check the tables and the layout before any GPU run.
+
+Usage: python gen_classes.py OUTPUT_HEADER [--cap N]
+"""
+import math
+import os
+import sys
+
+import numpy as np
+
+LMAX_SHELL = 6
+DEFAULT_CAP = 64          # register budget of one group, in doubles of W
+KEEP = 1e-14              # drop real Gaunt coefficients below this magnitude
+
+
+# ----------------------------------------------------------------------------------------------
+# Real solid harmonics by recurrence (Racah normalisation, order m = -l..l, index l*l + m + l)
+# ----------------------------------------------------------------------------------------------
+def sect_coef(l):
+    """S^{l+1}_{+-(l+1)} = f_l (x S^l_l -+ y S^l_{-l}) ... with f_0 = 1."""
+    return 1.0 if l == 0 else math.sqrt((2 * l + 1) / (2 * l + 2))
+
+
+def vert_coefs(l, m):
+    """S^{l+1}_m = a z S^l_m - b r^2 S^{l-1}_m (|m| <= l)."""
+    m = abs(m)
+    den = math.sqrt((l + m + 1) * (l - m + 1))
+    return (2 * l + 1) / den, math.sqrt((l + m) * (l - m)) / den
+
+
+def solid_real(lmax, pts):
+    """Real solid harmonics at points pts (N, 3) -> (N, (lmax+1)^2), in the dtype of pts
+    (recurrence coefficients are evaluated in that dtype, so long double inputs give long
+    double accuracy)."""
+    pts = np.atleast_2d(pts)
+    dt = pts.dtype
+    x, y, z = pts[:, 0], pts[:, 1], pts[:, 2]
+    r2 = x * x + y * y + z * z
+    S = np.zeros((pts.shape[0], (lmax + 1) ** 2), dtype=dt)
+    idx = lambda l, m: l * l + m + l
+    S[:, 0] = 1.0
+    sc, ss = np.ones_like(x), np.zeros_like(x)
+    for l in range(lmax):
+        f = dt.type(1) if l == 0 else np.sqrt(dt.type(2 * l + 1) / dt.type(2 * l + 2))
+        sc, ss = f * (x * sc - y * ss), f * (y * sc + x * ss)
+        S[:, idx(l + 1, l + 1)] = sc
+        S[:, idx(l + 1, -(l + 1))] = ss
+    for m in range(0, lmax + 1):
+        for sgn in ([1] if m == 0 else [1, -1]):
+            mm = sgn * m
+            prev = np.zeros_like(x)
+            cur = S[:, idx(m, mm)].copy()
+            for l in range(m, lmax):
+                den = np.sqrt(dt.type((l + m + 1) * (l - m + 1)))
+                a = dt.type(2 * l + 1) / den
+                b = np.sqrt(dt.type((l + m) * (l - m))) / den
+                nxt = a * z * cur - b * r2 * prev
+                S[:, idx(l + 1, mm)] = nxt
+                prev, cur = cur, nxt
+    return S
+
+
+def _gauss_legendre_ld(n):
+    """Gauss-Legendre nodes and weights in long double (Newton refinement of numpy's)."""
+    x0, _ = np.polynomial.legendre.leggauss(n)
+    x = x0.astype(np.longdouble)
+    for _ in range(4):
+        p0, p1 = np.ones_like(x), x.copy()
+        for k in range(2, n + 1):
+            p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+        dp = n * (x * p1 - p0) / (x * x - 1)
+        x = x - p1 / dp
+    p0, p1 = np.ones_like(x), x.copy()
+    for k in range(2, n + 1):
+        p0, p1 = p1, ((2 * k - 1) * x * p1 - (k - 1) * p0) / k
+    dp = n * (x * p1 - p0) / (x * x - 1)
+    w = 2 / ((1 - x * x) * dp * dp)
+    return x, w
+
+
+def sphere_grid(order):
+    """Quadrature exact for polynomials of degree <= order on the unit sphere (long double)."""
+    ngl = order // 2 + 2
+    nphi = order + 2
+    zg, wg = _gauss_legendre_ld(ngl)
+    phi = np.longdouble(2) * np.arccos(np.longdouble(-1)) * np.arange(nphi, dtype=np.longdouble) / nphi
+    Z, PHI = np.meshgrid(zg, phi, indexing="ij")
+    W = np.outer(wg, np.full(nphi, np.longdouble(2) * np.arccos(np.longdouble(-1)) / nphi))
+    s = np.sqrt(1 - Z * Z)
+    pts = np.stack([s * np.cos(PHI), s * np.sin(PHI), Z], axis=-1).reshape(-1, 3)
+    return pts, W.reshape(-1)
+
+
+_GAUNT = None
+
+
+def real_gaunt_table():
+    """g[i1, i2, I] with S^{l1}_{m1} S^{l2}_{m2} = sum_{L,M} g r^{l1+l2-L} S^L_M, l1, l2 <= 6."""
+    global _GAUNT
+    if _GAUNT is None:
+        lm, Lm = LMAX_SHELL, 2 * LMAX_SHELL
+        pts, w = sphere_grid(lm + lm + Lm + 2)
+        S = solid_real(Lm, pts)
+        n = (lm + 1) ** 2
+        four_pi = 4 * np.arccos(np.longdouble(-1))
+        norm = np.array([np.longdouble(2 * L + 1) / four_pi for L in range(Lm + 1) for _ in range(2 * L + 1)])
+        wa = w[:, None] * S[:, :n]
+        g = np.einsum("pa,pb,pc->abc", wa, S[:, :n], S) * norm[None, None, :]
+        g = g.astype(np.float64)
+        g[np.abs(g) < KEEP] = 0.0
+        _GAUNT = g
+    return _GAUNT
+
+
+def rot_x90(l):
+    """J = D^l(R) for R = rotation by +pi/2 about x: S^l(R v) = J S^l(v)."""
+    pts, w = sphere_grid(2 * l + 2)
+    R = np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]], dtype=np.longdouble)
+    a = solid_real(l, pts @ R.T)[:, l * l:]
+    b = solid_real(l, pts)[:, l * l:]
+    J = np.longdouble(2 * l + 1) / (4 * np.arccos(np.longdouble(-1))) * np.einsum("p,pi,pj->ij", w, a, b)
+    J = J.astype(np.float64)
+    J[np.abs(J) < 1e-14] = 0.0
+    return J
+
+
+def trans_coef(l, l1, m):
+    """c(l, l1, m) = eps_{l l1 m m} (Eq. 8): shift of S^l_m along z keeps m."""
+    m = abs(m)
+    return math.sqrt(math.comb(l + m, l1 + m) * math.comb(l - m, l1 - m))
+
+
+# ----------------------------------------------------------------------------------------------
+# Class layout: families, groups, W index map
+# ----------------------------------------------------------------------------------------------
+def kmax_of(LA, LB, L):
+    return min(LB, (LA + LB - L) // 2)
+
+
+def family_entries(LA, LB, mu):
+    """Ordered W entries (L, M, k) of family |M| = mu: L ascending, k ascending, cos then sin."""
+    out = []
+    for L in range(mu, LA + LB + 1):
+        for k in range(kmax_of(LA, LB, L) + 1):
+            out.append((L, mu, k))
+            if mu > 0:
+                out.append((L, -mu, k))
+    return out
+
+
+def class_groups(LA, LB, cap=DEFAULT_CAP):
+    """Partition families 0..LA+LB into groups with at most max(cap, largest family) entries."""
+    fams = list(range(LA + LB + 1))
+    size = {mu: len(family_entries(LA, LB, mu)) for mu in fams}
+    c = max(cap, max(size.values()))
+    groups = []
+    for mu in sorted(fams, key=lambda f: (-size[f], f)):
+        best = None
+        for gi, g in enumerate(groups):
+            load = sum(size[f] for f in g)
+            if load + size[mu] <= c and (best is None or load < sum(size[f] for f in groups[best])):
+                best = gi
+        if best is None:
+            groups.append([mu])
+        else:
+            groups[best].append(mu)
+    groups = [sorted(g) for g in groups]
+    groups.sort(key=lambda g: -sum(size[f] for f in g))
+    return groups
+
+
+def group_index(LA, LB, group):
+    """{(L, M, k): position in the group's W array}."""
+    idx = {}
+    for mu in group:
+        for e in family_entries(LA, LB, mu):
+            idx[e] = len(idx)
+    return idx
+
+
+def class_terms(LA, LB):
+    """Coupling terms (ma, mb, l1, l2, L, M, k, coef) with coef = c_a c_b g."""
+    g = real_gaunt_table()
+    terms = []
+    for ma in range(-LA, LA + 1):
+        for mb in range(-LB, LB + 1):
+            for l1 in range(abs(ma), LA + 1):
+                ca = trans_coef(LA, l1, ma)
+                for l2 in range(abs(mb), LB + 1):
+                    cb = trans_coef(LB, l2, mb)
+                    i1, i2 = l1 * l1 + ma + l1, l2 * l2 + mb + l2
+                    for L in range(abs(l1 - l2), l1 + l2 + 1, 2):
+                        for M in range(-L, L + 1):
+                            v = g[i1, i2, L * L + M + L]
+                            if v != 0.0:
+                                terms.append((ma, mb, l1, l2, L, M, (l1 + l2 - L) // 2, ca * cb * v))
+    return terms
+
+
+# ----------------------------------------------------------------------------------------------
+# numpy execution of the emitted algorithm (used by the CPU tests)
+# ----------------------------------------------------------------------------------------------
+def boys_np(mmax, T):
+    """Boys function by mpmath (test helper for the emulation only)."""
+    import mpmath
+    mpmath.mp.dps = 30
+    out = np.zeros(mmax + 1)
+    for m in range(mmax + 1):
+        if T == 0:
+            out[m] = 1.0 / (2 * m + 1)
+        else:
+            a = mpmath.mpf(m) + 0.5
+            out[m] = float(mpmath.gammainc(a, 0, T) / (2 * mpmath.mpf(T) ** a))
+    return out
+
+
+def frame(R):
+    """(cos theta, sin theta, cos phi, sin phi) of the A->B axis, identity frame for R = 0."""
+    Rl = float(np.linalg.norm(R))
+    rho = float(math.hypot(R[0], R[1]))
+    if Rl == 0.0:
+        return 1.0, 0.0, 1.0, 0.0, 0.0
+    ct, st = R[2] / Rl, rho / Rl
+    cp, sp = (R[0] / rho, R[1] / rho) if rho > 0 else (1.0, 0.0)
+    return ct, st, cp, sp, Rl
+
+
+def rotate_into_frame(v, ct, st, cp, sp):
+    u = cp * v[0] + sp * v[1]
+    return np.array([ct * u - st * v[2], -sp * v[0] + cp * v[1], st * u + ct * v[2]])
+
+
+def zrot(l, c, s):
+    """Z(angle) for S^l given cos/sin of m*angle arrays c[m], s[m]."""
+    Zm = np.zeros((2 * l + 1, 2 * l + 1))
+    Zm[l, l] = 1.0
+    for m in range(1, l + 1):
+        Zm[l + m, l + m] = c[m]
+        Zm[l + m, l - m] = -s[m]
+        Zm[l - m, l + m] = s[m]
+        Zm[l - m, l - m] = c[m]
+    return Zm
+
+
+def emulate_block(LA, LB, A, B, ea, wa, eb, wb, nuc_pos, nuc_Z, cap=DEFAULT_CAP, boys=boys_np):
+    """The V block (2LA+1) x (2LB+1) of shells (LA at A) x (LB at B), computed by the emitted
+    algorithm in numpy. ``wa``/``wb`` are the final primitive weights (contraction x norm)."""
+    A, B = np.asarray(A, float), np.asarray(B, float)
+    ct, st, cp, sp, Rl = frame(B - A)
+    th, ph = math.atan2(st, ct), math.atan2(sp, cp)
+    groups = class_groups(LA, LB, cap)
+    terms = class_terms(LA, LB)
+    NA, NB = 2 * LA + 1, 2 * LB + 1
+    Vp = np.zeros((NA, NB))
+    LM = LA + LB
+    for a_, wa_ in zip(ea, wa):
+        for b_, wb_ in zip(eb, wb):
+            p = a_ + b_
+            P = (a_ * A + b_ * B) / p
+            K = math.exp(-a_ * b_ / p * Rl * Rl)
+            ta, tb = b_ * Rl / p, -a_ * Rl / p
+            W = {}
+            for c, Z in zip(nuc_pos, nuc_Z):
+                C = rotate_into_frame(np.asarray(c) - P, ct, st, cp, sp)
+                T = p * float(C @ C)
+                F = boys(LM, T) * Z
+                S = solid_real(LM, C[None])[0]
+                for L in range(LM + 1):
+                    for k in range(kmax_of(LA, LB, L) + 1):
+                        G = sum(T ** j / math.factorial(j) * F[L + j] for j in range(k + 1))
+                        for M in range(-L, L + 1):
+                            W[(L, M, k)] = W.get((L, M, k), 0.0) + G * S[L * L + M + L]
+            pre = -wa_ * wb_ * K
+            for (ma, mb, l1, l2, L, M, k, coef) in terms:
+                fk = pre * 2 * math.pi * math.factorial(k) / p ** (k + 1)
+                Vp[ma + LA, mb + LB] += coef * ta ** (LA - l1) * tb ** (LB - l2) * fk * W.get((L, M, k), 0.0)
+    # the group partition must cover every coupled W entry exactly once
+    seen = {}
+    for g in groups:
+        for e in group_index(LA, LB, g):
+            assert e not in seen
+            seen[e] = 1
+    for t in terms:
+        assert (t[4], t[5], t[6]) in seen
+    # rotate back: V = Da^T V' Db, D^T = Z(phi) J^T Z(theta) J
+    def dT(l):
+        cth = [math.cos(m * th) for m in range(l + 1)]
+        sth = [math.sin(m * th) for m in range(l + 1)]
+        cph = [math.cos(m * ph) for m in range(l + 1)]
+        sph = [math.sin(m * ph) for m in range(l + 1)]
+        J = rot_x90(l)
+        return zrot(l, cph, sph) @ J.T @ zrot(l, cth, sth) @ J
+    Dat, Dbt = dT(LA), dT(LB)
+    return Dat @ Vp @ Dbt.T
+
+
+# ----------------------------------------------------------------------------------------------
+# Emission
+# ----------------------------------------------------------------------------------------------
+def lit(v):
+    return repr(float(v))
+
+
+def emit_group(LA, LB, gi, group):
+    LM = LA + LB
+    idx = group_index(LA, LB, group)
+    NW = len(idx)
+    mu_max = max(group)
+    name = f"G{LA}{LB}_{gi}"
+    o = []
+    o.append(f"struct {name} {{")
+    o.append(f"  static constexpr int NW = {NW};")
+    # ---- nucleus step ----
+    o.append("  static __device__ __forceinline__ void step(double (&W)[NW], double x, double y, double z, double r2,")
+    o.append(f"                                               const double (&ZF)[{LM + 1}], const double (&tj)[{LB + 1}]) {{")
+    o.append("    double sc = 1.0, ss = 0.0;")
+    fams = sorted(group)
+    cur_sect = 0
+    for mu in fams:
+        while cur_sect < mu:
+            f = sect_coef(cur_sect)
+            if cur_sect == 0:
+                o.append("    sc = x; ss = y;")
+            else:
+                o.append(f"    {{ const double nc = {lit(f)} * (x * sc - y * ss); ss = {lit(f)} * (y * sc + x * ss); sc = nc; }}")
+            cur_sect += 1
+        o.append(f"    {{ // family |M| = {mu}")
+        o.append("      double cc = sc, cs = ss, pc = 0.0, ps = 0.0;")
+        for L in range(mu, LM + 1):
+            if L > mu:
+                a, b = vert_coefs(L - 1, mu)
+                if mu == L - 1:
+                    o.append(f"      {{ const double nc = {lit(a)} * z * cc; pc = cc; cc = nc; }}")
+                    if mu > 0:
+                        o.append(f"      {{ const double ns = {lit(a)} * z * cs; ps = cs; cs = ns; }}")
+                else:
+                    o.append(f"      {{ const double nc = {lit(a)} * z * cc - {lit(b)} * r2 * pc; pc = cc; cc = nc; }}")
+                    if mu > 0:
+                        o.append(f"      {{ const double ns = {lit(a)} * z * cs - {lit(b)} * r2 * ps; ps = cs; cs = ns; }}")
+            km = kmax_of(LA, LB, L)
+            o.append(f"      {{ double g = ZF[{L}];")
+            for k in range(km + 1):
+                if k > 0:
+                    o.append(f"        g = fma(tj[{k}], ZF[{L + k}], g);")
+                o.append(f"        W[{idx[(L, mu, k)]}] = fma(g, cc, W[{idx[(L, mu, k)]}]);")
+                if mu > 0:
+                    o.append(f"        W[{idx[(L, -mu, k)]}] = fma(g, cs, W[{idx[(L, -mu, k)]}]);")
+            o.append("      }")
+        o.append("    }")
+    o.append("  }")
+    # ---- scaling by pre * 2 pi k!/p^{k+1} ----
+    o.append(f"  static __device__ __forceinline__ void scale(double (&W)[NW], const double (&fk)[{LB + 1}]) {{")
+    for (L, M, k), i in idx.items():
+        o.append(f"    W[{i}] *= fk[{k}];")
+    o.append("  }")
+    # ---- coupling ----
+    terms = [t for t in class_terms(LA, LB) if abs(t[5]) in group]
+    by_mm = {}
+    for t in terms:
+        by_mm.setdefault((t[0], t[1]), []).append(t)
+    NB = 2 * LB + 1
+    o.append(f"  static __device__ __forceinline__ void couple(const double (&W)[NW], const double (&ta)[{LA + 1}],")
+    o.append(f"                                                 const double (&tb)[{LB + 1}], double* __restrict__ Vp) {{")
+    for (ma, mb), ts in sorted(by_mm.items()):
+        o.append(f"    {{ // (ma, mb) = ({ma}, {mb})")
+        o.append("      double v = 0.0;")
+        by_l1 = {}
+        for t in ts:
+            by_l1.setdefault(t[2], {}).setdefault(t[3], []).append(t)
+        for l1, d2 in sorted(by_l1.items()):
+            o.append("      { double u = 0.0;")
+            for l2, tl in sorted(d2.items()):
+                expr = None
+                for t in tl:
+                    wi = idx[(t[4], t[5], t[6])]
+                    expr = f"{lit(t[7])} * W[{wi}]" if expr is None else f"fma({lit(t[7])}, W[{wi}], {expr})"
+                if LB - l2 == 0:
+                    o.append(f"        u += {expr};")
+                else:
+                    o.append(f"        u = fma(tb[{LB - l2}], {expr}, u);")
+            if LA - l1 == 0:
+                o.append("        v += u; }")
+            else:
+                o.append(f"        v = fma(ta[{LA - l1}], u, v); }}")
+        o.append(f"      atomicAdd(Vp + {(ma + LA) * NB + (mb + LB)}, v);")
+        o.append("    }")
+    o.append("  }")
+    o.append("};")
+    return "\n".join(o)
+
+
+def emit_rotation(l):
+    """v <- Z(phi) J^T Z(theta) J v for a vector of length 2l+1."""
+    J = rot_x90(l)
+    n = 2 * l + 1
+    o = [f"template <> struct Rot<{l}> {{",
+         f"  static __device__ __forceinline__ void apply(double (&v)[{n}], const double* __restrict__ cth, "
+         "const double* __restrict__ sth,",
+         "                                              const double* __restrict__ cph, const double* __restrict__ sph) {"]
+    def matvec(M, src, dst):
+        for i in range(n):
+            terms = [(M[i, j], j) for j in range(n) if M[i, j] != 0.0]
+            if not terms:
+                o.append(f"    const double {dst}{i} = 0.0;")
+                continue
+            e = f"{lit(terms[0][0])} * {src}[{terms[0][1]}]"
+            for c, j in terms[1:]:
+                e = f"fma({lit(c)}, {src}[{j}], {e})"
+            o.append(f"    const double {dst}{i} = {e};")
+    o.append(f"    double w[{n}];")
+    matvec(J, "v", "a")
+    for i in range(n):
+        o.append(f"    w[{i}] = a{i};")
+    # Z(theta)
+    for m in range(1, l + 1):
+        o.append(f"    {{ const double c = w[{l + m}], s = w[{l - m}];")
+        o.append(f"      w[{l + m}] = cth[{m}] * c - sth[{m}] * s; w[{l - m}] = sth[{m}] * c + cth[{m}] * s; }}")
+    matvec(J.T, "w", "b")
+    for i in range(n):
+        o.append(f"    v[{i}] = b{i};")
+    for m in range(1, l + 1):
+        o.append(f"    {{ const double c = v[{l + m}], s = v[{l - m}];")
+        o.append(f"      v[{l + m}] = cph[{m}] * c - sph[{m}] * s; v[{l - m}] = sph[{m}] * c + cph[{m}] * s; }}")
+    o.append("  }")
+    o.append("};")
+    return "\n".join(o)
+
+
+def emit_header(cap=DEFAULT_CAP, lmax=LMAX_SHELL):
+    out = ["// Generated by gen_classes.py -- do not edit. Class-specific code of the nuclear-attraction",
+           "// kernel: nucleus step, coupling (product rule + shift along the A->B axis) and rotations.",
+           f"// Group register budget: {cap} doubles.",
+           "#pragma once",
+           "",
+           "template <int L> struct Rot;"]
+    for l in range(lmax + 1):
+        out.append(emit_rotation(l))
+    out.append("template <int LA, int LB> struct ClassInfo;")
+    out.append("template <int LA, int LB, int G> struct GroupOf;")
+    for LA in range(lmax + 1):
+        for LB in range(LA + 1):
+            groups = class_groups(LA, LB, cap)
+            for gi, g in enumerate(groups):
+                out.append(emit_group(LA, LB, gi, g))
+            out.append(f"template <> struct ClassInfo<{LA}, {LB}> {{ static constexpr int Q = {len(groups)}; }};")
+            for gi, g in enumerate(groups):
+                out.append(f"template <> struct GroupOf<{LA}, {LB}, {gi}> : G{LA}{LB}_{gi} {{}};")
+    return "\n".join(out) + "\n"
+
+
+def main(argv):
+    out = argv[1] if len(argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)), "generated",
+                                                     "shgo_classes.inc")
+    cap = DEFAULT_CAP
+    if "--cap" in argv:
+        cap = int(argv[argv.index("--cap") + 1])
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    text = emit_header(cap)
+    tmp = out + ".tmp"
+    with open(tmp, "w") as f:
+        f.write(text)
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    print(main(sys.argv))

@@ -1,0 +1,146 @@
+"""CPU checks of the GPU path's generated tables and algorithm (no GPU needed).
+
+The class code emitted by ``csrc/gen_classes.py`` rests on: real solid harmonics by recurrence,
+the real Gaunt table (product rule), the shift coefficients along the A->B axis (Eq. 8 with
+mu = m), the constant rotation J and the z rotations. Each is checked here against facts
+outside the generator, and ``emulate_block`` (a numpy run of exactly the emitted term lists)
+is compared with the oracle for every class.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import xcheck
+from paper_2404_16245_amd import synth
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                "paper_2404_16245_amd", "csrc"))
+import gen_classes as gc  # noqa: E402
+
+
+def test_recurrence_harmonics_against_scipy_fit():
+    pts = np.random.default_rng(0).normal(size=(6, 3))
+    S = gc.solid_real(12, pts)
+    for l in range(13):
+        ref = np.array([xcheck.eval_real_solid(l, *p) for p in pts])
+        assert np.allclose(S[:, l * l:(l + 1) ** 2], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+def test_gaunt_table_reproduces_products():
+    g = gc.real_gaunt_table()
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        v = rng.normal(size=3)
+        r2 = float(v @ v)
+        S = gc.solid_real(12, v[None])[0]
+        for l1 in range(7):
+            for l2 in range(7):
+                for m1 in range(-l1, l1 + 1):
+                    for m2 in range(-l2, l2 + 1):
+                        i1, i2 = l1 * l1 + m1 + l1, l2 * l2 + m2 + l2
+                        s = 0.0
+                        for L in range(abs(l1 - l2), l1 + l2 + 1, 2):
+                            k = (l1 + l2 - L) // 2
+                            s += r2 ** k * float(g[i1, i2, L * L:(L + 1) ** 2] @ S[L * L:(L + 1) ** 2])
+                        ref = S[i1] * S[i2]
+                        assert abs(s - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_gaunt_table_against_clebsch_gordan():
+    # real Gaunt = U_l1 (x) U_l2 (x) conj(U_L) applied to <l1 0 l2 0|L0><l1 m1 l2 m2|LM> (oracle's CG)
+    def U(l):
+        d = 2 * l + 1
+        M = np.zeros((d, d), complex)
+        h = 1 / math.sqrt(2)
+        M[l, l] = 1
+        for m in range(1, l + 1):
+            M[m + l, m + l] = (-1) ** m * h
+            M[m + l, -m + l] = h
+            M[-m + l, -m + l] = 1j * h
+            M[-m + l, m + l] = -1j * (-1) ** m * h
+        return M
+    g = gc.real_gaunt_table()
+    for (l1, l2) in [(2, 3), (6, 6), (4, 1), (5, 5)]:
+        for L in range(abs(l1 - l2), l1 + l2 + 1, 2):
+            Gc = np.zeros((2 * l1 + 1, 2 * l2 + 1, 2 * L + 1))
+            c0 = oracle.cg(l1, 0, l2, 0, L, 0)
+            for u1 in range(-l1, l1 + 1):
+                for u2 in range(-l2, l2 + 1):
+                    if abs(u1 + u2) <= L:
+                        Gc[u1 + l1, u2 + l2, u1 + u2 + L] = c0 * oracle.cg(l1, u1, l2, u2, L, u1 + u2)
+            R = np.einsum("ai,bj,ck,ijk->abc", U(l1), U(l2), U(L).conj(), Gc)
+            ours = g[l1 * l1:(l1 + 1) ** 2, l2 * l2:(l2 + 1) ** 2, L * L:(L + 1) ** 2]
+            assert np.abs(ours - R.real).max() < 2e-15
+
+
+@pytest.mark.parametrize("l", range(7))
+def test_rotation_tables(l):
+    J = gc.rot_x90(l)
+    assert np.allclose(J @ J.T, np.eye(2 * l + 1), atol=1e-15)
+    R = np.array([[1.0, 0, 0], [0, 0, -1.0], [0, 1.0, 0]])
+    rng = np.random.default_rng(2 + l)
+    th = 0.7
+    cz = [math.cos(m * th) for m in range(l + 1)]
+    sz = [math.sin(m * th) for m in range(l + 1)]
+    Rz = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1.0]])
+    for _ in range(3):
+        v = rng.normal(size=3)
+        S = gc.solid_real(l, v[None])[0, l * l:]
+        assert np.allclose(gc.solid_real(l, (R @ v)[None])[0, l * l:], J @ S, atol=1e-12)
+        assert np.allclose(gc.solid_real(l, (Rz @ v)[None])[0, l * l:], gc.zrot(l, cz, sz) @ S, atol=1e-12)
+
+
+def test_shift_along_z_keeps_m():
+    rng = np.random.default_rng(3)
+    v, t = rng.normal(size=3), 0.83
+    S = gc.solid_real(6, v[None])[0]
+    St = gc.solid_real(6, (v + [0, 0, t])[None])[0]
+    for l in range(7):
+        for m in range(-l, l + 1):
+            s = sum(gc.trans_coef(l, l1, m) * t ** (l - l1) * S[l1 * l1 + m + l1] for l1 in range(abs(m), l + 1))
+            assert s == pytest.approx(St[l * l + m + l], rel=1e-12, abs=1e-12)
+
+
+def test_groups_partition_families():
+    for LA in range(7):
+        for LB in range(LA + 1):
+            groups = gc.class_groups(LA, LB)
+            fams = sorted(f for g in groups for f in g)
+            assert fams == list(range(LA + LB + 1))
+            cap = max(gc.DEFAULT_CAP, max(len(gc.family_entries(LA, LB, f)) for f in fams))
+            assert all(sum(len(gc.family_entries(LA, LB, f)) for f in g) <= cap for g in groups)
+
+
+CLASSES = [(la, lb) for la in range(7) for lb in range(la + 1)]
+
+
+@pytest.mark.parametrize("la,lb", CLASSES)
+def test_emulated_algorithm_against_oracle(la, lb):
+    rng = np.random.default_rng(500 + 10 * la + lb)
+    A, B = rng.uniform(0, 3, 3), rng.uniform(0, 3, 3)
+    ea, eb = rng.uniform(0.3, 4, 2), rng.uniform(0.3, 4, 1)
+    da, db = rng.uniform(0.1, 1, 2), np.ones(1)
+    bs = synth.Basis(np.array([A, B]), np.array([la, lb], np.int32), np.array([2, 1], np.int32),
+                     np.array([0, 2], np.int64), np.concatenate([ea, eb]), np.concatenate([da, db]))
+    nuc = synth.Nuclei(rng.uniform(0, 3, (2, 3)), np.array([2.0, 5.0]))
+    ref = oracle.nuc_blocks(bs, nuc, [0], [1], precision=2).reshape(2 * la + 1, 2 * lb + 1)
+    wa, wb = xcheck.contracted_weights(la, ea, da), xcheck.contracted_weights(lb, eb, db)
+    V = gc.emulate_block(la, lb, A, B, ea, wa, eb, wb, nuc.pos, nuc.Z)
+    assert np.all(np.abs(V - ref) <= 1e-13 + 1e-11 * np.abs(ref))
+
+
+def test_emulated_algorithm_on_z_axis_and_same_center():
+    # R along z (identity frame) and R = 0 (A = B)
+    nuc = synth.Nuclei(np.array([[0.2, -0.4, 1.1]]), np.array([3.0]))
+    for B in ([0.0, 0.0, 1.3], [0.0, 0.0, -0.7], [0.0, 0.0, 0.0]):
+        A = np.zeros(3)
+        bs = synth.Basis(np.array([A, B]), np.array([4, 3], np.int32), np.array([1, 1], np.int32),
+                         np.array([0, 1], np.int64), np.array([0.8, 1.9]), np.ones(2))
+        ref = oracle.nuc_blocks(bs, nuc, [0], [1], precision=2).reshape(9, 7)
+        wa, wb = xcheck.contracted_weights(4, [0.8], [1.0]), xcheck.contracted_weights(3, [1.9], [1.0])
+        V = gc.emulate_block(4, 3, A, B, [0.8], wa, [1.9], wb, nuc.pos, nuc.Z)
+        assert np.all(np.abs(V - ref) <= 1e-13 + 1e-11 * np.abs(ref))

@@ -1,0 +1,119 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by element.
+
+Bar (floating point, FP64): |V_gpu - V_oracle| <= 1e-13 + 1e-11 |V_oracle| for every element.
+Inputs are the seeded synthetic workloads of ``paper_2404_16245_amd.synth``.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_16245_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-11, 1e-13
+
+
+def assert_parity(got, ref, rtol=RTOL, atol=ATOL, what=""):
+    got, ref = np.asarray(got), np.asarray(ref)
+    assert got.shape == ref.shape
+    err = np.abs(got - ref)
+    bad = err > atol + rtol * np.abs(ref)
+    if bad.any():
+        i = int(np.argmax(np.where(bad, err, -1)))
+        raise AssertionError(f"{what}: {int(bad.sum())} of {bad.size} elements out of tolerance; "
+                             f"worst at {i}: got {got.flat[i]!r} ref {ref.flat[i]!r}")
+
+
+@pytest.fixture(scope="module")
+def shgo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_16245_amd as s
+    s.context(0)
+    return s
+
+
+def test_boys_device_against_oracle(shgo):
+    import torch
+    T = np.concatenate([[0.0, 1e-14, 1e-8, 1e-3], np.linspace(0.01, 29.99, 700), [29.999999, 30.0, 30.000001],
+                        np.linspace(30.5, 120.0, 200), [500.0, 1e4, 6.4e4]])
+    F = shgo.shgo_boys(shgo.context(0), torch.tensor(T, device="cuda"), 13).cpu().numpy()
+    ref = np.array([oracle.boys(13, t, precision=2) for t in T])
+    assert_parity(F, ref, rtol=5e-15 * 4, atol=0.0, what="Boys")
+
+
+def test_small_molecule_matrix(shgo):
+    b, n = synth.small_molecule(seed=1)
+    V = shgo.nuclear_attraction(b, n).cpu().numpy()
+    assert_parity(V, oracle.nuc_matrix(b, n), what="4-atom s/p/d matrix")
+    assert np.array_equal(V, V.T)
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_small_molecule_other_seeds(shgo, seed):
+    b, n = synth.small_molecule(seed=seed)
+    assert_parity(shgo.nuclear_attraction(b, n).cpu().numpy(), oracle.nuc_matrix(b, n), what=f"seed {seed}")
+
+
+def test_every_class_blocks(shgo):
+    hb, hn, pa, pb = synth.high_l_sweep(seed=7, pairs_per_class=3)
+    got = shgo.nuclear_attraction_pairs(hb, hn, pa, pb).cpu().numpy()
+    assert_parity(got, oracle.nuc_blocks(hb, hn, pa, pb), what="49 classes x 3 pairs")
+
+
+def test_ragged_tiles_and_swapped_pairs(shgo):
+    # 70 pairs per class: one full 64-pair tile plus a ragged tail; (2,5) pairs run swapped
+    hb, hn, pa, pb = synth.high_l_sweep(seed=8, pairs_per_class=70, classes=[(6, 6), (2, 5), (1, 0)])
+    got = shgo.nuclear_attraction_pairs(hb, hn, pa, pb).cpu().numpy()
+    assert_parity(got, oracle.nuc_blocks(hb, hn, pa, pb), what="ragged tiles")
+
+
+def test_contracted_screened_matrix(shgo):
+    b, n = synth.molecule(seed=11, n_atoms=8, box=12.0, ls=(0, 1, 2, 3, 4), kmax=6)
+    for screen in (0.0, 1e-12, 1e-4):
+        V = shgo.nuclear_attraction(b, n, screen=screen).cpu().numpy()
+        assert_parity(V, oracle.nuc_matrix(b, n, screen=screen), what=f"contracted, screen {screen}")
+    # the screen really removes work in this box
+    assert not np.allclose(shgo.nuclear_attraction(b, n, screen=1e-4).cpu().numpy(),
+                           shgo.nuclear_attraction(b, n).cpu().numpy(), rtol=0, atol=1e-12)
+
+
+def test_edge_cases(shgo):
+    b, n = synth.small_molecule(seed=1)
+    # no nuclei: V = 0 exactly
+    empty = synth.Nuclei(np.zeros((0, 3)), np.zeros(0))
+    assert np.all(shgo.nuclear_attraction(b, empty).cpu().numpy() == 0.0)
+    # nuclei sitting on the shell centers, shells sharing a center (R = 0), a pair a = a
+    on = synth.Nuclei(b.center[::3].copy(), np.array([1.0, 2.0, 3.0, 4.0]))
+    assert_parity(shgo.nuclear_attraction(b, on).cpu().numpy(), oracle.nuc_matrix(b, on), what="nuclei on centers")
+    # nucleus exactly at the Gaussian-product center (T = 0) of two equal-exponent shells
+    c0 = np.array([0.3, -0.2, 0.5])
+    two = synth.Basis(np.array([c0 - [0, 0, 0.4], c0 + [0, 0, 0.4]]), np.array([3, 2], np.int32),
+                      np.array([1, 1], np.int32), np.array([0, 1], np.int64), np.array([0.9, 0.9]), np.ones(2))
+    atP = synth.Nuclei(c0[None], np.array([2.0]))
+    assert_parity(shgo.nuclear_attraction(two, atP).cpu().numpy(), oracle.nuc_matrix(two, atP), what="T = 0")
+    # one shell, every l
+    for l in range(7):
+        one = synth.Basis(np.array([[0.1, 0.2, 0.3]]), np.array([l], np.int32), np.array([2], np.int32),
+                          np.array([0], np.int64), np.array([0.4, 3.0]), np.array([0.5, 0.7]))
+        assert_parity(shgo.nuclear_attraction(one, n).cpu().numpy(), oracle.nuc_matrix(one, n), what=f"one shell l={l}")
+    # a = b listed explicitly and an empty pair list
+    got = shgo.nuclear_attraction_pairs(b, n, [4, 4], [4, 2]).cpu().numpy()
+    assert_parity(got, oracle.nuc_blocks(b, n, [4, 4], [4, 2]), what="explicit pairs")
+    assert shgo.nuclear_attraction_pairs(b, n, [], []).numel() == 0
+
+
+def test_full_sweep_sampled(shgo):
+    # the full high-l sweep (49 classes x 2041 pairs, 64 nuclei), checked on sampled blocks
+    hb, hn, pa, pb = synth.high_l_sweep(seed=2)
+    got = shgo.nuclear_attraction_pairs(hb, hn, pa, pb).cpu().numpy()
+    sizes = oracle.block_sizes(hb, pa, pb)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(99)
+    sample = np.unique(np.concatenate([rng.choice(len(pa), 120, replace=False), [0, len(pa) - 1]]))
+    ref = oracle.nuc_blocks(hb, hn, pa[sample], pb[sample])
+    got_s = np.concatenate([got[offs[i]:offs[i + 1]] for i in sample])
+    assert_parity(got_s, ref, what="sampled full sweep")
+    assert np.all(np.isfinite(got))

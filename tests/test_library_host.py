@@ -1,0 +1,84 @@
+"""Host-side checks of the C-ABI library that need no GPU: exported symbols, validation paths,
+status strings, basis-function counts."""
+import re
+import os
+
+import numpy as np
+import pytest
+
+import paper_2404_16245_amd as shgo
+from paper_2404_16245_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "shgo.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(shgo_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = shgo.load_library()
+    names = declared_functions()
+    assert len(names) >= 13
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(shgo.EXPORTED)
+
+
+def test_status_strings():
+    for s in range(7):
+        assert shgo.shgo_status_string(s)
+    assert shgo.shgo_status_string(0) == "ok"
+
+
+def test_nbf():
+    b, _ = synth.small_molecule()
+    assert shgo.shgo_nbf(b) == 36
+    hb, _, _, _ = synth.high_l_sweep(pairs_per_class=1)
+    assert shgo.shgo_nbf(hb) == int(np.sum(2 * hb.l + 1))
+
+
+def _basis():
+    b, n = synth.small_molecule()
+    return b, n
+
+
+def test_validation_accepts_good_input():
+    b, n = _basis()
+    assert shgo.shgo_validate(b, n) == (0, "")
+    assert shgo.shgo_validate(b, synth.Nuclei(np.zeros((0, 3)), np.zeros(0)))[0] == shgo.SHGO_OK
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda b, n: b.l.__setitem__(2, 7), shgo.SHGO_ERR_UNSUPPORTED_L),
+    (lambda b, n: b.l.__setitem__(2, -1), shgo.SHGO_ERR_UNSUPPORTED_L),
+    (lambda b, n: b.expo.__setitem__(4, 0.0), shgo.SHGO_ERR_INVALID_ARG),
+    (lambda b, n: b.expo.__setitem__(4, -1.0), shgo.SHGO_ERR_INVALID_ARG),
+    (lambda b, n: b.expo.__setitem__(4, np.nan), shgo.SHGO_ERR_NOT_FINITE),
+    (lambda b, n: b.coef.__setitem__(1, np.inf), shgo.SHGO_ERR_NOT_FINITE),
+    (lambda b, n: b.center.__setitem__((1, 2), np.nan), shgo.SHGO_ERR_NOT_FINITE),
+    (lambda b, n: n.pos.__setitem__((0, 0), np.inf), shgo.SHGO_ERR_NOT_FINITE),
+    (lambda b, n: n.Z.__setitem__(0, np.nan), shgo.SHGO_ERR_NOT_FINITE),
+])
+def test_validation_rejects_bad_input(mutate, status):
+    b, n = _basis()
+    mutate(b, n)
+    st, msg = shgo.shgo_validate(b, n)
+    assert st == status and msg
+
+
+def test_validation_rejects_bad_screen():
+    b, n = _basis()
+    assert shgo.shgo_validate(b, n, screen=-1.0)[0] == shgo.SHGO_ERR_INVALID_ARG
+    assert shgo.shgo_validate(b, n, screen=float("nan"))[0] == shgo.SHGO_ERR_INVALID_ARG
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(shgo.ShgoError) as e:
+        shgo.shgo_create(0)
+    assert e.value.status == shgo.SHGO_ERR_DEVICE
