@@ -70,25 +70,38 @@ def class_id(la, lb):
     return a * (a + 1) // 2 + b
 
 
+def surviving_prim_pairs(basis, pa, pb, screen):
+    """Primitive pairs per shell pair that pass exp(-ab/(a+b) |A-B|^2) > screen (all if screen = 0)."""
+    ka = basis.nprim[pa].astype(np.int64)
+    kb = basis.nprim[pb].astype(np.int64)
+    if not screen > 0:
+        return ka * kb
+    n = ka * kb
+    rep = np.repeat(np.arange(len(pa)), n)
+    start = np.concatenate([[0], np.cumsum(n)[:-1]])
+    local = np.arange(int(n.sum())) - np.repeat(start, n)
+    i = local // np.repeat(kb, n)
+    j = local % np.repeat(kb, n)
+    ea = basis.expo[basis.prim_off[pa][rep] + i]
+    eb = basis.expo[basis.prim_off[pb][rep] + j]
+    R2 = np.sum((basis.center[pa] - basis.center[pb]) ** 2, axis=1)[rep]
+    keep = np.exp(-ea * eb / (ea + eb) * R2) > screen
+    return np.bincount(rep, weights=keep, minlength=len(pa)).astype(np.int64)
+
+
 def workload_flops(basis, nuclei, pa, pb, screen=0.0):
     """Model flops per class id (primitive pairs after screening) and in total."""
     gn = _gaunt_nnz()
+    la, lb = basis.l[pa].astype(np.int64), basis.l[pb].astype(np.int64)
+    hi, lo = np.maximum(la, lb), np.minimum(la, lb)
+    cid = hi * (hi + 1) // 2 + lo
+    npp = surviving_prim_pairs(basis, np.asarray(pa), np.asarray(pb), screen)
     per_class = np.zeros(28)
-    n_nuc = nuclei.n
-    for i in range(len(pa)):
-        a, b = int(pa[i]), int(pb[i])
-        la, lb = int(basis.l[a]), int(basis.l[b])
-        hi, lo = (a, b) if la >= lb else (b, a)
-        nucl, pair = model_flops(max(la, lb), min(la, lb), gn)
-        ea = basis.expo[basis.prim_off[hi]:basis.prim_off[hi] + basis.nprim[hi]]
-        eb = basis.expo[basis.prim_off[lo]:basis.prim_off[lo] + basis.nprim[lo]]
-        if screen > 0:
-            R2 = float(np.sum((basis.center[hi] - basis.center[lo]) ** 2))
-            mu = np.outer(ea, eb) / np.add.outer(ea, eb)
-            npp = int(np.count_nonzero(np.exp(-mu * R2) > screen))
-        else:
-            npp = len(ea) * len(eb)
-        per_class[class_id(la, lb)] += npp * (n_nuc * nucl + pair)
+    for c in np.unique(cid):
+        a = int((np.sqrt(8 * c + 1) - 1) // 2)
+        b = int(c - a * (a + 1) // 2)
+        nucl, pair = model_flops(a, b, gn)
+        per_class[c] = float(npp[cid == c].sum()) * (nuclei.n * nucl + pair)
     return per_class, float(per_class.sum())
 
 
@@ -216,34 +229,29 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
-    class_ms, nrec = shgo.shgo_plan_class_ms(plan)
+    phase_ms, nrec = shgo.shgo_plan_phase_ms(plan)
     shgo.shgo_plan_set_timing(plan, 0)
     ms_per_step = total_ms / args.steps
     value = plan.integrals * args.steps / (total_ms * 1e-3)
     log(f"bench: {ms_per_step:.4f} ms/step, {value:.4e} integrals/s")
 
     per_class_flops, total_flops = workload_flops(basis, nuclei, pa, pb, screen)
-    avg_class_ms = class_ms / max(nrec, 1)
-    dom = int(np.argmax(avg_class_ms))
-    la = int((np.sqrt(8 * dom + 1) - 1) // 2)
-    lb = dom - la * (la + 1) // 2
-    dom_s = avg_class_ms[dom] * 1e-3
-    achieved = per_class_flops[dom] / dom_s / 1e12
-    tag = f"k_class_{la}_{lb}_{args.workload}"
+    avg_phase_ms = phase_ms / max(nrec, 1)
+    kern_s = avg_phase_ms[1] * 1e-3
+    achieved = total_flops / kern_s / 1e12
+    tag = f"k_integrals_{args.workload}"
     traffic = traffic_from_profile(tag)
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": traffic,
-                "kernel": f"k_class<{la},{lb}>", "kernel_ms": avg_class_ms[dom],
-                "model_flops_per_launch": per_class_flops[dom]}
+                "kernel": "k_integrals (persistent, every class)", "kernel_ms": avg_phase_ms[1],
+                "model_flops_per_launch": total_flops}
     step_tflops = total_flops / (ms_per_step * 1e-3) / 1e12
     res = {"metric": METRIC, "value": value, "unit": "integrals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
            "integrals_per_step": plan.integrals,
            "fp64_model_tflops": step_tflops, "fp64_vector_peak_frac": step_tflops / (FP64_VECTOR_PEAK / 1e12),
-           "roofline": roofline,
-           "class_kernel_ms": {f"{int((np.sqrt(8 * c + 1) - 1) // 2)},{c - int((np.sqrt(8 * c + 1) - 1) // 2) * (int((np.sqrt(8 * c + 1) - 1) // 2) + 1) // 2}": round(float(avg_class_ms[c]), 5)
-                               for c in range(28) if avg_class_ms[c] > 0}}
+           "pair_build_ms": avg_phase_ms[0], "roofline": roofline}
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(basis, nuclei, pa, pb, args.cpu_seconds)

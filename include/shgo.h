@@ -39,7 +39,6 @@ extern "C" {
 #endif
 
 #define SHGO_LMAX 6 /* highest supported angular momentum of a shell */
-#define SHGO_NUM_CLASSES 28 /* (la, lb) classes with SHGO_LMAX >= la >= lb >= 0 */
 
 typedef enum {
   SHGO_OK = 0,
@@ -116,15 +115,16 @@ int64_t shgo_plan_integrals(const shgo_plan* plan);
  * (shgo_plan_output_size doubles; every element is written). Allocates nothing. */
 shgo_status shgo_execute(shgo_plan* plan, double* out, void* stream);
 
-/* Per-kernel timing. With n_slots > 0, every later shgo_execute records a pair of HIP events
- * around each class kernel (class id = la(la+1)/2 + lb for la >= lb), cycling through n_slots
- * sets of events; n_slots = 0 turns recording off. */
+/* Phase timing. With n_slots > 0, every later shgo_execute records HIP event pairs around
+ * its two phases -- 0: pair build (normalisation, enumeration, screening, class sort, work
+ * queue), 1: the integral kernel (one persistent launch over every class) -- cycling through
+ * n_slots sets of events; n_slots = 0 turns recording off. */
+#define SHGO_NUM_PHASES 2
 shgo_status shgo_plan_set_timing(shgo_plan* plan, int32_t n_slots);
 
-/* After the caller has synchronised the stream: for each of the SHGO_NUM_CLASSES classes, the
- * summed kernel milliseconds over the recorded executions still held in the slots (ms[c]) and
- * the number of those executions (count, the same for every class). */
-shgo_status shgo_plan_class_ms(shgo_plan* plan, double* ms, int32_t* count);
+/* After the caller has synchronised the stream: per phase, the summed milliseconds over the
+ * recorded executions still held in the slots (ms[SHGO_NUM_PHASES]) and how many those are. */
+shgo_status shgo_plan_phase_ms(shgo_plan* plan, double* ms, int32_t* count);
 
 /* Boys function F_m(t) = int_0^1 u^{2m} exp(-t u^2) du for m = 0..mmax (the radial factor of
  * Eq. 12), evaluated by the device routine the integral kernels use.  T: device array of n

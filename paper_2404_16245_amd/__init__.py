@@ -28,8 +28,8 @@ SHGO_LMAX = 6
 
 EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
-            "shgo_plan_integrals", "shgo_execute", "shgo_boys", "shgo_plan_set_timing", "shgo_plan_class_ms"]
-SHGO_NUM_CLASSES = 28
+            "shgo_plan_integrals", "shgo_execute", "shgo_boys", "shgo_plan_set_timing", "shgo_plan_phase_ms"]
+SHGO_NUM_PHASES = 2
 
 
 class ShgoError(RuntimeError):
@@ -90,8 +90,8 @@ def load_library(path=LIB_PATH):
     lib.shgo_boys.restype = ctypes.c_int
     lib.shgo_plan_set_timing.argtypes = [vp, i32]
     lib.shgo_plan_set_timing.restype = ctypes.c_int
-    lib.shgo_plan_class_ms.argtypes = [vp, vp, vp]
-    lib.shgo_plan_class_ms.restype = ctypes.c_int
+    lib.shgo_plan_phase_ms.argtypes = [vp, vp, vp]
+    lib.shgo_plan_phase_ms.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -238,12 +238,13 @@ def shgo_plan_set_timing(plan, n_slots):
     _check(lib, plan.ctx, lib.shgo_plan_set_timing(plan.handle, int(n_slots)))
 
 
-def shgo_plan_class_ms(plan):
-    """(ms[SHGO_NUM_CLASSES] summed over the recorded executions, number of executions)."""
+def shgo_plan_phase_ms(plan):
+    """(ms[SHGO_NUM_PHASES] summed over the recorded executions, number of executions).
+    Phase 0: pair build; phase 1: the integral kernel."""
     lib = load_library()
-    ms = np.zeros(SHGO_NUM_CLASSES)
+    ms = np.zeros(SHGO_NUM_PHASES)
     cnt = np.zeros(1, dtype=np.int32)
-    _check(lib, plan.ctx, lib.shgo_plan_class_ms(plan.handle, ms.ctypes.data, cnt.ctypes.data))
+    _check(lib, plan.ctx, lib.shgo_plan_phase_ms(plan.handle, ms.ctypes.data, cnt.ctypes.data))
     return ms, int(cnt[0])
 
 

@@ -149,6 +149,23 @@ def rot_x90(l):
     return J
 
 
+def monic_c(L, mu):
+    """S^L_{+-mu} = monic_c(L, mu) * Q_L for the monic recurrences of the nucleus step."""
+    c = 1.0
+    for l in range(mu):
+        c *= sect_coef(l)
+    for l in range(mu, L):
+        c *= vert_coefs(l, mu)[0]
+    return c
+
+
+def monic_e(l, mu):
+    """e_l of the monic vertical recurrence Q_{l+1} = z Q_l - e_l r^2 Q_{l-1}."""
+    a, b = vert_coefs(l, mu)
+    a_prev = vert_coefs(l - 1, mu)[0]
+    return b / (a * a_prev)
+
+
 def trans_coef(l, l1, m):
     """c(l, l1, m) = eps_{l l1 m m} (Eq. 8): shift of S^l_m along z keeps m."""
     m = abs(m)
@@ -336,47 +353,51 @@ def emit_group(LA, LB, gi, group):
     o.append(f"struct {name} {{")
     o.append(f"  static constexpr int NW = {NW};")
     # ---- nucleus step ----
+    # Monic recurrences: with Q^mu_mu + i Q^-mu_mu = Z (x + iy)^mu and
+    # Q_{L+1} = z Q_L - e_L r^2 Q_{L-1}, the real solid harmonics are S^L_{+-mu} = c_L Q^{+-mu}_L / Z
+    # (c_L = prod of the sectoral and vertical recurrence coefficients); c_L is applied in scale().
     o.append("  static __device__ __forceinline__ void step(double (&W)[NW], double x, double y, double z, double r2,")
-    o.append(f"                                               const double (&ZF)[{LM + 1}], const double (&tj)[{LB + 1}]) {{")
-    o.append("    double sc = 1.0, ss = 0.0;")
+    o.append(f"                                               double Z, const double (&F)[{LM + 1}], const double (&tj)[{LB + 1}]) {{")
+    o.append("    double sc = Z, ss = 0.0;")
     fams = sorted(group)
     cur_sect = 0
     for mu in fams:
         while cur_sect < mu:
-            f = sect_coef(cur_sect)
             if cur_sect == 0:
-                o.append("    sc = x; ss = y;")
+                o.append("    sc = Z * x; ss = Z * y;")
             else:
-                o.append(f"    {{ const double nc = {lit(f)} * (x * sc - y * ss); ss = {lit(f)} * (y * sc + x * ss); sc = nc; }}")
+                o.append("    { const double nc = fma(x, sc, -y * ss); ss = fma(y, sc, x * ss); sc = nc; }")
             cur_sect += 1
         o.append(f"    {{ // family |M| = {mu}")
         o.append("      double cc = sc, cs = ss, pc = 0.0, ps = 0.0;")
         for L in range(mu, LM + 1):
             if L > mu:
-                a, b = vert_coefs(L - 1, mu)
-                if mu == L - 1:
-                    o.append(f"      {{ const double nc = {lit(a)} * z * cc; pc = cc; cc = nc; }}")
+                if L - 1 == mu:
+                    o.append("      { pc = cc; cc = z * cc; }")
                     if mu > 0:
-                        o.append(f"      {{ const double ns = {lit(a)} * z * cs; ps = cs; cs = ns; }}")
+                        o.append("      { ps = cs; cs = z * cs; }")
                 else:
-                    o.append(f"      {{ const double nc = {lit(a)} * z * cc - {lit(b)} * r2 * pc; pc = cc; cc = nc; }}")
+                    e = monic_e(L - 1, mu)
+                    o.append(f"      {{ const double E = {lit(-e)} * r2;")
+                    o.append("        const double nc = fma(z, cc, E * pc); pc = cc; cc = nc;")
                     if mu > 0:
-                        o.append(f"      {{ const double ns = {lit(a)} * z * cs - {lit(b)} * r2 * ps; ps = cs; cs = ns; }}")
+                        o.append("        const double ns = fma(z, cs, E * ps); ps = cs; cs = ns;")
+                    o.append("      }")
             km = kmax_of(LA, LB, L)
-            o.append(f"      {{ double g = ZF[{L}];")
+            o.append(f"      {{ double g = F[{L}];")
             for k in range(km + 1):
                 if k > 0:
-                    o.append(f"        g = fma(tj[{k}], ZF[{L + k}], g);")
+                    o.append(f"        g = fma(tj[{k}], F[{L + k}], g);")
                 o.append(f"        W[{idx[(L, mu, k)]}] = fma(g, cc, W[{idx[(L, mu, k)]}]);")
                 if mu > 0:
                     o.append(f"        W[{idx[(L, -mu, k)]}] = fma(g, cs, W[{idx[(L, -mu, k)]}]);")
             o.append("      }")
         o.append("    }")
     o.append("  }")
-    # ---- scaling by pre * 2 pi k!/p^{k+1} ----
+    # ---- scaling by pre * 2 pi k!/p^{k+1} and the harmonic normalisation c_L ----
     o.append(f"  static __device__ __forceinline__ void scale(double (&W)[NW], const double (&fk)[{LB + 1}]) {{")
     for (L, M, k), i in idx.items():
-        o.append(f"    W[{i}] *= fk[{k}];")
+        o.append(f"    W[{i}] *= fk[{k}] * {lit(monic_c(L, abs(M)))};")
     o.append("  }")
     # ---- coupling ----
     terms = [t for t in class_terms(LA, LB) if abs(t[5]) in group]
@@ -386,6 +407,7 @@ def emit_group(LA, LB, gi, group):
     NB = 2 * LB + 1
     o.append(f"  static __device__ __forceinline__ void couple(const double (&W)[NW], const double (&ta)[{LA + 1}],")
     o.append(f"                                                 const double (&tb)[{LB + 1}], double* __restrict__ Vp) {{")
+    o.append("    // Vp: this lane's entry (0, 0) of the tile accumulator; entries are SHGO_TILE apart")
     for (ma, mb), ts in sorted(by_mm.items()):
         o.append(f"    {{ // (ma, mb) = ({ma}, {mb})")
         o.append("      double v = 0.0;")
@@ -407,7 +429,7 @@ def emit_group(LA, LB, gi, group):
                 o.append("        v += u; }")
             else:
                 o.append(f"        v = fma(ta[{LA - l1}], u, v); }}")
-        o.append(f"      atomicAdd(Vp + {(ma + LA) * NB + (mb + LB)}, v);")
+        o.append(f"      atomicAdd(Vp + {(ma + LA) * NB + (mb + LB)} * SHGO_TILE, v);")
         o.append("    }")
     o.append("  }")
     o.append("};")
@@ -462,12 +484,17 @@ def emit_header(cap=DEFAULT_CAP, lmax=LMAX_SHELL):
         out.append(emit_rotation(l))
     out.append("template <int LA, int LB> struct ClassInfo;")
     out.append("template <int LA, int LB, int G> struct GroupOf;")
+    qs = [len(class_groups(LA, LB, cap)) for LA in range(lmax + 1) for LB in range(LA + 1)]
+    out.append("// groups per class, indexed by la(la+1)/2 + lb")
+    out.append(f"constexpr int kClassGroups[{len(qs)}] = {{{', '.join(map(str, qs))}}};")
     for LA in range(lmax + 1):
         for LB in range(LA + 1):
             groups = class_groups(LA, LB, cap)
             for gi, g in enumerate(groups):
                 out.append(emit_group(LA, LB, gi, g))
-            out.append(f"template <> struct ClassInfo<{LA}, {LB}> {{ static constexpr int Q = {len(groups)}; }};")
+            nwmax = max(len(group_index(LA, LB, g)) for g in groups)
+            out.append(f"template <> struct ClassInfo<{LA}, {LB}> {{ static constexpr int Q = {len(groups)}; "
+                       f"static constexpr int NWMAX = {nwmax}; }};")
             for gi, g in enumerate(groups):
                 out.append(f"template <> struct GroupOf<{LA}, {LB}, {gi}> : G{LA}{LB}_{gi} {{}};")
     return "\n".join(out) + "\n"

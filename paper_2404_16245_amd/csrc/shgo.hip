@@ -23,10 +23,13 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <utility>
 #include <string>
 #include <vector>
 
 #include "shgo.h"
+#define SHGO_TILE 64  // shell pairs per tile: one per lane of a wavefront
 #include "generated/shgo_classes.inc"
 
 namespace {
@@ -37,9 +40,9 @@ namespace {
 constexpr int kBoysOrders = 22;    // F_0..F_21 stored per grid point (mmax <= 14 with 8 Taylor terms)
 constexpr int kBoysPoints = 481;   // grid t_i = i/16, i = 0..480
 constexpr double kBoysTcut = 30.0; // below: table + downward recursion; above: asymptote + upward
-constexpr int kNumClasses = SHGO_NUM_CLASSES;
-static_assert(kNumClasses == (SHGO_LMAX + 1) * (SHGO_LMAX + 2) / 2, "class count");
+constexpr int kNumClasses = (SHGO_LMAX + 1) * (SHGO_LMAX + 2) / 2;  // (la, lb) with la >= lb
 constexpr int kKeysPerClass = 256;
+constexpr int kTile = SHGO_TILE;
 constexpr int kNumKeys = kNumClasses * kKeysPerClass;
 
 __host__ __device__ constexpr int class_id(int la, int lb) { return la * (la + 1) / 2 + lb; }
@@ -73,7 +76,7 @@ struct DevPairs {
   int32_t* orig;           // [n_cand] sorted: candidate index
   int32_t* nsurv;          // [n_cand] sorted: surviving primitive pairs
   int32_t* key_count;      // [kNumKeys]
-  int32_t* key_fill;       // [kNumKeys]
+  int32_t* rank;           // [n_cand] position inside the key's bucket
   int32_t* key_off;        // [kNumKeys + 1]
   double screen;
 };
@@ -106,8 +109,45 @@ __device__ __forceinline__ void boys(double t, double (&F)[M + 1], const double*
 #pragma unroll
     for (int m = M - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
   } else {
-    const double it = 1.0 / t;
-    const double f0 = 0.88622692545275801365 * sqrt(it);  // sqrt(pi)/2 / sqrt(t)
+    // 1/sqrt(t) from the hardware estimate and two Newton steps (each doubles the bits)
+    double rs = __builtin_amdgcn_rsq(t);
+    rs = rs * fma(-0.5 * t * rs, rs, 1.5);
+    rs = rs * fma(-0.5 * t * rs, rs, 1.5);
+    const double it = rs * rs;
+    const double f0 = 0.88622692545275801365 * rs;  // sqrt(pi)/2 / sqrt(t)
+    const double corr = 0.5 * e * it * fma(it, fma(it, 0.75, -0.5), 1.0);
+    F[0] = f0 - corr;
+    const double h = 0.5 * it;
+#pragma unroll
+    for (int m = 0; m < M; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -e) * h;
+  }
+}
+
+// The same evaluation with the Taylor row F_{M..M+7}(t_i) already loaded (row[k], k < 8) and
+// e = exp(-t): used by the integral kernels, which fetch the row of the next nucleus early.
+template <int M>
+__device__ __forceinline__ void boys_row(double t, double e, const double (&row)[8], double (&F)[M + 1]) {
+  if (t < kBoysTcut) {
+    const int i = (int)(t * 16.0 + 0.5);
+    const double d = -(t - 0.0625 * (double)i);
+    double f = row[7];
+    f = fma(f, d * (1.0 / 7.0), row[6]);
+    f = fma(f, d * (1.0 / 6.0), row[5]);
+    f = fma(f, d * (1.0 / 5.0), row[4]);
+    f = fma(f, d * (1.0 / 4.0), row[3]);
+    f = fma(f, d * (1.0 / 3.0), row[2]);
+    f = fma(f, d * (1.0 / 2.0), row[1]);
+    f = fma(f, d, row[0]);
+    F[M] = f;
+    const double t2 = 2.0 * t;
+#pragma unroll
+    for (int m = M - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
+  } else {
+    double rs = __builtin_amdgcn_rsq(t);
+    rs = rs * fma(-0.5 * t * rs, rs, 1.5);
+    rs = rs * fma(-0.5 * t * rs, rs, 1.5);
+    const double it = rs * rs;
+    const double f0 = 0.88622692545275801365 * rs;
     const double corr = 0.5 * e * it * fma(it, fma(it, 0.75, -0.5), 1.0);
     F[0] = f0 - corr;
     const double h = 0.5 * it;
@@ -178,31 +218,47 @@ __device__ __forceinline__ bool keep_prim(double a, double b, double R2, double 
   return exp(-a * b / (a + b) * R2) > screen;
 }
 
-__global__ void k_classify(DevBasis bs, DevPairs pr) {
+// Classification in workgroups of 256 candidates: the key of each candidate, its rank among
+// the workgroup's candidates with the same key (LDS atomics), and one global atomic per
+// (workgroup, key) that reserves the workgroup's range inside the key's bucket.
+__global__ void __launch_bounds__(256) k_classify(DevBasis bs, DevPairs pr) {
+  __shared__ int hist[kNumKeys];
+  __shared__ int base[kNumKeys];
+  for (int b = threadIdx.x; b < kNumKeys; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= pr.n_cand) return;
-  int a, b;
-  if (pr.full) {
-    tri_pair(i, bs.n_shells, a, b);
-  } else {
-    a = pr.pa[i];
-    b = pr.pb[i];
+  int key = -1, rank = 0;
+  if (i < pr.n_cand) {
+    int a, b;
+    if (pr.full) {
+      tri_pair(i, bs.n_shells, a, b);
+    } else {
+      a = pr.pa[i];
+      b = pr.pb[i];
+    }
+    const int la = bs.l[a], lb = bs.l[b];
+    const int s1 = la >= lb ? a : b, s2 = la >= lb ? b : a;
+    const int L1 = bs.l[s1], L2 = bs.l[s2];
+    double R2 = 0.0;
+    for (int x = 0; x < 3; ++x) {
+      const double d = bs.center[3 * s2 + x] - bs.center[3 * s1 + x];
+      R2 += d * d;
+    }
+    int ns = 0;
+    const int64_t o1 = bs.prim_off[s1], o2 = bs.prim_off[s2];
+    for (int p = 0; p < bs.nprim[s1]; ++p)
+      for (int q = 0; q < bs.nprim[s2]; ++q) ns += keep_prim(bs.expo[o1 + p], bs.expo[o2 + q], R2, pr.screen);
+    key = class_id(L1, L2) * kKeysPerClass + min(ns, kKeysPerClass - 1);
+    rank = atomicAdd(&hist[key], 1);
   }
-  const int la = bs.l[a], lb = bs.l[b];
-  const int s1 = la >= lb ? a : b, s2 = la >= lb ? b : a;
-  const int L1 = bs.l[s1], L2 = bs.l[s2];
-  double R2 = 0.0;
-  for (int x = 0; x < 3; ++x) {
-    const double d = bs.center[3 * s2 + x] - bs.center[3 * s1 + x];
-    R2 += d * d;
+  __syncthreads();
+  for (int b = threadIdx.x; b < kNumKeys; b += blockDim.x)
+    if (hist[b] > 0) base[b] = atomicAdd(&pr.key_count[b], hist[b]);
+  __syncthreads();
+  if (i < pr.n_cand) {
+    pr.key[i] = key;
+    pr.rank[i] = base[key] + rank;
   }
-  int ns = 0;
-  const int64_t o1 = bs.prim_off[s1], o2 = bs.prim_off[s2];
-  for (int p = 0; p < bs.nprim[s1]; ++p)
-    for (int q = 0; q < bs.nprim[s2]; ++q) ns += keep_prim(bs.expo[o1 + p], bs.expo[o2 + q], R2, pr.screen);
-  const int key = class_id(L1, L2) * kKeysPerClass + min(ns, kKeysPerClass - 1);
-  pr.key[i] = key;
-  atomicAdd(&pr.key_count[key], 1);
 }
 
 // Exclusive scan of key_count into key_off (one workgroup of 1024 threads).
@@ -245,7 +301,7 @@ __global__ void k_scatter(DevBasis bs, DevPairs pr) {
     b = pr.pb[i];
   }
   const int key = pr.key[i];
-  const int slot = pr.key_off[key] + atomicAdd(&pr.key_fill[key], 1);
+  const int slot = pr.key_off[key] + pr.rank[i];
   const bool sw = bs.l[a] < bs.l[b];
   pr.s1[slot] = sw ? b : a;
   pr.s2[slot] = sw ? a : b;
@@ -254,15 +310,31 @@ __global__ void k_scatter(DevBasis bs, DevPairs pr) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// a2-a8: the class kernel
+// a2-a8: the persistent integral kernel
 // ---------------------------------------------------------------------------------------------
-struct ClassArgs {
+// Work item = (class, tile of SHGO_TILE class-sorted shell pairs, group of |M| families). Every
+// wavefront pulls items from one queue (classes in decreasing cost per tile), runs the group's
+// primitive-pair and nucleus loops for the tile's pairs (one pair per lane) and adds its part of
+// each block V' to the tile's accumulator in HBM with atomic adds. The wavefront that completes
+// the last group of a tile rotates the tile's blocks back to the laboratory frame and writes them.
+struct ClassMeta {
+  int32_t order[kNumClasses];      // queue order: classes by decreasing cost per tile
+  int64_t vacc_base[kNumClasses];  // first accumulator double of each class
+  int32_t tile_base[kNumClasses];  // first tile counter of each class
+};
+
+struct WorkArgs {
   DevBasis bs;
   DevPairs pr;
   const Nuc* __restrict__ nuc;
   int32_t n_nuc;
   const double* __restrict__ boys_tab;
   double* __restrict__ out;
+  double* __restrict__ vacc;       // tile accumulators: [tile][NA*NB][SHGO_TILE]
+  int32_t* __restrict__ tile_cnt;  // groups finished per tile
+  int32_t* __restrict__ queue;     // [0]: next work item
+  int32_t* __restrict__ item_off;  // [kNumClasses + 1]: prefix of items per class in queue order
+  ClassMeta meta;
 };
 
 // Per-lane shell-pair state.
@@ -299,7 +371,7 @@ __device__ __forceinline__ void frame_of(PairState& ps) {
 }
 
 // Advance (i, j) to the next primitive pair that survives screening; false when exhausted.
-__device__ __forceinline__ bool next_prim(const PairState& ps, const ClassArgs& ca, int& i, int& j) {
+__device__ __forceinline__ bool next_prim(const PairState& ps, const WorkArgs& wa, int& i, int& j) {
   const double R2 = ps.R * ps.R;
   while (true) {
     ++j;
@@ -308,20 +380,20 @@ __device__ __forceinline__ bool next_prim(const PairState& ps, const ClassArgs& 
       ++i;
     }
     if (i >= ps.K1) return false;
-    if (keep_prim(ca.bs.expo[ps.o1 + i], ca.bs.expo[ps.o2 + j], R2, ca.pr.screen)) return true;
+    if (keep_prim(wa.bs.expo[ps.o1 + i], wa.bs.expo[ps.o2 + j], R2, wa.pr.screen)) return true;
   }
 }
 
 template <int LA, int LB, int G>
-__device__ __forceinline__ void run_group(const PairState& ps, const ClassArgs& ca, int wave_iters,
+__device__ __forceinline__ void run_group(const PairState& ps, const WorkArgs& wa, int wave_iters,
                                           double* __restrict__ Vp) {
   using Grp = GroupOf<LA, LB, G>;
   constexpr int LM = LA + LB;
   int pi = 0, pj = -1;
   for (int it = 0; it < wave_iters; ++it) {
-    const bool have = ps.active && next_prim(ps, ca, pi, pj);
+    const bool have = ps.active && next_prim(ps, wa, pi, pj);
     if (have) {
-      const double a = ca.bs.expo[ps.o1 + pi], b = ca.bs.expo[ps.o2 + pj];
+      const double a = wa.bs.expo[ps.o1 + pi], b = wa.bs.expo[ps.o2 + pj];
       const double p = a + b, ip = 1.0 / p;
       const double Px = (a * ps.A[0] + b * ps.B[0]) * ip;
       const double Py = (a * ps.A[1] + b * ps.B[1]) * ip;
@@ -329,29 +401,43 @@ __device__ __forceinline__ void run_group(const PairState& ps, const ClassArgs& 
       double W[Grp::NW];
 #pragma unroll
       for (int q = 0; q < Grp::NW; ++q) W[q] = 0.0;
-      for (int c = 0; c < ca.n_nuc; ++c) {
-        const Nuc n = ca.nuc[c];
+      // nucleus loop, software-pipelined: the geometry and Boys-table row of nucleus c+1 are
+      // fetched while nucleus c is processed
+      double nx = 0.0, ny = 0.0, nz = 0.0, nr2 = 0.0, nt = 0.0, nZ = 0.0, nrow[8];
+      auto geometry = [&](int c) {
+        const Nuc n = wa.nuc[c];
         const double cx = n.x - Px, cy = n.y - Py, cz = n.z - Pz;
         const double u = fma(ps.cp, cx, ps.sp * cy);
-        const double x = fma(ps.ct, u, -ps.st * cz);
-        const double y = fma(-ps.sp, cx, ps.cp * cy);
-        const double z = fma(ps.st, u, ps.ct * cz);
-        const double r2 = fma(cx, cx, fma(cy, cy, cz * cz));
-        const double t = p * r2;
-        double F[LM + 1];
-        boys<LM>(t, F, ca.boys_tab);
-        double ZF[LM + 1];
+        nx = fma(ps.ct, u, -ps.st * cz);
+        ny = fma(-ps.sp, cx, ps.cp * cy);
+        nz = fma(ps.st, u, ps.ct * cz);
+        nr2 = fma(cx, cx, fma(cy, cy, cz * cz));
+        nt = p * nr2;
+        nZ = n.Z;
+        const int i = min((int)(nt * 16.0 + 0.5), kBoysPoints - 1);
+        const double* __restrict__ r = wa.boys_tab + i * kBoysOrders + LM;
 #pragma unroll
-        for (int m = 0; m <= LM; ++m) ZF[m] = n.Z * F[m];
+        for (int k = 0; k < 8; ++k) nrow[k] = r[k];
+      };
+      if (wa.n_nuc > 0) geometry(0);
+      for (int c = 0; c < wa.n_nuc; ++c) {
+        const double x = nx, y = ny, z = nz, r2 = nr2, t = nt, Zc = nZ;
+        double row[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) row[k] = nrow[k];
+        if (c + 1 < wa.n_nuc) geometry(c + 1);
+        const double e = exp(-t);
+        double F[LM + 1];
+        boys_row<LM>(t, e, row, F);
         double tj[LB + 1];
         tj[0] = 1.0;
 #pragma unroll
         for (int k = 1; k <= LB; ++k) tj[k] = tj[k - 1] * t * (1.0 / k);
-        Grp::step(W, x, y, z, r2, ZF, tj);
+        Grp::step(W, x, y, z, r2, Zc, F, tj);
       }
       // prefactor -w_a w_b exp(-mu R^2) and 2 pi k!/p^{k+1}
       const double K = exp(-a * b * ip * ps.R * ps.R);
-      const double pre = -ca.bs.w[ps.o1 + pi] * ca.bs.w[ps.o2 + pj] * K;
+      const double pre = -wa.bs.w[ps.o1 + pi] * wa.bs.w[ps.o2 + pj] * K;
       double fk[LB + 1];
       fk[0] = pre * 6.283185307179586477 * ip;
 #pragma unroll
@@ -371,14 +457,14 @@ __device__ __forceinline__ void run_group(const PairState& ps, const ClassArgs& 
 }
 
 template <int LA, int LB, int G>
-__device__ __forceinline__ void dispatch_group(int g, const PairState& ps, const ClassArgs& ca, int wave_iters,
+__device__ __forceinline__ void dispatch_group(int g, const PairState& ps, const WorkArgs& wa, int wave_iters,
                                                double* Vp) {
   if constexpr (G < ClassInfo<LA, LB>::Q) {
     if (g == G) {
-      run_group<LA, LB, G>(ps, ca, wave_iters, Vp);
+      run_group<LA, LB, G>(ps, wa, wave_iters, Vp);
       return;
     }
-    dispatch_group<LA, LB, G + 1>(g, ps, ca, wave_iters, Vp);
+    dispatch_group<LA, LB, G + 1>(g, ps, wa, wave_iters, Vp);
   }
 }
 
@@ -393,98 +479,158 @@ __device__ __forceinline__ void angles(double c1, double s1, double (&c)[L + 1],
   }
 }
 
+// Rotate the accumulated blocks of a tile back to the laboratory frame
+// (V = D_a^T V' D_b, D^T = Z(phi) J^T Z(theta) J; rows in place, then columns) and write them.
 template <int LA, int LB>
-__global__ void __launch_bounds__((64 * ClassInfo<LA, LB>::Q)) k_class(ClassArgs ca) {
-  constexpr int Q = ClassInfo<LA, LB>::Q;
-  constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NAB = NA * NB;
-  extern __shared__ double Vs[];  // [64][NA][NB]
-  const int cls = class_id(LA, LB);
-  const int start = ca.pr.key_off[cls * kKeysPerClass];
-  const int end = ca.pr.key_off[(cls + 1) * kKeysPerClass];
-  const int base = start + blockIdx.x * 64;
-  if (base >= end) return;  // uniform over the workgroup
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-
-  for (int i = threadIdx.x; i < 64 * NAB; i += 64 * Q) Vs[i] = 0.0;
-
-  PairState ps;
-  const int slot = base + lane;
-  ps.active = slot < end;
-  const int sl = ps.active ? slot : end - 1;
-  ps.s1 = ca.pr.s1[sl];
-  ps.s2 = ca.pr.s2[sl];
-  ps.nsurv = ps.active ? ca.pr.nsurv[sl] : 0;
-#pragma unroll
-  for (int x = 0; x < 3; ++x) {
-    ps.A[x] = ca.bs.center[3 * ps.s1 + x];
-    ps.B[x] = ca.bs.center[3 * ps.s2 + x];
-  }
-  ps.o1 = ca.bs.prim_off[ps.s1];
-  ps.o2 = ca.bs.prim_off[ps.s2];
-  ps.K1 = ca.bs.nprim[ps.s1];
-  ps.K2 = ca.bs.nprim[ps.s2];
-  frame_of(ps);
-  // the number of primitive-pair iterations of this wavefront (keys cap at 255; the cap only
-  // costs idle iterations, every lane still visits all of its surviving pairs)
-  int iters = ps.active ? (ps.nsurv >= kKeysPerClass - 1 ? ps.K1 * ps.K2 : ps.nsurv) : 0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) iters = max(iters, __shfl_xor(iters, off));
-  __syncthreads();
-
-  double* Vp = Vs + lane * NAB;
-  dispatch_group<LA, LB, 0>(wave, ps, ca, iters, Vp);
-  __syncthreads();
-
-  // rotate back: V = D_a^T V' D_b with D^T = Z(phi) J^T Z(theta) J; rows first, then columns
+__device__ __forceinline__ void finish_tile(const PairState& ps, const WorkArgs& wa, int slot, double* Vp) {
+  constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1;
   double cth[LA + 1], sth[LA + 1], cph[LA + 1], sph[LA + 1];
   angles<LA>(ps.ct, ps.st, cth, sth);
   angles<LA>(ps.cp, ps.sp, cph, sph);
-  for (int r = wave; r < NA; r += Q) {
+  for (int r = 0; r < NA; ++r) {
     double v[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) v[j] = Vp[r * NB + j];
+    for (int j = 0; j < NB; ++j) v[j] = Vp[(r * NB + j) * kTile];
     Rot<LB>::apply(v, cth, sth, cph, sph);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) Vp[r * NB + j] = v[j];
+    for (int j = 0; j < NB; ++j) Vp[(r * NB + j) * kTile] = v[j];
   }
-  __syncthreads();
-  if (!ps.active) return;
-  for (int col = wave; col < NB; col += Q) {
+  // the rotated rows must be read back from L2, not from a stale vector-L1 line
+  __threadfence();
+  for (int col = 0; col < NB; ++col) {
     double v[NA];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) v[i] = Vp[i * NB + col];
+    for (int i = 0; i < NA; ++i) v[i] = Vp[(i * NB + col) * kTile];
     Rot<LA>::apply(v, cth, sth, cph, sph);
-    if (ca.pr.full) {
-      const int64_t r0 = ca.bs.bf_off[ps.s1], c0 = ca.bs.bf_off[ps.s2], n = ca.bs.nbf;
+    if (!ps.active) continue;
+    if (wa.pr.full) {
+      const int64_t r0 = wa.bs.bf_off[ps.s1], c0 = wa.bs.bf_off[ps.s2], n = wa.bs.nbf;
       if (ps.s1 != ps.s2) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-          ca.out[(r0 + i) * n + c0 + col] = v[i];
-          ca.out[(c0 + col) * n + r0 + i] = v[i];
+          wa.out[(r0 + i) * n + c0 + col] = v[i];
+          wa.out[(c0 + col) * n + r0 + i] = v[i];
         }
       } else {
         // diagonal block: the upper triangle is mirrored so that V is exactly symmetric
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
           if (i <= col) {
-            ca.out[(r0 + i) * n + c0 + col] = v[i];
-            ca.out[(c0 + col) * n + r0 + i] = v[i];
+            wa.out[(r0 + i) * n + c0 + col] = v[i];
+            wa.out[(c0 + col) * n + r0 + i] = v[i];
           }
         }
       }
     } else {
-      const int o = ca.pr.orig[slot];
-      const int64_t bo = ca.pr.blk_off[o];
-      const bool sw = ca.pr.pa[o] != ps.s1;
+      const int o = wa.pr.orig[slot];
+      const int64_t bo = wa.pr.blk_off[o];
+      const bool sw = wa.pr.pa[o] != ps.s1;
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
         if (sw)
-          ca.out[bo + (int64_t)col * NA + i] = v[i];
+          wa.out[bo + (int64_t)col * NA + i] = v[i];
         else
-          ca.out[bo + (int64_t)i * NB + col] = v[i];
+          wa.out[bo + (int64_t)i * NB + col] = v[i];
       }
     }
   }
+}
+
+// One work item of class (LA, LB): tile j / Q, group j % Q. Kept out of line so that every
+// class is compiled and register-allocated on its own.
+template <int LA, int LB>
+__device__ __attribute__((noinline)) void process_item(int j, const WorkArgs& wa) {
+  constexpr int Q = ClassInfo<LA, LB>::Q;
+  constexpr int NAB = (2 * LA + 1) * (2 * LB + 1);
+  constexpr int cls = class_id(LA, LB);
+  const int lane = threadIdx.x & 63;
+  const int tile = j / Q, g = j - tile * Q;
+  const int start = wa.pr.key_off[cls * kKeysPerClass];
+  const int end = wa.pr.key_off[(cls + 1) * kKeysPerClass];
+  const int slot = start + tile * kTile + lane;
+
+  PairState ps;
+  ps.active = slot < end;
+  const int sl = ps.active ? slot : end - 1;
+  ps.s1 = wa.pr.s1[sl];
+  ps.s2 = wa.pr.s2[sl];
+  ps.nsurv = ps.active ? wa.pr.nsurv[sl] : 0;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    ps.A[x] = wa.bs.center[3 * ps.s1 + x];
+    ps.B[x] = wa.bs.center[3 * ps.s2 + x];
+  }
+  ps.o1 = wa.bs.prim_off[ps.s1];
+  ps.o2 = wa.bs.prim_off[ps.s2];
+  ps.K1 = wa.bs.nprim[ps.s1];
+  ps.K2 = wa.bs.nprim[ps.s2];
+  frame_of(ps);
+  // primitive-pair iterations of this wavefront (keys saturate at 255; then every candidate
+  // primitive pair is visited and the screened ones skipped)
+  int iters = ps.active ? (ps.nsurv >= kKeysPerClass - 1 ? ps.K1 * ps.K2 : ps.nsurv) : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) iters = max(iters, __shfl_xor(iters, off));
+
+  double* Vp = wa.vacc + wa.meta.vacc_base[cls] + (int64_t)tile * NAB * kTile + lane;
+  dispatch_group<LA, LB, 0>(g, ps, wa, iters, Vp);
+
+  // completion: release this group's atomic adds, count it, and let the last group finish
+  int done = 0;
+  if (lane == 0)
+    done = __hip_atomic_fetch_add(wa.tile_cnt + wa.meta.tile_base[cls] + tile, 1, __ATOMIC_ACQ_REL,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  done = __shfl(done, 0);
+  if (done == Q - 1) {
+    __threadfence();
+    finish_tile<LA, LB>(ps, wa, slot, Vp);
+  }
+}
+
+template <int LA, int LB>
+__device__ __forceinline__ void dispatch_class(int c, int j, const WorkArgs& wa) {
+  if constexpr (LA <= SHGO_LMAX) {
+    if (c == class_id(LA, LB)) {
+      process_item<LA, LB>(j, wa);
+      return;
+    }
+    if constexpr (LB < LA)
+      dispatch_class<LA, LB + 1>(c, j, wa);
+    else
+      dispatch_class<LA + 1, 0>(c, j, wa);
+  }
+}
+
+// Queue layout: for the k-th class in queue order, its tiles x groups items, tile-major.
+__global__ void k_items(DevPairs pr, ClassMeta meta, int32_t* item_off) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int off = 0;
+  for (int k = 0; k < kNumClasses; ++k) {
+    const int c = meta.order[k];
+    const int count = pr.key_off[(c + 1) * kKeysPerClass] - pr.key_off[c * kKeysPerClass];
+    item_off[k] = off;
+    off += (count + kTile - 1) / kTile * kClassGroups[c];
+  }
+  item_off[kNumClasses] = off;
+}
+
+// Every wavefront loops: take the next item, run it; the loop ends once the queue is drained.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_integrals(WorkArgs wa) {
+  const int lane = threadIdx.x & 63;
+  const int total = wa.item_off[kNumClasses];
+  while (true) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(wa.queue, 1);
+    item = __shfl(item, 0);
+    if (item >= total) break;
+    int k = 0;
+    while (wa.item_off[k + 1] <= item) ++k;
+    dispatch_class<0, 0>(wa.meta.order[k], item - wa.item_off[k], wa);
+  }
+}
+
+__global__ void k_fill_f64(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -509,49 +655,20 @@ std::vector<double> boys_table() {
   return tab;
 }
 
-using LaunchFn = void (*)(const ClassArgs&, int grid, hipStream_t);
-
-template <int LA, int LB>
-void launch_class(const ClassArgs& ca, int grid, hipStream_t st) {
-  constexpr int Q = ClassInfo<LA, LB>::Q;
-  const size_t lds = (size_t)64 * (2 * LA + 1) * (2 * LB + 1) * sizeof(double);
-  hipLaunchKernelGGL((k_class<LA, LB>), dim3(grid), dim3(64 * Q), lds, st, ca);
-}
-
-template <int LA, int LB>
-hipError_t prepare_class() {
-  const size_t lds = (size_t)64 * (2 * LA + 1) * (2 * LB + 1) * sizeof(double);
-  return hipFuncSetAttribute((const void*)k_class<LA, LB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
-
-struct ClassTable {
-  LaunchFn launch[kNumClasses];
-  hipError_t (*prepare[kNumClasses])();
-  ClassTable() {
-    fill<0, 0>();
-  }
-  template <int LA, int LB>
-  void fill() {
-    if constexpr (LA <= SHGO_LMAX) {
-      launch[class_id(LA, LB)] = &launch_class<LA, LB>;
-      prepare[class_id(LA, LB)] = &prepare_class<LA, LB>;
-      if constexpr (LB < LA)
-        fill<LA, LB + 1>();
-      else
-        fill<LA + 1, 0>();
-    }
-  }
-};
-
-const ClassTable& class_table() {
-  static ClassTable t;
-  return t;
+// Relative cost of one tile of a class (orders the queue only): nucleus-step and coupling
+// operation counts.
+double class_cost(int la, int lb, int n_nuc) {
+  const int lm = la + lb;
+  double nw = 0.0;
+  for (int k = 0; k <= lb; ++k) nw += (double)(lm - 2 * k + 1) * (lm - 2 * k + 1);
+  return (double)n_nuc * (60.0 + 4.0 * (lm + 1) * (lm + 1) + 2.0 * nw) + 40.0 + 30.0 * nw;
 }
 
 }  // namespace
 
 struct shgo_context {
   int device = 0;
+  int grid = 0;  // workgroups of the persistent kernel resident on the device at once
   double* boys_tab = nullptr;
   std::string err;
 };
@@ -562,15 +679,22 @@ struct shgo_plan {
   int32_t n_shells = 0, n_nuc = 0;
   int64_t nbf = 0, n_cand = 0, out_size = 0, integrals = 0;
   double screen = 0.0;
-  int class_cand[kNumClasses] = {0};  // candidate pairs per class (grid bound)
+  int class_cand[kNumClasses] = {0};  // candidate pairs per class (bounds the sorted counts)
   std::vector<void*> allocs;
   DevBasis bs{};
   DevPairs pr{};
   Nuc* nuc = nullptr;
-  // per-class kernel timing (off when slots == 0)
+  // persistent-kernel workspace
+  ClassMeta meta{};
+  double* vacc = nullptr;
+  int64_t vacc_len = 0;
+  int32_t* tile_cnt = nullptr;  // [n_tiles] tile counters, then the queue head
+  int64_t n_tiles = 0;
+  int32_t* item_off = nullptr;
+  // phase timing (off when slots == 0): events [slot][phase][start, end]
   int32_t slots = 0;
   int64_t exec_count = 0;
-  std::vector<hipEvent_t> events;  // [slots][kNumClasses][2]
+  std::vector<hipEvent_t> events;
 };
 
 namespace {
@@ -708,8 +832,28 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
   e = e != hipSuccess ? e : dalloc(p, &pr.orig, (size_t)p->n_cand);
   e = e != hipSuccess ? e : dalloc(p, &pr.nsurv, (size_t)p->n_cand);
   e = e != hipSuccess ? e : dalloc(p, &pr.key_count, (size_t)kNumKeys);
-  e = e != hipSuccess ? e : dalloc(p, &pr.key_fill, (size_t)kNumKeys);
+  e = e != hipSuccess ? e : dalloc(p, &pr.rank, (size_t)p->n_cand);
   e = e != hipSuccess ? e : dalloc(p, &pr.key_off, (size_t)kNumKeys + 1);
+  // persistent-kernel workspace: tile accumulators sized by the per-class candidate counts,
+  // and the queue order (classes by decreasing cost per tile)
+  {
+    std::vector<std::pair<double, int>> cost;
+    for (int la = 0; la <= SHGO_LMAX; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        const int c = class_id(la, lb);
+        const int64_t tiles = ((int64_t)p->class_cand[c] + kTile - 1) / kTile;
+        p->meta.vacc_base[c] = p->vacc_len;
+        p->meta.tile_base[c] = (int32_t)p->n_tiles;
+        p->vacc_len += tiles * kTile * (2 * la + 1) * (2 * lb + 1);
+        p->n_tiles += tiles;
+        cost.push_back({-class_cost(la, lb, n->n_nuclei), c});
+      }
+    std::stable_sort(cost.begin(), cost.end());
+    for (int k = 0; k < kNumClasses; ++k) p->meta.order[k] = cost[k].second;
+  }
+  e = e != hipSuccess ? e : dalloc(p, &p->vacc, (size_t)p->vacc_len);
+  e = e != hipSuccess ? e : dalloc(p, &p->tile_cnt, (size_t)p->n_tiles + 1);
+  e = e != hipSuccess ? e : dalloc(p, &p->item_off, (size_t)kNumClasses + 1);
   if (e != hipSuccess) {
     shgo_plan_destroy(p);
     return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "device allocation failed");
@@ -784,13 +928,13 @@ shgo_status shgo_create(int device, shgo_context** out) {
     delete c;
     return SHGO_ERR_DEVICE;
   }
-  const ClassTable& ct = class_table();
-  for (int k = 0; k < kNumClasses; ++k)
-    if (ct.prepare[k]() != hipSuccess) {
-      (void)hipFree(c->boys_tab);
-      delete c;
-      return SHGO_ERR_DEVICE;
-    }
+  int n_cu = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrals, 256, 0) != hipSuccess) {
+    shgo_destroy(c);
+    return SHGO_ERR_DEVICE;
+  }
+  c->grid = std::max(1, n_cu * std::max(1, per_cu));
   *out = c;
   return SHGO_OK;
 }
@@ -855,22 +999,27 @@ shgo_status shgo_execute(shgo_plan* p, double* out, void* stream) {
   if (p->n_cand == 0) return SHGO_OK;
   const int tb = 256;
   auto blocks = [&](int64_t n) { return (int)((n + tb - 1) / tb); };
+  const int slot = p->slots > 0 ? (int)(p->exec_count % p->slots) : -1;
+  auto mark = [&](int phase, int edge) {
+    if (slot >= 0) (void)hipEventRecord(p->events[((size_t)slot * SHGO_NUM_PHASES + phase) * 2 + edge], st);
+  };
+  // a1: normalisation, classification, class sort; workspace reset
+  mark(0, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks(kNumKeys)), dim3(tb), 0, st, p->pr.key_count, (int64_t)kNumKeys, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(kNumKeys)), dim3(tb), 0, st, p->pr.key_fill, (int64_t)kNumKeys, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(p->n_tiles + 1)), dim3(tb), 0, st, p->tile_cnt, p->n_tiles + 1, 0);
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks(p->vacc_len)), dim3(tb), 0, st, p->vacc, p->vacc_len);
   if (p->n_shells > 0) hipLaunchKernelGGL(k_prim_weights, dim3(blocks(p->n_shells)), dim3(tb), 0, st, p->bs);
   hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
   hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr);
   hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-  ClassArgs ca{p->bs, p->pr, p->nuc, p->n_nuc, ctx->boys_tab, out};
-  const ClassTable& ct = class_table();
-  const int slot = p->slots > 0 ? (int)(p->exec_count % p->slots) : -1;
-  for (int c = kNumClasses - 1; c >= 0; --c) {
-    const int n = p->class_cand[c];
-    if (n == 0) continue;
-    if (slot >= 0) (void)hipEventRecord(p->events[((size_t)slot * kNumClasses + c) * 2], st);
-    ct.launch[c](ca, (n + 63) / 64, st);
-    if (slot >= 0) (void)hipEventRecord(p->events[((size_t)slot * kNumClasses + c) * 2 + 1], st);
-  }
+  hipLaunchKernelGGL(k_items, dim3(1), dim3(64), 0, st, p->pr, p->meta, p->item_off);
+  mark(0, 1);
+  // a2-a8: one persistent launch over every class
+  WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, ctx->boys_tab, out, p->vacc, p->tile_cnt,
+              p->tile_cnt + p->n_tiles, p->item_off, p->meta};
+  mark(1, 0);
+  hipLaunchKernelGGL(k_integrals, dim3(ctx->grid), dim3(256), 0, st, wa);
+  mark(1, 1);
   p->exec_count++;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -884,7 +1033,7 @@ shgo_status shgo_plan_set_timing(shgo_plan* p, int32_t n_slots) {
   p->events.clear();
   p->slots = 0;
   p->exec_count = 0;
-  std::vector<hipEvent_t> evs((size_t)n_slots * kNumClasses * 2);
+  std::vector<hipEvent_t> evs((size_t)n_slots * SHGO_NUM_PHASES * 2, nullptr);
   for (auto& ev : evs) {
     if (hipEventCreate(&ev) != hipSuccess) {
       for (auto& e2 : evs)
@@ -897,19 +1046,18 @@ shgo_status shgo_plan_set_timing(shgo_plan* p, int32_t n_slots) {
   return SHGO_OK;
 }
 
-shgo_status shgo_plan_class_ms(shgo_plan* p, double* ms, int32_t* count) {
+shgo_status shgo_plan_phase_ms(shgo_plan* p, double* ms, int32_t* count) {
   if (!p || !ms || !count) return SHGO_ERR_INVALID_ARG;
   const int64_t n = std::min<int64_t>(p->exec_count, p->slots);
   *count = (int32_t)n;
-  for (int c = 0; c < kNumClasses; ++c) {
-    ms[c] = 0.0;
-    if (p->class_cand[c] == 0) continue;
-    for (int64_t s = 0; s < n; ++s) {
+  for (int ph = 0; ph < SHGO_NUM_PHASES; ++ph) {
+    ms[ph] = 0.0;
+    for (int64_t sl = 0; sl < n; ++sl) {
       float t = 0.f;
-      if (hipEventElapsedTime(&t, p->events[((size_t)s * kNumClasses + c) * 2], p->events[((size_t)s * kNumClasses + c) * 2 + 1]) !=
-          hipSuccess)
+      const size_t e0 = ((size_t)sl * SHGO_NUM_PHASES + ph) * 2;
+      if (hipEventElapsedTime(&t, p->events[e0], p->events[e0 + 1]) != hipSuccess)
         return fail(p->ctx, SHGO_ERR_DEVICE, "hipEventElapsedTime failed (stream not synchronised?)");
-      ms[c] += t;
+      ms[ph] += t;
     }
   }
   return SHGO_OK;
