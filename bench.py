@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--workload", default="high_l_sweep", choices=["high_l_sweep", "small_molecule", "batched"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run a plain device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -215,6 +217,14 @@ def main():
 
     out = torch.empty(plan.output_size, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    if args.copy_bytes > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the kernel's
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"bench: {args.workload}, {plan.integrals} integrals per step, warmup {args.warmup}, steps {args.steps}")
     for _ in range(args.warmup):
         shgo.shgo_execute(plan, out)
