@@ -17,8 +17,9 @@ For every class (LA, LB) with LA >= LB it emits straight-line HIP code for
 * the rotation back to the laboratory frame, D^l(Q)^T = Z(phi) J^T Z(theta) J with the constant
   matrix J = D^l(rotation by +pi/2 about x) and z rotations Z.
 
-The W entries of one class are split by |M| ("families") into groups that each fit a register
-budget; one wavefront of the kernel runs one group for 64 shell pairs.
+The W entries of one class are split into half-families (the entries with M = +mu, or with
+M = -mu) and packed into groups that each fit a register budget; one wavefront of the kernel
+runs one group for 64 shell pairs.
 
 The tables (real Gaunt coefficients g, the J matrices) are computed here by exact quadrature on
 the unit sphere of polynomials evaluated with the same recurrences the kernel uses. The module
@@ -190,32 +191,50 @@ def family_entries(LA, LB, mu):
     return out
 
 
+def class_units(LA, LB):
+    """Half-families (mu, sign): the entries with M = +mu (cosine type) or M = -mu (sine type).
+    The two halves of a family run independent vertical recurrences, so they can sit in
+    different groups."""
+    return [(0, 1)] + [(mu, sg) for mu in range(1, LA + LB + 1) for sg in (1, -1)]
+
+
+def unit_entries(LA, LB, unit):
+    """Ordered W entries (L, M, k) of a half-family: L ascending, k ascending."""
+    mu, sg = unit
+    return [(L, sg * mu, k) for L in range(mu, LA + LB + 1) for k in range(kmax_of(LA, LB, L) + 1)]
+
+
+def unit_of(M):
+    return (abs(M), 1 if M >= 0 else -1)
+
+
 def class_groups(LA, LB, cap=DEFAULT_CAP):
-    """Partition families 0..LA+LB into groups with at most max(cap, largest family) entries."""
-    fams = list(range(LA + LB + 1))
-    size = {mu: len(family_entries(LA, LB, mu)) for mu in fams}
+    """Partition the half-families into groups of at most max(cap, largest half-family) entries
+    (largest first, each into the least loaded group it fits)."""
+    units = class_units(LA, LB)
+    size = {u: len(unit_entries(LA, LB, u)) for u in units}
     c = max(cap, max(size.values()))
     groups = []
-    for mu in sorted(fams, key=lambda f: (-size[f], f)):
+    for u in sorted(units, key=lambda v: (-size[v], v[0], -v[1])):
         best = None
         for gi, g in enumerate(groups):
-            load = sum(size[f] for f in g)
-            if load + size[mu] <= c and (best is None or load < sum(size[f] for f in groups[best])):
+            load = sum(size[v] for v in g)
+            if load + size[u] <= c and (best is None or load < sum(size[v] for v in groups[best])):
                 best = gi
         if best is None:
-            groups.append([mu])
+            groups.append([u])
         else:
-            groups[best].append(mu)
-    groups = [sorted(g) for g in groups]
-    groups.sort(key=lambda g: -sum(size[f] for f in g))
+            groups[best].append(u)
+    groups = [sorted(g, key=lambda v: (v[0], -v[1])) for g in groups]
+    groups.sort(key=lambda g: -sum(size[v] for v in g))
     return groups
 
 
 def group_index(LA, LB, group):
     """{(L, M, k): position in the group's W array}."""
     idx = {}
-    for mu in group:
-        for e in family_entries(LA, LB, mu):
+    for u in group:
+        for e in unit_entries(LA, LB, u):
             idx[e] = len(idx)
     return idx
 
@@ -347,7 +366,6 @@ def emit_group(LA, LB, gi, group):
     LM = LA + LB
     idx = group_index(LA, LB, group)
     NW = len(idx)
-    mu_max = max(group)
     name = f"G{LA}{LB}_{gi}"
     o = []
     o.append(f"struct {name} {{")
@@ -359,38 +377,30 @@ def emit_group(LA, LB, gi, group):
     o.append("  static __device__ __forceinline__ void step(double (&W)[NW], double x, double y, double z, double r2,")
     o.append(f"                                               double Z, const double (&F)[{LM + 1}], const double (&tj)[{LB + 1}]) {{")
     o.append("    double sc = Z, ss = 0.0;")
-    fams = sorted(group)
     cur_sect = 0
-    for mu in fams:
+    for (mu, sg) in group:
         while cur_sect < mu:
             if cur_sect == 0:
                 o.append("    sc = Z * x; ss = Z * y;")
             else:
                 o.append("    { const double nc = fma(x, sc, -y * ss); ss = fma(y, sc, x * ss); sc = nc; }")
             cur_sect += 1
-        o.append(f"    {{ // family |M| = {mu}")
-        o.append("      double cc = sc, cs = ss, pc = 0.0, ps = 0.0;")
+        q = "sc" if sg > 0 else "ss"
+        o.append(f"    {{ // half-family M = {sg * mu}")
+        o.append(f"      double cq = {q}, pq = 0.0;")
         for L in range(mu, LM + 1):
             if L > mu:
                 if L - 1 == mu:
-                    o.append("      { pc = cc; cc = z * cc; }")
-                    if mu > 0:
-                        o.append("      { ps = cs; cs = z * cs; }")
+                    o.append("      pq = cq; cq = z * cq;")
                 else:
                     e = monic_e(L - 1, mu)
-                    o.append(f"      {{ const double E = {lit(-e)} * r2;")
-                    o.append("        const double nc = fma(z, cc, E * pc); pc = cc; cc = nc;")
-                    if mu > 0:
-                        o.append("        const double ns = fma(z, cs, E * ps); ps = cs; cs = ns;")
-                    o.append("      }")
+                    o.append(f"      {{ const double nq = fma(z, cq, ({lit(-e)} * r2) * pq); pq = cq; cq = nq; }}")
             km = kmax_of(LA, LB, L)
             o.append(f"      {{ double g = F[{L}];")
             for k in range(km + 1):
                 if k > 0:
                     o.append(f"        g = fma(tj[{k}], F[{L + k}], g);")
-                o.append(f"        W[{idx[(L, mu, k)]}] = fma(g, cc, W[{idx[(L, mu, k)]}]);")
-                if mu > 0:
-                    o.append(f"        W[{idx[(L, -mu, k)]}] = fma(g, cs, W[{idx[(L, -mu, k)]}]);")
+                o.append(f"        W[{idx[(L, sg * mu, k)]}] = fma(g, cq, W[{idx[(L, sg * mu, k)]}]);")
             o.append("      }")
         o.append("    }")
     o.append("  }")
@@ -400,7 +410,7 @@ def emit_group(LA, LB, gi, group):
         o.append(f"    W[{i}] *= fk[{k}] * {lit(monic_c(L, abs(M)))};")
     o.append("  }")
     # ---- coupling ----
-    terms = [t for t in class_terms(LA, LB) if abs(t[5]) in group]
+    terms = [t for t in class_terms(LA, LB) if unit_of(t[5]) in group]
     by_mm = {}
     for t in terms:
         by_mm.setdefault((t[0], t[1]), []).append(t)

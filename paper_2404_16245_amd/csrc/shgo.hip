@@ -44,12 +44,27 @@ constexpr int kNumClasses = (SHGO_LMAX + 1) * (SHGO_LMAX + 2) / 2;  // (la, lb) 
 constexpr int kKeysPerClass = 256;
 constexpr int kTile = SHGO_TILE;
 constexpr int kNumKeys = kNumClasses * kKeysPerClass;
+constexpr int kIntegralThreads = 512;  // one workgroup per CU: 2 waves per SIMD share the LDS table
+constexpr int kPrefetchMaxW = 32;      // groups up to this many W doubles prefetch the next nucleus
 
 __host__ __device__ constexpr int class_id(int la, int lb) { return la * (la + 1) / 2 + lb; }
 
 struct alignas(32) Nuc {
   double x, y, z, Z;
 };
+// Nuclei are read through the scalar data cache: the index is the same in every lane, and the
+// constant address space lets the compiler use scalar loads.
+typedef const __attribute__((address_space(4))) Nuc* NucPtr;
+
+// Boys table staged in LDS by every workgroup of the integral kernel (84.6 KB).
+__shared__ double s_boys[kBoysPoints * kBoysOrders];
+
+__device__ __forceinline__ NucPtr uniform_nuclei(const Nuc* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (NucPtr)(((uint64_t)hi << 32) | lo);
+}
 
 struct DevBasis {
   const double* center;    // [n][3]
@@ -329,13 +344,22 @@ struct WorkArgs {
   const Nuc* __restrict__ nuc;
   int32_t n_nuc;
   const double* __restrict__ boys_tab;
-  double* __restrict__ out;
   double* __restrict__ vacc;       // tile accumulators: [tile][NA*NB][SHGO_TILE]
   int32_t* __restrict__ tile_cnt;  // groups finished per tile
   int32_t* __restrict__ queue;     // [0]: next work item
   int32_t* __restrict__ item_off;  // [kNumClasses + 1]: prefix of items per class in queue order
   ClassMeta meta;
 };
+// The work arguments live in device memory (one copy per plan) and are read through the scalar
+// data cache: every lane of a wavefront reads the same fields.
+typedef const __attribute__((address_space(4))) WorkArgs* WAP;
+
+__device__ __forceinline__ WAP uniform_args(const WorkArgs* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (WAP)(((uint64_t)hi << 32) | lo);
+}
 
 // Per-lane shell-pair state.
 struct PairState {
@@ -371,7 +395,7 @@ __device__ __forceinline__ void frame_of(PairState& ps) {
 }
 
 // Advance (i, j) to the next primitive pair that survives screening; false when exhausted.
-__device__ __forceinline__ bool next_prim(const PairState& ps, const WorkArgs& wa, int& i, int& j) {
+__device__ __forceinline__ bool next_prim(const PairState& ps, WAP wa, int& i, int& j) {
   const double R2 = ps.R * ps.R;
   while (true) {
     ++j;
@@ -380,12 +404,12 @@ __device__ __forceinline__ bool next_prim(const PairState& ps, const WorkArgs& w
       ++i;
     }
     if (i >= ps.K1) return false;
-    if (keep_prim(wa.bs.expo[ps.o1 + i], wa.bs.expo[ps.o2 + j], R2, wa.pr.screen)) return true;
+    if (keep_prim(wa->bs.expo[ps.o1 + i], wa->bs.expo[ps.o2 + j], R2, wa->pr.screen)) return true;
   }
 }
 
 template <int LA, int LB, int G>
-__device__ __forceinline__ void run_group(const PairState& ps, const WorkArgs& wa, int wave_iters,
+__device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_iters,
                                           double* __restrict__ Vp) {
   using Grp = GroupOf<LA, LB, G>;
   constexpr int LM = LA + LB;
@@ -393,7 +417,7 @@ __device__ __forceinline__ void run_group(const PairState& ps, const WorkArgs& w
   for (int it = 0; it < wave_iters; ++it) {
     const bool have = ps.active && next_prim(ps, wa, pi, pj);
     if (have) {
-      const double a = wa.bs.expo[ps.o1 + pi], b = wa.bs.expo[ps.o2 + pj];
+      const double a = wa->bs.expo[ps.o1 + pi], b = wa->bs.expo[ps.o2 + pj];
       const double p = a + b, ip = 1.0 / p;
       const double Px = (a * ps.A[0] + b * ps.B[0]) * ip;
       const double Py = (a * ps.A[1] + b * ps.B[1]) * ip;
@@ -401,31 +425,25 @@ __device__ __forceinline__ void run_group(const PairState& ps, const WorkArgs& w
       double W[Grp::NW];
 #pragma unroll
       for (int q = 0; q < Grp::NW; ++q) W[q] = 0.0;
-      // nucleus loop, software-pipelined: the geometry and Boys-table row of nucleus c+1 are
-      // fetched while nucleus c is processed
+      // nucleus loop: geometry in the pair frame, Boys row from LDS, then the group's step
       double nx = 0.0, ny = 0.0, nz = 0.0, nr2 = 0.0, nt = 0.0, nZ = 0.0, nrow[8];
+      const NucPtr nucs = uniform_nuclei(wa->nuc);
+      const int n_nuc = __builtin_amdgcn_readfirstlane(wa->n_nuc);
       auto geometry = [&](int c) {
-        const Nuc n = wa.nuc[c];
-        const double cx = n.x - Px, cy = n.y - Py, cz = n.z - Pz;
+        const double cx = nucs[c].x - Px, cy = nucs[c].y - Py, cz = nucs[c].z - Pz;
         const double u = fma(ps.cp, cx, ps.sp * cy);
         nx = fma(ps.ct, u, -ps.st * cz);
         ny = fma(-ps.sp, cx, ps.cp * cy);
         nz = fma(ps.st, u, ps.ct * cz);
         nr2 = fma(cx, cx, fma(cy, cy, cz * cz));
         nt = p * nr2;
-        nZ = n.Z;
+        nZ = nucs[c].Z;
         const int i = min((int)(nt * 16.0 + 0.5), kBoysPoints - 1);
-        const double* __restrict__ r = wa.boys_tab + i * kBoysOrders + LM;
+        const double* __restrict__ r = s_boys + i * kBoysOrders + LM;
 #pragma unroll
         for (int k = 0; k < 8; ++k) nrow[k] = r[k];
       };
-      if (wa.n_nuc > 0) geometry(0);
-      for (int c = 0; c < wa.n_nuc; ++c) {
-        const double x = nx, y = ny, z = nz, r2 = nr2, t = nt, Zc = nZ;
-        double row[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) row[k] = nrow[k];
-        if (c + 1 < wa.n_nuc) geometry(c + 1);
+      auto nucleus = [&](double x, double y, double z, double r2, double t, double Zc, const double (&row)[8]) {
         const double e = exp(-t);
         double F[LM + 1];
         boys_row<LM>(t, e, row, F);
@@ -434,10 +452,27 @@ __device__ __forceinline__ void run_group(const PairState& ps, const WorkArgs& w
 #pragma unroll
         for (int k = 1; k <= LB; ++k) tj[k] = tj[k - 1] * t * (1.0 / k);
         Grp::step(W, x, y, z, r2, Zc, F, tj);
+      };
+      if constexpr (Grp::NW <= kPrefetchMaxW) {
+        // small groups have registers to spare: the next nucleus is fetched one step ahead
+        if (n_nuc > 0) geometry(0);
+        for (int c = 0; c < n_nuc; ++c) {
+          const double x = nx, y = ny, z = nz, r2 = nr2, t = nt, Zc = nZ;
+          double row[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) row[k] = nrow[k];
+          if (c + 1 < n_nuc) geometry(c + 1);
+          nucleus(x, y, z, r2, t, Zc, row);
+        }
+      } else {
+        for (int c = 0; c < n_nuc; ++c) {
+          geometry(c);
+          nucleus(nx, ny, nz, nr2, nt, nZ, nrow);
+        }
       }
       // prefactor -w_a w_b exp(-mu R^2) and 2 pi k!/p^{k+1}
       const double K = exp(-a * b * ip * ps.R * ps.R);
-      const double pre = -wa.bs.w[ps.o1 + pi] * wa.bs.w[ps.o2 + pj] * K;
+      const double pre = -wa->bs.w[ps.o1 + pi] * wa->bs.w[ps.o2 + pj] * K;
       double fk[LB + 1];
       fk[0] = pre * 6.283185307179586477 * ip;
 #pragma unroll
@@ -457,7 +492,7 @@ __device__ __forceinline__ void run_group(const PairState& ps, const WorkArgs& w
 }
 
 template <int LA, int LB, int G>
-__device__ __forceinline__ void dispatch_group(int g, const PairState& ps, const WorkArgs& wa, int wave_iters,
+__device__ __forceinline__ void dispatch_group(int g, const PairState& ps, WAP wa, int wave_iters,
                                                double* Vp) {
   if constexpr (G < ClassInfo<LA, LB>::Q) {
     if (g == G) {
@@ -482,7 +517,8 @@ __device__ __forceinline__ void angles(double c1, double s1, double (&c)[L + 1],
 // Rotate the accumulated blocks of a tile back to the laboratory frame
 // (V = D_a^T V' D_b, D^T = Z(phi) J^T Z(theta) J; rows in place, then columns) and write them.
 template <int LA, int LB>
-__device__ __forceinline__ void finish_tile(const PairState& ps, const WorkArgs& wa, int slot, double* Vp) {
+__device__ __forceinline__ void finish_tile(const PairState& ps, WAP wa, double* __restrict__ out, int slot,
+                                            double* Vp) {
   constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1;
   double cth[LA + 1], sth[LA + 1], cph[LA + 1], sph[LA + 1];
   angles<LA>(ps.ct, ps.st, cth, sth);
@@ -503,34 +539,34 @@ __device__ __forceinline__ void finish_tile(const PairState& ps, const WorkArgs&
     for (int i = 0; i < NA; ++i) v[i] = Vp[(i * NB + col) * kTile];
     Rot<LA>::apply(v, cth, sth, cph, sph);
     if (!ps.active) continue;
-    if (wa.pr.full) {
-      const int64_t r0 = wa.bs.bf_off[ps.s1], c0 = wa.bs.bf_off[ps.s2], n = wa.bs.nbf;
+    if (wa->pr.full) {
+      const int64_t r0 = wa->bs.bf_off[ps.s1], c0 = wa->bs.bf_off[ps.s2], n = wa->bs.nbf;
       if (ps.s1 != ps.s2) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-          wa.out[(r0 + i) * n + c0 + col] = v[i];
-          wa.out[(c0 + col) * n + r0 + i] = v[i];
+          out[(r0 + i) * n + c0 + col] = v[i];
+          out[(c0 + col) * n + r0 + i] = v[i];
         }
       } else {
         // diagonal block: the upper triangle is mirrored so that V is exactly symmetric
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
           if (i <= col) {
-            wa.out[(r0 + i) * n + c0 + col] = v[i];
-            wa.out[(c0 + col) * n + r0 + i] = v[i];
+            out[(r0 + i) * n + c0 + col] = v[i];
+            out[(c0 + col) * n + r0 + i] = v[i];
           }
         }
       }
     } else {
-      const int o = wa.pr.orig[slot];
-      const int64_t bo = wa.pr.blk_off[o];
-      const bool sw = wa.pr.pa[o] != ps.s1;
+      const int o = wa->pr.orig[slot];
+      const int64_t bo = wa->pr.blk_off[o];
+      const bool sw = wa->pr.pa[o] != ps.s1;
 #pragma unroll
       for (int i = 0; i < NA; ++i) {
         if (sw)
-          wa.out[bo + (int64_t)col * NA + i] = v[i];
+          out[bo + (int64_t)col * NA + i] = v[i];
         else
-          wa.out[bo + (int64_t)i * NB + col] = v[i];
+          out[bo + (int64_t)i * NB + col] = v[i];
       }
     }
   }
@@ -539,31 +575,32 @@ __device__ __forceinline__ void finish_tile(const PairState& ps, const WorkArgs&
 // One work item of class (LA, LB): tile j / Q, group j % Q. Kept out of line so that every
 // class is compiled and register-allocated on its own.
 template <int LA, int LB>
-__device__ __attribute__((noinline)) void process_item(int j, const WorkArgs& wa) {
+__device__ __attribute__((noinline)) void process_item(int j, const WorkArgs* wa_ptr, double* __restrict__ out) {
+  const WAP wa = uniform_args(wa_ptr);
   constexpr int Q = ClassInfo<LA, LB>::Q;
   constexpr int NAB = (2 * LA + 1) * (2 * LB + 1);
   constexpr int cls = class_id(LA, LB);
   const int lane = threadIdx.x & 63;
   const int tile = j / Q, g = j - tile * Q;
-  const int start = wa.pr.key_off[cls * kKeysPerClass];
-  const int end = wa.pr.key_off[(cls + 1) * kKeysPerClass];
+  const int start = wa->pr.key_off[cls * kKeysPerClass];
+  const int end = wa->pr.key_off[(cls + 1) * kKeysPerClass];
   const int slot = start + tile * kTile + lane;
 
   PairState ps;
   ps.active = slot < end;
   const int sl = ps.active ? slot : end - 1;
-  ps.s1 = wa.pr.s1[sl];
-  ps.s2 = wa.pr.s2[sl];
-  ps.nsurv = ps.active ? wa.pr.nsurv[sl] : 0;
+  ps.s1 = wa->pr.s1[sl];
+  ps.s2 = wa->pr.s2[sl];
+  ps.nsurv = ps.active ? wa->pr.nsurv[sl] : 0;
 #pragma unroll
   for (int x = 0; x < 3; ++x) {
-    ps.A[x] = wa.bs.center[3 * ps.s1 + x];
-    ps.B[x] = wa.bs.center[3 * ps.s2 + x];
+    ps.A[x] = wa->bs.center[3 * ps.s1 + x];
+    ps.B[x] = wa->bs.center[3 * ps.s2 + x];
   }
-  ps.o1 = wa.bs.prim_off[ps.s1];
-  ps.o2 = wa.bs.prim_off[ps.s2];
-  ps.K1 = wa.bs.nprim[ps.s1];
-  ps.K2 = wa.bs.nprim[ps.s2];
+  ps.o1 = wa->bs.prim_off[ps.s1];
+  ps.o2 = wa->bs.prim_off[ps.s2];
+  ps.K1 = wa->bs.nprim[ps.s1];
+  ps.K2 = wa->bs.nprim[ps.s2];
   frame_of(ps);
   // primitive-pair iterations of this wavefront (keys saturate at 255; then every candidate
   // primitive pair is visited and the screened ones skipped)
@@ -571,32 +608,32 @@ __device__ __attribute__((noinline)) void process_item(int j, const WorkArgs& wa
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) iters = max(iters, __shfl_xor(iters, off));
 
-  double* Vp = wa.vacc + wa.meta.vacc_base[cls] + (int64_t)tile * NAB * kTile + lane;
+  double* Vp = wa->vacc + wa->meta.vacc_base[cls] + (int64_t)tile * NAB * kTile + lane;
   dispatch_group<LA, LB, 0>(g, ps, wa, iters, Vp);
 
   // completion: release this group's atomic adds, count it, and let the last group finish
   int done = 0;
   if (lane == 0)
-    done = __hip_atomic_fetch_add(wa.tile_cnt + wa.meta.tile_base[cls] + tile, 1, __ATOMIC_ACQ_REL,
+    done = __hip_atomic_fetch_add(wa->tile_cnt + wa->meta.tile_base[cls] + tile, 1, __ATOMIC_ACQ_REL,
                                   __HIP_MEMORY_SCOPE_AGENT);
   done = __shfl(done, 0);
   if (done == Q - 1) {
     __threadfence();
-    finish_tile<LA, LB>(ps, wa, slot, Vp);
+    finish_tile<LA, LB>(ps, wa, out, slot, Vp);
   }
 }
 
 template <int LA, int LB>
-__device__ __forceinline__ void dispatch_class(int c, int j, const WorkArgs& wa) {
+__device__ __forceinline__ void dispatch_class(int c, int j, const WorkArgs* wa, double* out) {
   if constexpr (LA <= SHGO_LMAX) {
     if (c == class_id(LA, LB)) {
-      process_item<LA, LB>(j, wa);
+      process_item<LA, LB>(j, wa, out);
       return;
     }
     if constexpr (LB < LA)
-      dispatch_class<LA, LB + 1>(c, j, wa);
+      dispatch_class<LA, LB + 1>(c, j, wa, out);
     else
-      dispatch_class<LA + 1, 0>(c, j, wa);
+      dispatch_class<LA + 1, 0>(c, j, wa, out);
   }
 }
 
@@ -614,17 +651,21 @@ __global__ void k_items(DevPairs pr, ClassMeta meta, int32_t* item_off) {
 }
 
 // Every wavefront loops: take the next item, run it; the loop ends once the queue is drained.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_integrals(WorkArgs wa) {
+__global__ void __launch_bounds__(kIntegralThreads) __attribute__((amdgpu_waves_per_eu(2)))
+k_integrals(const WorkArgs* __restrict__ wa_ptr, double* __restrict__ out) {
+  const WAP wa = uniform_args(wa_ptr);
+  for (int i = threadIdx.x; i < kBoysPoints * kBoysOrders; i += blockDim.x) s_boys[i] = wa->boys_tab[i];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int total = wa.item_off[kNumClasses];
+  const int total = wa->item_off[kNumClasses];
   while (true) {
     int item = 0;
-    if (lane == 0) item = atomicAdd(wa.queue, 1);
+    if (lane == 0) item = atomicAdd(wa->queue, 1);
     item = __shfl(item, 0);
     if (item >= total) break;
     int k = 0;
-    while (wa.item_off[k + 1] <= item) ++k;
-    dispatch_class<0, 0>(wa.meta.order[k], item - wa.item_off[k], wa);
+    while (wa->item_off[k + 1] <= item) ++k;
+    dispatch_class<0, 0>(wa->meta.order[k], item - wa->item_off[k], wa_ptr, out);
   }
 }
 
@@ -691,6 +732,7 @@ struct shgo_plan {
   int32_t* tile_cnt = nullptr;  // [n_tiles] tile counters, then the queue head
   int64_t n_tiles = 0;
   int32_t* item_off = nullptr;
+  WorkArgs* d_wa = nullptr;  // the integral kernel's arguments, in device memory
   // phase timing (off when slots == 0): events [slot][phase][start, end]
   int32_t slots = 0;
   int64_t exec_count = 0;
@@ -854,6 +896,7 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
   e = e != hipSuccess ? e : dalloc(p, &p->vacc, (size_t)p->vacc_len);
   e = e != hipSuccess ? e : dalloc(p, &p->tile_cnt, (size_t)p->n_tiles + 1);
   e = e != hipSuccess ? e : dalloc(p, &p->item_off, (size_t)kNumClasses + 1);
+  e = e != hipSuccess ? e : dalloc(p, &p->d_wa, 1);
   if (e != hipSuccess) {
     shgo_plan_destroy(p);
     return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "device allocation failed");
@@ -887,6 +930,13 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
   pr.pa = dpa;
   pr.pb = dpb;
   pr.blk_off = dblk;
+  const WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, ctx->boys_tab, p->vacc, p->tile_cnt,
+                    p->tile_cnt + p->n_tiles, p->item_off, p->meta};
+  e = hipMemcpy(p->d_wa, &wa, sizeof(WorkArgs), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    shgo_plan_destroy(p);
+    return fail(ctx, SHGO_ERR_DEVICE, std::string("upload failed: ") + hipGetErrorString(e));
+  }
   *out = p;
   return SHGO_OK;
 }
@@ -930,7 +980,7 @@ shgo_status shgo_create(int device, shgo_context** out) {
   }
   int n_cu = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrals, 256, 0) != hipSuccess) {
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrals, kIntegralThreads, 0) != hipSuccess) {
     shgo_destroy(c);
     return SHGO_ERR_DEVICE;
   }
@@ -1015,10 +1065,8 @@ shgo_status shgo_execute(shgo_plan* p, double* out, void* stream) {
   hipLaunchKernelGGL(k_items, dim3(1), dim3(64), 0, st, p->pr, p->meta, p->item_off);
   mark(0, 1);
   // a2-a8: one persistent launch over every class
-  WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, ctx->boys_tab, out, p->vacc, p->tile_cnt,
-              p->tile_cnt + p->n_tiles, p->item_off, p->meta};
   mark(1, 0);
-  hipLaunchKernelGGL(k_integrals, dim3(ctx->grid), dim3(256), 0, st, wa);
+  hipLaunchKernelGGL(k_integrals, dim3(ctx->grid), dim3(kIntegralThreads), 0, st, (const WorkArgs*)p->d_wa, out);
   mark(1, 1);
   p->exec_count++;
   hipError_t e = hipGetLastError();

@@ -109,10 +109,14 @@ def test_groups_partition_families():
     for LA in range(7):
         for LB in range(LA + 1):
             groups = gc.class_groups(LA, LB)
-            fams = sorted(f for g in groups for f in g)
-            assert fams == list(range(LA + LB + 1))
-            cap = max(gc.DEFAULT_CAP, max(len(gc.family_entries(LA, LB, f)) for f in fams))
-            assert all(sum(len(gc.family_entries(LA, LB, f)) for f in g) <= cap for g in groups)
+            units = sorted(u for g in groups for u in g)
+            assert units == sorted(gc.class_units(LA, LB))
+            cap = max(gc.DEFAULT_CAP, max(len(gc.unit_entries(LA, LB, u)) for u in units))
+            assert all(sum(len(gc.unit_entries(LA, LB, u)) for u in g) <= cap for g in groups)
+            # the half-families together hold every W entry of every |M| family exactly once
+            ent = sorted(e for g in groups for u in g for e in gc.unit_entries(LA, LB, u))
+            ref = sorted(e for mu in range(LA + LB + 1) for e in gc.family_entries(LA, LB, mu))
+            assert ent == ref
 
 
 CLASSES = [(la, lb) for la in range(7) for lb in range(la + 1)]
