@@ -410,36 +410,57 @@ def emit_group(LA, LB, gi, group):
         o.append(f"    W[{i}] *= fk[{k}] * {lit(monic_c(L, abs(M)))};")
     o.append("  }")
     # ---- coupling ----
+    # Outputs are visited in blocks of equal (|ma|, |mb|): inside a block the sign variants
+    # (ma, mb) = (+-|ma|, +-|mb|) share their coefficients up to sign, so their terms are
+    # interleaved by coefficient magnitude and each materialised constant serves several FMAs.
     terms = [t for t in class_terms(LA, LB) if unit_of(t[5]) in group]
-    by_mm = {}
-    for t in terms:
-        by_mm.setdefault((t[0], t[1]), []).append(t)
     NB = 2 * LB + 1
+    blocks = {}
+    for t in terms:
+        blocks.setdefault((abs(t[0]), abs(t[1])), []).append(t)
     o.append(f"  static __device__ __forceinline__ void couple(const double (&W)[NW], const double (&ta)[{LA + 1}],")
     o.append(f"                                                 const double (&tb)[{LB + 1}], double* __restrict__ Vp) {{")
     o.append("    // Vp: this lane's entry (0, 0) of the tile accumulator; entries are SHGO_TILE apart")
-    for (ma, mb), ts in sorted(by_mm.items()):
-        o.append(f"    {{ // (ma, mb) = ({ma}, {mb})")
-        o.append("      double v = 0.0;")
-        by_l1 = {}
-        for t in ts:
-            by_l1.setdefault(t[2], {}).setdefault(t[3], []).append(t)
-        for l1, d2 in sorted(by_l1.items()):
-            o.append("      { double u = 0.0;")
-            for l2, tl in sorted(d2.items()):
-                expr = None
-                for t in tl:
+    for (aa, ab), ts in sorted(blocks.items()):
+        outs = sorted(set((t[0], t[1]) for t in ts))
+        name = {mm: f"v{i}" for i, mm in enumerate(outs)}
+        o.append(f"    {{ // |ma| = {aa}, |mb| = {ab}")
+        o.append("      double " + ", ".join(f"{name[mm]} = 0.0" for mm in outs) + ";")
+        for l1 in sorted(set(t[2] for t in ts)):
+            t1 = [t for t in ts if t[2] == l1]
+            o1 = sorted(set((t[0], t[1]) for t in t1))
+            o.append("      { double " + ", ".join(f"u{name[mm][1:]} = 0.0" for mm in o1) + ";")
+            for l2 in sorted(set(t[3] for t in t1)):
+                t2 = [t for t in t1 if t[3] == l2]
+                o2 = sorted(set((t[0], t[1]) for t in t2))
+                first = {mm: True for mm in o2}
+                lines = []
+                for t in sorted(t2, key=lambda t: (abs(t[7]), t[7] < 0, t[0], t[1], t[4], t[5])):
+                    mm = (t[0], t[1])
+                    e = f"e{name[mm][1:]}"
                     wi = idx[(t[4], t[5], t[6])]
-                    expr = f"{lit(t[7])} * W[{wi}]" if expr is None else f"fma({lit(t[7])}, W[{wi}], {expr})"
-                if LB - l2 == 0:
-                    o.append(f"        u += {expr};")
+                    if first[mm]:
+                        lines.append(f"double {e} = {lit(t[7])} * W[{wi}];")
+                        first[mm] = False
+                    else:
+                        lines.append(f"{e} = fma({lit(t[7])}, W[{wi}], {e});")
+                o.append("        { " + " ".join(lines))
+                for mm in o2:
+                    k = name[mm][1:]
+                    if LB - l2 == 0:
+                        o.append(f"          u{k} += e{k};")
+                    else:
+                        o.append(f"          u{k} = fma(tb[{LB - l2}], e{k}, u{k});")
+                o.append("        }")
+            for mm in o1:
+                k = name[mm][1:]
+                if LA - l1 == 0:
+                    o.append(f"        {name[mm]} += u{k};")
                 else:
-                    o.append(f"        u = fma(tb[{LB - l2}], {expr}, u);")
-            if LA - l1 == 0:
-                o.append("        v += u; }")
-            else:
-                o.append(f"        v = fma(ta[{LA - l1}], u, v); }}")
-        o.append(f"      atomicAdd(Vp + {(ma + LA) * NB + (mb + LB)} * SHGO_TILE, v);")
+                    o.append(f"        {name[mm]} = fma(ta[{LA - l1}], u{k}, {name[mm]});")
+            o.append("      }")
+        for mm in outs:
+            o.append(f"      atomicAdd(Vp + {(mm[0] + LA) * NB + (mm[1] + LB)} * SHGO_TILE, {name[mm]});")
         o.append("    }")
     o.append("  }")
     o.append("};")
