@@ -43,10 +43,8 @@ def _load():
         lib.oracle_blocks.restype = ctypes.c_int
         lib.oracle_matrix.argtypes = [ctypes.c_int] + basis_args + [ctypes.c_int, _d, _d, ctypes.c_double, _d, ctypes.c_int]
         lib.oracle_matrix.restype = ctypes.c_int
-        if hasattr(lib, "oracle_grad"):
-            lib.oracle_grad.argtypes = ([ctypes.c_int] + basis_args[1:] + [ctypes.c_int, _d, _d, ctypes.c_double, _d, _d, _d,
-                                                                          ctypes.c_int])
-            lib.oracle_grad.restype = ctypes.c_int
+        lib.oracle_grad.argtypes = (basis_args + [ctypes.c_int, _d, _d, ctypes.c_double, _d, _d, _d, _d, ctypes.c_int])
+        lib.oracle_grad.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -162,6 +160,25 @@ def nuc_matrix(basis, nuclei, screen=0.0, precision=0, nthreads=0):
     if rc:
         raise ValueError("oracle: invalid basis")
     return V
+
+
+def grad(basis, nuclei, D, screen=0.0, nthreads=0):
+    """Analytic gradient of E = sum_ij D_ij V_ij by dual numbers.
+
+    Returns (dE/d nuclear positions [n_nuc, 3], dE/d shell centers [n_shells, 3], E)."""
+    nbf = basis.nbf()
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    assert D.shape == (nbf, nbf)
+    dn = np.zeros((nuclei.n, 3))
+    dc = np.zeros((basis.n_shells, 3))
+    e = np.zeros(1)
+    keep, bargs = _basis_args(basis)
+    nkeep, nargs = _nuc_args(nuclei)
+    rc = _load().oracle_grad(*bargs, *nargs, float(screen), _p(D, _d), _p(dn, _d), _p(dc, _d), _p(e, _d),
+                             int(nthreads))
+    if rc:
+        raise ValueError("oracle: invalid basis")
+    return dn, dc, float(e[0])
 
 
 def split_blocks(flat, basis, pa, pb):

@@ -544,6 +544,84 @@ int run_blocks(const Basis& bs, int n_nuc, const double* nuc_pos, const double* 
   return 0;
 }
 
+// Gradient of E = sum_ij D_ij V_ij (V the full symmetric matrix) with respect to the nuclear
+// positions and the shell centers, by forward-mode dual numbers (Eq. 11 differentiated through
+// every step of the route, Boys included via dF_m/dT = -F_{m+1}). For each shell pair a <= b the
+// pair's energy is sum D~ V_ab with D~ = D_ab + D_ba^T (a != b) or D_aa (a = b); each center
+// coordinate is seeded in its own evaluation of the whole block, each nuclear coordinate in an
+// evaluation of that nucleus's term only. The screening decision uses the plain values, so the
+// surviving primitive pairs stay those of the reference geometry.
+int grad_pairs(const Basis& bs, int n_nuc, const double* nuc_pos, const double* nuc_Z, const double* D, double screen,
+               double* dnuc, double* dcen, double* energy, int nthreads) {
+  int lmax = 0;
+  for (int s = 0; s < bs.n_shells; ++s) lmax = std::max(lmax, (int)bs.l[s]);
+  Coupling<Dual> cp(lmax);
+  std::vector<int64_t> so(bs.n_shells + 1, 0);
+  for (int s = 0; s < bs.n_shells; ++s) so[s + 1] = so[s] + 2 * bs.l[s] + 1;
+  const int64_t nbf = so[bs.n_shells];
+  std::vector<int32_t> pa, pb;
+  for (int a = 0; a < bs.n_shells; ++a)
+    for (int b = a; b < bs.n_shells; ++b) {
+      pa.push_back(a);
+      pb.push_back(b);
+    }
+  std::vector<Dual> npos(3 * n_nuc), nz(n_nuc);
+  for (int i = 0; i < 3 * n_nuc; ++i) npos[i] = Dual(nuc_pos[i]);
+  for (int i = 0; i < n_nuc; ++i) nz[i] = Dual(nuc_Z[i]);
+  for (int i = 0; i < 3 * n_nuc; ++i) dnuc[i] = 0.0;
+  for (int i = 0; i < 3 * bs.n_shells; ++i) dcen[i] = 0.0;
+  double e_tot = 0.0;
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+  {
+    std::vector<double> dn(3 * n_nuc, 0.0), dc(3 * bs.n_shells, 0.0);
+    double e_loc = 0.0;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t i = 0; i < (int64_t)pa.size(); ++i) {
+      const int a = pa[i], b = pb[i];
+      const int da = 2 * bs.l[a] + 1, db = 2 * bs.l[b] + 1;
+      std::vector<double> Dt(da * db);
+      for (int x = 0; x < da; ++x)
+        for (int y = 0; y < db; ++y)
+          Dt[x * db + y] = D[(so[a] + x) * nbf + so[b] + y] + (a != b ? D[(so[b] + y) * nbf + so[a] + x] : 0.0);
+      const ShellT<Dual> sa = make_shell<Dual>(bs, a, nullptr), sb = make_shell<Dual>(bs, b, nullptr);
+      std::vector<Dual> blk(da * db);
+      auto pair_energy = [&](const ShellT<Dual>& A, const ShellT<Dual>& B, int nn, const Dual* pos, const Dual* Z) {
+        shell_block<Dual>(A, B, nn, pos, Z, false, screen, cp, blk.data());
+        Dual e;
+        for (int j = 0; j < da * db; ++j) e = e + Dual(Dt[j]) * blk[j];
+        return e;
+      };
+      e_loc += pair_energy(sa, sb, n_nuc, npos.data(), nz.data()).v;
+      for (int x = 0; x < 3; ++x) {
+        ShellT<Dual> sa2 = sa, sb2 = sb;
+        sa2.A[x].d = 1.0;
+        if (a == b) sb2.A[x].d = 1.0;  // one shell: its center appears on both sides
+        dc[3 * a + x] += pair_energy(sa2, sb2, n_nuc, npos.data(), nz.data()).d;
+        if (a != b) {
+          ShellT<Dual> sa3 = sa, sb3 = sb;
+          sb3.A[x].d = 1.0;
+          dc[3 * b + x] += pair_energy(sa3, sb3, n_nuc, npos.data(), nz.data()).d;
+        }
+      }
+      for (int c = 0; c < n_nuc; ++c)
+        for (int x = 0; x < 3; ++x) {
+          Dual pc[3] = {npos[3 * c], npos[3 * c + 1], npos[3 * c + 2]};
+          pc[x].d = 1.0;
+          dn[3 * c + x] += pair_energy(sa, sb, 1, pc, &nz[c]).d;
+        }
+    }
+#pragma omp critical
+    {
+      for (int j = 0; j < 3 * n_nuc; ++j) dnuc[j] += dn[j];
+      for (int j = 0; j < 3 * bs.n_shells; ++j) dcen[j] += dc[j];
+      e_tot += e_loc;
+    }
+  }
+  if (energy) *energy = e_tot;
+  return 0;
+}
+
 int check_basis(const Basis& bs) {
   for (int s = 0; s < bs.n_shells; ++s) {
     if (bs.l[s] < 0 || bs.l[s] > 8 || bs.nprim[s] < 1) return 1;
@@ -678,6 +756,16 @@ int oracle_matrix(int precision, int n_shells, const double* center, const int32
       }
   }
   return 0;
+}
+
+// dE/d(nuclear positions) [n_nuc][3], dE/d(shell centers) [n_shells][3] and E itself for
+// E = sum_ij D_ij V_ij, D an nbf x nbf row-major matrix. Returns 0, or 1 on an invalid basis.
+int oracle_grad(int n_shells, const double* center, const int32_t* l, const int32_t* nprim, const int64_t* prim_off,
+                const double* expo, const double* coef, int n_nuc, const double* nuc_pos, const double* nuc_Z,
+                double screen, const double* D, double* dnuc, double* dcen, double* energy, int nthreads) {
+  Basis bs{n_shells, center, l, nprim, prim_off, expo, coef};
+  if (check_basis(bs)) return 1;
+  return grad_pairs(bs, n_nuc, nuc_pos, nuc_Z, D, screen, dnuc, dcen, energy, nthreads);
 }
 
 }  // extern "C"

@@ -160,16 +160,6 @@ def test_blocks_against_quadrature(la, lb):
     assert np.allclose(V, ref, rtol=1e-10, atol=1e-12)
 
 
-def real_wigner_d(l, Q):
-    """D^l with S^l(Q x) = D^l S^l(x), by least squares over random points."""
-    rng = np.random.default_rng(77 + l)
-    X = rng.normal(size=(4 * (2 * l + 1) + 5, 3))
-    Sx = np.array([xcheck.eval_real_solid(l, *x) for x in X])
-    SQx = np.array([xcheck.eval_real_solid(l, *(Q @ x)) for x in X])
-    Dt, *_ = np.linalg.lstsq(Sx, SQx, rcond=None)
-    return Dt.T
-
-
 def test_rotation_covariance():
     bs, nuc = synth.molecule(seed=31, n_atoms=3, box=3.0, ls=(0, 1, 2, 3, 4, 5, 6), kmax=2)
     Q = synth.random_rotation(5)
@@ -180,7 +170,7 @@ def test_rotation_covariance():
     pa, pb = pa[sel], pb[sel]
     B0 = oracle.split_blocks(oracle.nuc_blocks(bs, nuc, pa, pb), bs, pa, pb)
     B1 = oracle.split_blocks(oracle.nuc_blocks(rot, nuc_r, pa, pb), bs, pa, pb)
-    D = [real_wigner_d(l, Q) for l in range(7)]
+    D = [xcheck.real_wigner_d(l, Q) for l in range(7)]
     for i in range(len(pa)):
         la, lb = bs.l[pa[i]], bs.l[pb[i]]
         ref = D[la] @ B0[i] @ D[lb].T

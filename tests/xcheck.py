@@ -284,3 +284,13 @@ def contracted_block(route, basis, nuclei, sa, sb):
             for c, Z in zip(nuclei.pos, nuclei.Z):
                 out -= Z * wa[i] * wb[j] * route(la, A, a, lb, B, b, c)
     return out
+
+
+def real_wigner_d(l, Q):
+    """D^l with S^l(Q x) = D^l S^l(x), by least squares over random points."""
+    rng = np.random.default_rng(77 + l)
+    X = rng.normal(size=(4 * (2 * l + 1) + 5, 3))
+    Sx = np.array([eval_real_solid(l, *x) for x in X])
+    SQx = np.array([eval_real_solid(l, *(Q @ x)) for x in X])
+    Dt, *_ = np.linalg.lstsq(Sx, SQx, rcond=None)
+    return Dt.T
