@@ -86,6 +86,55 @@ def solid_real(lmax, pts):
     return S
 
 
+def solid_real_grad(lmax, pts):
+    """Real solid harmonics and their Cartesian gradients by forward-mode differentiation of the
+    same recurrences: returns S (N, n) and dS (3, N, n), n = (lmax+1)^2, in the dtype of pts."""
+    pts = np.atleast_2d(pts)
+    dt = pts.dtype
+    N = pts.shape[0]
+    x, y, z = pts[:, 0], pts[:, 1], pts[:, 2]
+    r2 = x * x + y * y + z * z
+    one, zero = np.ones(N, dtype=dt), np.zeros(N, dtype=dt)
+    dx = [one, zero, zero]
+    dy = [zero, one, zero]
+    dz = [zero, zero, one]
+    dr2 = [2 * x, 2 * y, 2 * z]
+    S = np.zeros((N, (lmax + 1) ** 2), dtype=dt)
+    dS = np.zeros((3, N, (lmax + 1) ** 2), dtype=dt)
+    idx = lambda l, m: l * l + m + l
+    S[:, 0] = 1.0
+    sc, ss = one.copy(), zero.copy()
+    dsc, dss = [zero.copy() for _ in range(3)], [zero.copy() for _ in range(3)]
+    for l in range(lmax):
+        f = dt.type(1) if l == 0 else np.sqrt(dt.type(2 * l + 1) / dt.type(2 * l + 2))
+        nsc = f * (x * sc - y * ss)
+        nss = f * (y * sc + x * ss)
+        ndsc = [f * (dx[i] * sc + x * dsc[i] - dy[i] * ss - y * dss[i]) for i in range(3)]
+        ndss = [f * (dy[i] * sc + y * dsc[i] + dx[i] * ss + x * dss[i]) for i in range(3)]
+        sc, ss, dsc, dss = nsc, nss, ndsc, ndss
+        S[:, idx(l + 1, l + 1)] = sc
+        S[:, idx(l + 1, -(l + 1))] = ss
+        for i in range(3):
+            dS[i, :, idx(l + 1, l + 1)] = dsc[i]
+            dS[i, :, idx(l + 1, -(l + 1))] = dss[i]
+    for m in range(0, lmax + 1):
+        for sgn in ([1] if m == 0 else [1, -1]):
+            mm = sgn * m
+            prev, dprev = zero.copy(), [zero.copy() for _ in range(3)]
+            cur, dcur = S[:, idx(m, mm)].copy(), [dS[i, :, idx(m, mm)].copy() for i in range(3)]
+            for l in range(m, lmax):
+                den = np.sqrt(dt.type((l + m + 1) * (l - m + 1)))
+                a = dt.type(2 * l + 1) / den
+                b = np.sqrt(dt.type((l + m) * (l - m))) / den
+                nxt = a * z * cur - b * r2 * prev
+                dnxt = [a * (dz[i] * cur + z * dcur[i]) - b * (dr2[i] * prev + r2 * dprev[i]) for i in range(3)]
+                S[:, idx(l + 1, mm)] = nxt
+                for i in range(3):
+                    dS[i, :, idx(l + 1, mm)] = dnxt[i]
+                prev, cur, dprev, dcur = cur, nxt, dcur, dnxt
+    return S, dS
+
+
 def _gauss_legendre_ld(n):
     """Gauss-Legendre nodes and weights in long double (Newton refinement of numpy's)."""
     x0, _ = np.polynomial.legendre.leggauss(n)
@@ -148,6 +197,23 @@ def rot_x90(l):
     J = J.astype(np.float64)
     J[np.abs(J) < 1e-14] = 0.0
     return J
+
+
+_GRADM = {}
+
+
+def grad_matrix(l):
+    """g[xi] ((2l+1) x (2l-1)): d/d(x, y, z)_xi S^l_m = sum_m' g[xi][m+l, m'+l-1] S^{l-1}_m', by exact
+    sphere quadrature of the differentiated recurrences (l >= 1)."""
+    if l not in _GRADM:
+        pts, w = sphere_grid(2 * l)
+        S, dS = solid_real_grad(l, pts)
+        lo = S[:, (l - 1) ** 2:l * l]
+        norm = np.longdouble(2 * l - 1) / (4 * np.arccos(np.longdouble(-1)))
+        g = np.stack([norm * np.einsum("p,pi,pj->ij", w, dS[i][:, l * l:], lo) for i in range(3)]).astype(np.float64)
+        g[np.abs(g) < 1e-14] = 0.0
+        _GRADM[l] = g
+    return _GRADM[l]
 
 
 def monic_c(L, mu):
@@ -355,6 +421,85 @@ def emulate_block(LA, LB, A, B, ea, wa, eb, wb, nuc_pos, nuc_Z, cap=DEFAULT_CAP,
     return Dat @ Vp @ Dbt.T
 
 
+def emulate_grad(LA, LB, A, B, ea, wa, eb, wb, nuc_pos, nuc_Z, Dt, boys=boys_np):
+    """numpy run of the adjoint kernel for one shell pair (LA at A) x (LB at B), LA >= LB:
+    E = sum Dt V_block and its gradients (dE/dA, dE/dB, dE/dc [n_nuc, 3]) from the emitted term
+    tables, gradient matrices and forward-mode recurrences."""
+    A, B = np.asarray(A, float), np.asarray(B, float)
+    ct, st, cp, sp, Rl = frame(B - A)
+    th, ph = math.atan2(st, ct), math.atan2(sp, cp)
+    Qm = np.array([[ct * cp, ct * sp, -st], [-sp, cp, 0.0], [st * cp, st * sp, ct]])  # lab -> frame
+    def dmat(l):   # D^l with D^T = Z(phi) J^T Z(theta) J
+        cth = [math.cos(m * th) for m in range(l + 1)]
+        sth = [math.sin(m * th) for m in range(l + 1)]
+        cph = [math.cos(m * ph) for m in range(l + 1)]
+        sph = [math.sin(m * ph) for m in range(l + 1)]
+        J = rot_x90(l)
+        return (zrot(l, cph, sph) @ J.T @ zrot(l, cth, sth) @ J).T
+    Dp = dmat(LA) @ np.asarray(Dt, float) @ dmat(LB).T
+    blocks = {0: Dp.reshape(-1)}
+    if LA >= 1:
+        g = grad_matrix(LA)
+        blocks[1] = [(g[i].T @ Dp).reshape(-1) for i in range(3)]
+    if LB >= 1:
+        g = grad_matrix(LB)
+        blocks[2] = [(Dp @ g[i]).reshape(-1) for i in range(3)]
+    ents = grad_entries(LA, LB)
+    tabs = grad_tables(LA, LB)
+    LM = LA + LB
+    E = 0.0
+    dA, dB = np.zeros(3), np.zeros(3)
+    dC = np.zeros((len(nuc_Z), 3))
+    for a_, wa_ in zip(ea, wa):
+        for b_, wb_ in zip(eb, wb):
+            p = a_ + b_
+            P = (a_ * A + b_ * B) / p
+            mu = a_ * b_ / p
+            K = math.exp(-mu * Rl * Rl)
+            ta, tb = b_ * Rl / p, -a_ * Rl / p
+            pre = -wa_ * wb_ * K
+            fk = [pre * 2 * math.pi * math.factorial(k) / p ** (k + 1) for k in range(LB + 1)]
+            s0 = np.zeros(len(ents))
+            sa = np.zeros((3, len(ents)))
+            sb = np.zeros((3, len(ents)))
+            for kind, e, src, pa, pb, coef in tabs:
+                f = coef * ta ** pa * tb ** pb
+                if kind == 0:
+                    s0[e] += f * blocks[0][src]
+                elif kind == 1:
+                    for i in range(3):
+                        sa[i, e] += f * blocks[1][i][src]
+                else:
+                    for i in range(3):
+                        sb[i, e] += f * blocks[2][i][src]
+            scale = np.array([fk[e[2]] * monic_c(e[0], abs(e[1])) for e in ents])
+            wbar = scale * s0
+            wr = scale * (b_ / p * sa - a_ / p * sb)
+            wr[2] += -2.0 * mu * Rl * wbar
+            gP = np.zeros(3)
+            eR = np.zeros(3)
+            for ci, (c, Z) in enumerate(zip(nuc_pos, nuc_Z)):
+                C = rotate_into_frame(np.asarray(c) - P, ct, st, cp, sp)
+                T = p * float(C @ C)
+                F = boys(LM + 1, T)
+                S, dS = solid_real_grad(LM, C[None].astype(np.longdouble))
+                S, dS = S.astype(float)[0], dS.astype(float)[:, 0]
+                gr = np.zeros(3)
+                for e, (L, M, k) in enumerate(ents):
+                    cl = monic_c(L, abs(M))
+                    q, dq = S[L * L + M + L] / cl, dS[:, L * L + M + L] / cl
+                    G = sum(T ** j / math.factorial(j) * F[L + j] for j in range(k + 1))
+                    Gp = -T ** k / math.factorial(k) * F[L + k + 1]
+                    gr += Z * wbar[e] * (G * dq + Gp * q * 2 * p * C)
+                    eR += Z * wr[:, e] * G * q
+                    E += Z * wbar[e] * G * q
+                dC[ci] += Qm.T @ gr
+                gP -= gr
+            dA += Qm.T @ (a_ / p * gP - eR)
+            dB += Qm.T @ (b_ / p * gP + eR)
+    return E, dA, dB, dC
+
+
 # ----------------------------------------------------------------------------------------------
 # Emission
 # ----------------------------------------------------------------------------------------------
@@ -504,6 +649,175 @@ def emit_rotation(l):
     return "\n".join(o)
 
 
+def emit_rotation_inv(l):
+    """v <- D v = J^T Z(-theta) J Z(-phi) v, the inverse of Rot<l> (laboratory -> pair frame)."""
+    J = rot_x90(l)
+    n = 2 * l + 1
+    o = [f"template <> struct RotInv<{l}> {{",
+         f"  static __device__ __forceinline__ void apply(double (&v)[{n}], const double* __restrict__ cth, "
+         "const double* __restrict__ sth,",
+         "                                              const double* __restrict__ cph, const double* __restrict__ sph) {"]
+
+    def zrot_neg(vec, c, sn):
+        for m in range(1, l + 1):
+            o.append(f"    {{ const double c = {vec}[{l + m}], s = {vec}[{l - m}];")
+            o.append(f"      {vec}[{l + m}] = {c}[{m}] * c + {sn}[{m}] * s; {vec}[{l - m}] = -{sn}[{m}] * c + {c}[{m}] * s; }}")
+
+    def matvec(M, src, dst):
+        for i in range(n):
+            terms = [(M[i, j], j) for j in range(n) if M[i, j] != 0.0]
+            if not terms:
+                o.append(f"    const double {dst}{i} = 0.0;")
+                continue
+            e = f"{lit(terms[0][0])} * {src}[{terms[0][1]}]"
+            for c, j in terms[1:]:
+                e = f"fma({lit(c)}, {src}[{j}], {e})"
+            o.append(f"    const double {dst}{i} = {e};")
+    o.append(f"    double w[{n}];")
+    zrot_neg("v", "cph", "sph")
+    matvec(J, "v", "a")
+    for i in range(n):
+        o.append(f"    w[{i}] = a{i};")
+    zrot_neg("w", "cth", "sth")
+    matvec(J.T, "w", "b")
+    for i in range(n):
+        o.append(f"    v[{i}] = b{i};")
+    o.append("  }")
+    o.append("};")
+    return "\n".join(o)
+
+
+def grad_entries(LA, LB):
+    """Canonical order of all W entries (L, M, k) of a class for the gradient kernel."""
+    return list(group_index(LA, LB, class_units(LA, LB)).keys())
+
+
+def grad_tables(LA, LB):
+    """Term tables of the adjoint vectors of class (LA, LB), by entry of grad_entries:
+    (kind, entry, src, pa, pb, coef) with kind 0: class (LA, LB) on the rotated density block,
+    1: class (LA-1, LB) on the a-side gradient blocks, 2: class (LA, LB-1) on the b-side ones.
+    src indexes the row-major block of that kind; pa, pb are the powers of t_a and t_b."""
+    ent = {e: i for i, e in enumerate(grad_entries(LA, LB))}
+    out = []
+    specs = [(0, LA, LB)]
+    if LA >= 1:
+        specs.append((1, LA - 1, LB))
+    if LB >= 1:
+        specs.append((2, LA, LB - 1))
+    for kind, la, lb in specs:
+        nb = 2 * lb + 1
+        for (ma, mb, l1, l2, L, M, k, coef) in class_terms(la, lb):
+            out.append((kind, ent[(L, M, k)], (ma + la) * nb + (mb + lb), la - l1, lb - l2, coef))
+    return out
+
+
+def emit_grad(LA, LB):
+    """Tables and the forward-mode nucleus step of the adjoint (gradient) kernel of class (LA, LB)."""
+    LM = LA + LB
+    ents = grad_entries(LA, LB)
+    NW = len(ents)
+    idx = {e: i for i, e in enumerate(ents)}
+    o = [f"// ---- gradient, class ({LA}, {LB}) ----"]
+    terms = sorted(grad_tables(LA, LB), key=lambda t: (t[1], t[0], t[2]))
+    offs = [0] * (NW + 1)
+    for t in terms:
+        offs[t[1] + 1] += 1
+    for i in range(NW):
+        offs[i + 1] += offs[i]
+    o.append(f"__device__ const int kGradOff{LA}{LB}[{NW + 1}] = {{{', '.join(map(str, offs))}}};")
+    o.append(f"__device__ const GradTerm kGradTerm{LA}{LB}[{len(terms)}] = {{")
+    for kind, e, src, pa, pb, coef in terms:
+        o.append(f"  {{{lit(coef)}, {src}, {kind}, {pa}, {pb}}},")
+    o.append("};")
+    o.append(f"__device__ const int kGradK{LA}{LB}[{NW}] = {{{', '.join(str(e[2]) for e in ents)}}};")
+    o.append(f"__device__ const double kGradC{LA}{LB}[{NW}] = {{{', '.join(lit(monic_c(e[0], abs(e[1]))) for e in ents)}}};")
+    o.append(f"template <> struct GradClass<{LA}, {LB}> {{")
+    o.append(f"  static constexpr int NW = {NW};")
+    o.append(f"  static __device__ const int* off() {{ return kGradOff{LA}{LB}; }}")
+    o.append(f"  static __device__ const GradTerm* terms() {{ return kGradTerm{LA}{LB}; }}")
+    o.append(f"  static __device__ const int* kk() {{ return kGradK{LA}{LB}; }}")
+    o.append(f"  static __device__ const double* cl() {{ return kGradC{LA}{LB}; }}")
+    # nucleus step: Q and grad Q by forward-mode recurrences, contracted with the adjoint quadruples
+    o.append("  // adj: LDS quadruples (Wbar, WRx, WRy, WRz) per entry; acc: 0-2 sum a grad Q, 3 sum b Q,")
+    o.append("  // 4-6 sum (WR . G) Q, 7 sum a Q, with a = Wbar . G and b = Wbar . dG/dT")
+    o.append("  static __device__ __forceinline__ void step(const double* __restrict__ adj, double x, double y, double z,")
+    o.append(f"                                              double r2, const double (&F)[{LM + 2}], const double (&tj)[{LB + 1}],")
+    o.append("                                              double (&acc)[8]) {")
+    o.append("    double sc = 1.0, ss = 0.0, scp = 0.0, ssp = 0.0;")
+    cur = 0
+    for (mu, sg) in class_units(LA, LB):
+        while cur < mu:
+            o.append("    { const double nc = fma(x, sc, -y * ss), ns = fma(y, sc, x * ss); scp = sc; ssp = ss; sc = nc; ss = ns; }")
+            cur += 1
+        o.append(f"    {{ // half-family M = {sg * mu}")
+        if mu == 0:
+            o.append("      double q = 1.0, qx = 0.0, qy = 0.0, qz = 0.0;")
+        elif sg > 0:
+            o.append(f"      double q = sc, qx = {float(mu)} * scp, qy = {float(-mu)} * ssp, qz = 0.0;")
+        else:
+            o.append(f"      double q = ss, qx = {float(mu)} * ssp, qy = {float(mu)} * scp, qz = 0.0;")
+        o.append("      double pq = 0.0, px = 0.0, py = 0.0, pz = 0.0;")
+        for L in range(mu, LM + 1):
+            if L > mu:
+                if L - 1 == mu:
+                    o.append("      { pq = q; px = qx; py = qy; pz = qz; q = z * pq; qx = z * px; qy = z * py; qz = fma(z, pz, pq); }")
+                else:
+                    e = -monic_e(L - 1, mu)
+                    o.append(f"      {{ const double E = {lit(e)};")
+                    o.append("        const double nq = fma(z, q, E * r2 * pq);")
+                    o.append("        const double nx = fma(z, qx, E * fma(2.0 * x, pq, r2 * px));")
+                    o.append("        const double ny = fma(z, qy, E * fma(2.0 * y, pq, r2 * py));")
+                    o.append("        const double nz = fma(z, qz, q + E * fma(2.0 * z, pq, r2 * pz));")
+                    o.append("        pq = q; px = qx; py = qy; pz = qz; q = nq; qx = nx; qy = ny; qz = nz; }")
+            km = kmax_of(LA, LB, L)
+            o.append("      { double g = 0.0, a = 0.0, b = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;")
+            for k in range(km + 1):
+                e = idx[(L, sg * mu, k)]
+                if k == 0:
+                    o.append(f"        g = F[{L}];")
+                else:
+                    o.append(f"        g = fma(tj[{k}], F[{L + k}], g);")
+                o.append(f"        {{ const double* w = adj + {4 * e}; const double gp = -tj[{k}] * F[{L + k + 1}];")
+                o.append("          a = fma(w[0], g, a); b = fma(w[0], gp, b); ex = fma(w[1], g, ex); ey = fma(w[2], g, ey); ez = fma(w[3], g, ez); }")
+            o.append("        acc[0] = fma(a, qx, acc[0]); acc[1] = fma(a, qy, acc[1]); acc[2] = fma(a, qz, acc[2]);")
+            o.append("        acc[3] = fma(b, q, acc[3]); acc[4] = fma(ex, q, acc[4]); acc[5] = fma(ey, q, acc[5]);")
+            o.append("        acc[6] = fma(ez, q, acc[6]); acc[7] = fma(a, q, acc[7]); }")
+        o.append("    }")
+    o.append("  }")
+    o.append("};")
+    return "\n".join(o)
+
+
+def emit_grad_header(lmax=LMAX_SHELL):
+    out = ["// gradient kernel: inverse rotations, gradient matrices of the real solid harmonics, and per class",
+           "// the adjoint term tables and the forward-mode nucleus step",
+           "struct GradTerm {",
+           "  double coef;",
+           "  int16_t src;",
+           "  int8_t kind, pa, pb;",
+           "};",
+           "template <int L> struct RotInv;",
+           "template <int LA, int LB> struct GradClass;"]
+    for l in range(lmax + 1):
+        out.append(emit_rotation_inv(l))
+    for l in range(1, lmax + 1):
+        g = grad_matrix(l)
+        vals = ", ".join(lit(v) for v in g.reshape(-1))
+        out.append(f"// d/d(x,y,z) S^{l}_m = sum_m' g[xi][m+{l}][m'+{l - 1}] S^{l - 1}_m'")
+        out.append(f"__device__ const double kGradMat{l}[{g.size}] = {{{vals}}};")
+    out.append("__device__ __forceinline__ const double* grad_matrix(int l) {")
+    out.append("  switch (l) {")
+    for l in range(1, lmax + 1):
+        out.append(f"    case {l}: return kGradMat{l};")
+    out.append("  }")
+    out.append("  return nullptr;")
+    out.append("}")
+    for LA in range(lmax + 1):
+        for LB in range(LA + 1):
+            out.append(emit_grad(LA, LB))
+    return "\n".join(out) + "\n"
+
+
 def emit_header(cap=DEFAULT_CAP, lmax=LMAX_SHELL):
     out = ["// Generated by gen_classes.py -- do not edit. Class-specific code of the nuclear-attraction",
            "// kernel: nucleus step, coupling (product rule + shift along the A->B axis) and rotations.",
@@ -543,6 +857,10 @@ def main(argv):
     with open(tmp, "w") as f:
         f.write(text)
     os.replace(tmp, out)
+    gout = os.path.join(os.path.dirname(out), "shgo_grad.inc")
+    with open(gout + ".tmp", "w") as f:
+        f.write(emit_grad_header())
+    os.replace(gout + ".tmp", gout)
     return out
 
 

@@ -148,3 +148,78 @@ def test_emulated_algorithm_on_z_axis_and_same_center():
         wa, wb = xcheck.contracted_weights(4, [0.8], [1.0]), xcheck.contracted_weights(3, [1.9], [1.0])
         V = gc.emulate_block(4, 3, A, B, [0.8], wa, [1.9], wb, nuc.pos, nuc.Z)
         assert np.all(np.abs(V - ref) <= 1e-13 + 1e-11 * np.abs(ref))
+
+
+# ---------------------------------------------------------------------------------------------
+# gradient kernel tables and algorithm
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("l", range(1, 7))
+def test_harmonic_gradients_and_gradient_matrices(l):
+    rng = np.random.default_rng(60 + l)
+    X = rng.normal(size=(4, 3))
+    S, dS = gc.solid_real_grad(l, X)
+    g = gc.grad_matrix(l)
+    h = 1e-5
+    for xi in range(3):
+        e = np.zeros(3)
+        e[xi] = h
+        fd = (gc.solid_real(l, X + e) - gc.solid_real(l, X - e)) / (2 * h)
+        assert np.allclose(dS[xi], fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+        # the gradient of S^l is a combination of S^{l-1}
+        lower = gc.solid_real(l - 1, X)[:, (l - 1) ** 2:]
+        assert np.allclose(dS[xi][:, l * l:], lower @ g[xi].T, rtol=1e-12, atol=1e-12 * np.abs(dS[xi]).max())
+
+
+def test_grad_tables_cover_the_coupling():
+    # the kind-0 table of each class is the forward coupling, term for term
+    for la, lb in [(2, 1), (3, 3), (6, 4)]:
+        fwd = gc.class_terms(la, lb)
+        t0 = [t for t in gc.grad_tables(la, lb) if t[0] == 0]
+        assert len(t0) == len(fwd)
+        assert sorted(t[5] for t in t0) == sorted(t[7] for t in fwd)
+
+
+GRAD_CLASSES = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 2), (3, 1), (3, 3), (4, 2), (5, 1), (6, 3)]
+
+
+@pytest.mark.parametrize("la,lb", GRAD_CLASSES)
+def test_emulated_gradient_against_oracle(la, lb):
+    rng = np.random.default_rng(700 + 10 * la + lb)
+    A, B = rng.uniform(0, 2, 3), rng.uniform(0, 2, 3)
+    ea, eb = rng.uniform(0.3, 3, 2), rng.uniform(0.3, 3, 1)
+    da, db = rng.uniform(0.2, 1, 2), np.ones(1)
+    bs = synth.Basis(np.array([A, B]), np.array([la, lb], np.int32), np.array([2, 1], np.int32),
+                     np.array([0, 2], np.int64), np.concatenate([ea, eb]), np.concatenate([da, db]))
+    nuc = synth.Nuclei(rng.uniform(0, 2, (2, 3)), np.array([2.0, 5.0]))
+    D = np.zeros((bs.nbf(), bs.nbf()))
+    Dt = rng.normal(size=(2 * la + 1, 2 * lb + 1))
+    D[:2 * la + 1, 2 * la + 1:] = Dt
+    dn, dc, E = oracle.grad(bs, nuc, D)
+    wa, wb = xcheck.contracted_weights(la, ea, da), xcheck.contracted_weights(lb, eb, db)
+    Ee, dAe, dBe, dCe = gc.emulate_grad(la, lb, A, B, ea, wa, eb, wb, nuc.pos, nuc.Z, Dt)
+    scale = max(1.0, np.abs(np.concatenate([dn, dc])).max())
+    assert Ee == pytest.approx(E, rel=1e-12, abs=1e-13)
+    assert np.allclose(dAe, dc[0], atol=1e-12 * scale)
+    assert np.allclose(dBe, dc[1], atol=1e-12 * scale)
+    assert np.allclose(dCe, dn, atol=1e-12 * scale)
+
+
+def test_emulated_gradient_same_center_and_z_axis():
+    # A = B (R = 0: the frame is the identity and the R-derivative comes from the l = 1 shifts)
+    # and R along -z
+    nuc = synth.Nuclei(np.array([[0.2, -0.4, 1.1], [0.5, 0.3, -0.2]]), np.array([3.0, 1.0]))
+    rng = np.random.default_rng(9)
+    for B in ([0.0, 0.0, 0.0], [0.0, 0.0, -0.9]):
+        A = np.zeros(3)
+        bs = synth.Basis(np.array([A, B]), np.array([3, 2], np.int32), np.array([1, 1], np.int32),
+                         np.array([0, 1], np.int64), np.array([0.8, 1.9]), np.ones(2))
+        D = np.zeros((12, 12))
+        Dt = rng.normal(size=(7, 5))
+        D[:7, 7:] = Dt
+        dn, dc, E = oracle.grad(bs, nuc, D)
+        wa, wb = xcheck.contracted_weights(3, [0.8], [1.0]), xcheck.contracted_weights(2, [1.9], [1.0])
+        Ee, dAe, dBe, dCe = gc.emulate_grad(3, 2, A, B, [0.8], wa, [1.9], wb, nuc.pos, nuc.Z, Dt)
+        scale = max(1.0, np.abs(np.concatenate([dn, dc])).max())
+        assert Ee == pytest.approx(E, rel=1e-12, abs=1e-13)
+        assert np.allclose(np.concatenate([dAe, dBe, dCe.reshape(-1)]),
+                           np.concatenate([dc[0], dc[1], dn.reshape(-1)]), atol=1e-12 * scale)
