@@ -115,6 +115,20 @@ int64_t shgo_plan_integrals(const shgo_plan* plan);
  * (shgo_plan_output_size doubles; every element is written). Allocates nothing. */
 shgo_status shgo_execute(shgo_plan* plan, double* out, void* stream);
 
+/* Gradient of E = sum_ij D_ij V_ij (the nuclear-attraction matrix of Eq. 11, differentiated
+ * through Eq. 5, the shift of Eqs. 7-8, the product rule and the Boys function; an adjoint
+ * kernel, not finite differences) with respect to the nuclear positions and the shell centers.
+ * Matrix plans only (SHGO_ERR_INVALID_ARG for a pair plan).
+ *   D            device, nbf x nbf row-major (any matrix; only D_ij V_ij enters E)
+ *   dE_dnuclei   device [n_nuclei][3], overwritten
+ *   dE_dcenters  device [n_shells][3], overwritten
+ *   energy       device [1], overwritten with E, or NULL
+ * Runs on `stream` and allocates nothing. The work needs 8 (3 n_nuclei + 4 S) bytes of LDS per
+ * workgroup, S a per-class layout of at most ~2.9k doubles; SHGO_ERR_INVALID_ARG if that
+ * exceeds the 160 KB of a CU (about 2,800 nuclei for l <= 6), before any device work. */
+shgo_status shgo_execute_grad(shgo_plan* plan, const double* D, double* dE_dnuclei, double* dE_dcenters,
+                              double* energy, void* stream);
+
 /* Phase timing. With n_slots > 0, every later shgo_execute records HIP event pairs around
  * its two phases -- 0: pair build (normalisation, enumeration, screening, class sort, work
  * queue), 1: the integral kernel (one persistent launch over every class) -- cycling through

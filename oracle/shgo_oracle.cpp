@@ -584,6 +584,9 @@ int grad_pairs(const Basis& bs, int n_nuc, const double* nuc_pos, const double* 
       for (int x = 0; x < da; ++x)
         for (int y = 0; y < db; ++y)
           Dt[x * db + y] = D[(so[a] + x) * nbf + so[b] + y] + (a != b ? D[(so[b] + y) * nbf + so[a] + x] : 0.0);
+      bool any = false;
+      for (double v : Dt) any = any || v != 0.0;
+      if (!any) continue;  // a zero density block contributes nothing to E or its gradient
       const ShellT<Dual> sa = make_shell<Dual>(bs, a, nullptr), sb = make_shell<Dual>(bs, b, nullptr);
       std::vector<Dual> blk(da * db);
       auto pair_energy = [&](const ShellT<Dual>& A, const ShellT<Dual>& B, int nn, const Dual* pos, const Dual* Z) {

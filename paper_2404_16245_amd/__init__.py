@@ -28,7 +28,8 @@ SHGO_LMAX = 6
 
 EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
-            "shgo_plan_integrals", "shgo_execute", "shgo_boys", "shgo_plan_set_timing", "shgo_plan_phase_ms"]
+            "shgo_plan_integrals", "shgo_execute", "shgo_execute_grad", "shgo_boys", "shgo_plan_set_timing",
+            "shgo_plan_phase_ms"]
 SHGO_NUM_PHASES = 2
 
 
@@ -86,6 +87,8 @@ def load_library(path=LIB_PATH):
     lib.shgo_plan_integrals.restype = i64
     lib.shgo_execute.argtypes = [vp, vp, vp]
     lib.shgo_execute.restype = ctypes.c_int
+    lib.shgo_execute_grad.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.shgo_execute_grad.restype = ctypes.c_int
     lib.shgo_boys.argtypes = [vp, i64, vp, i32, vp, vp]
     lib.shgo_boys.restype = ctypes.c_int
     lib.shgo_plan_set_timing.argtypes = [vp, i32]
@@ -233,6 +236,26 @@ def shgo_execute(plan, out, stream=None):
     return out
 
 
+def _f64_device(t, name, n):
+    if str(t.dtype) != "torch.float64" or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    if t.numel() < n:
+        raise ValueError(f"{name} is too small ({t.numel()} < {n})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def shgo_execute_grad(plan, D, dE_dnuclei, dE_dcenters, energy=None, stream=None):
+    """Enqueue the adjoint kernel: gradient of E = sum_ij D_ij V_ij for a matrix plan.
+    D [nbf, nbf], dE_dnuclei [n_nuclei, 3], dE_dcenters [n_shells, 3], energy [1] or None:
+    contiguous float64 device tensors."""
+    lib = load_library()
+    e = ctypes.c_void_p(0) if energy is None else _f64_device(energy, "energy", 1)
+    _check(lib, plan.ctx, lib.shgo_execute_grad(plan.handle, _f64_device(D, "D", 0),
+                                                _f64_device(dE_dnuclei, "dE_dnuclei", 0),
+                                                _f64_device(dE_dcenters, "dE_dcenters", 0), e,
+                                                _stream_handle(stream)))
+
+
 def shgo_plan_set_timing(plan, n_slots):
     lib = load_library()
     _check(lib, plan.ctx, lib.shgo_plan_set_timing(plan.handle, int(n_slots)))
@@ -293,3 +316,66 @@ def nuclear_attraction_pairs(basis, nuclei, pair_a, pair_b, screen=0.0, device=0
     shgo_execute(plan, out)
     torch.cuda.current_stream().synchronize()
     return out
+
+
+def nuclear_attraction_grad(basis, nuclei, D, screen=0.0, device=0):
+    """(dE/d nuclear positions [n, 3], dE/d shell centers [n_shells, 3], E) for E = sum D V, as
+    float64 CUDA tensors."""
+    import torch
+    ctx = context(device)
+    plan = shgo_plan_matrix(ctx, basis, nuclei, screen)
+    dev = f"cuda:{device}"
+    Dt = torch.as_tensor(D, dtype=torch.float64, device=dev).contiguous()
+    dn = torch.empty((nuclei.n, 3), dtype=torch.float64, device=dev)
+    dc = torch.empty((basis.n_shells, 3), dtype=torch.float64, device=dev)
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    shgo_execute_grad(plan, Dt, dn, dc, e)
+    torch.cuda.current_stream().synchronize()
+    return dn, dc, e
+
+
+def _autograd_function():
+    import torch
+
+    class NuclearAttractionFn(torch.autograd.Function):
+        """V(centers, nuclear positions) with a backward through the adjoint kernel.
+
+        forward(centers [n_shells, 3], positions [n_nuclei, 3], basis, charges, screen) -> V [nbf, nbf];
+        the basis supplies l, exponents and contraction coefficients (its centers are ignored in
+        favour of ``centers``). backward(dL/dV) runs shgo_execute_grad with D = dL/dV on the plan
+        built in forward, so Boys values are recomputed, not stored."""
+
+        @staticmethod
+        def forward(ctx, centers, positions, basis, charges, screen=0.0):
+            from . import synth
+            dev = centers.device
+            b = synth.Basis(centers.detach().cpu().numpy().astype(np.float64), basis.l, basis.nprim,
+                            basis.prim_off, basis.expo, basis.coef)
+            n = synth.Nuclei(positions.detach().cpu().numpy().astype(np.float64), np.asarray(charges, np.float64))
+            sctx = context(dev.index or 0)
+            plan = shgo_plan_matrix(sctx, b, n, screen)
+            nbf = b.nbf()
+            V = torch.empty((nbf, nbf), dtype=torch.float64, device=dev)
+            shgo_execute(plan, V)
+            ctx.plan = plan
+            ctx.shapes = (b.n_shells, n.n)
+            return V
+
+        @staticmethod
+        def backward(ctx, grad_V):
+            n_shells, n_nuc = ctx.shapes
+            dev = grad_V.device
+            dn = torch.empty((n_nuc, 3), dtype=torch.float64, device=dev)
+            dc = torch.empty((n_shells, 3), dtype=torch.float64, device=dev)
+            shgo_execute_grad(ctx.plan, grad_V.to(torch.float64).contiguous(), dn, dc)
+            return dc, dn, None, None, None
+
+    return NuclearAttractionFn
+
+
+def __getattr__(name):
+    if name == "NuclearAttractionFn":
+        fn = _autograd_function()
+        globals()["NuclearAttractionFn"] = fn
+        return fn
+    raise AttributeError(name)
