@@ -129,6 +129,35 @@ shgo_status shgo_execute(shgo_plan* plan, double* out, void* stream);
 shgo_status shgo_execute_grad(shgo_plan* plan, const double* D, double* dE_dnuclei, double* dE_dcenters,
                               double* energy, void* stream);
 
+/* The same evaluation as a captured HIP graph. The first call for a given `out` captures the
+ * launches of shgo_execute on a private stream and instantiates the graph (HIP allocates then);
+ * later calls with the same `out` only launch it on `stream`. A call with another `out`, and
+ * shgo_plan_set_schedule / shgo_plan_autotune, replace the graph. The graph holds no memset
+ * nodes (buffers are cleared by fill kernels) and no timing events. */
+shgo_status shgo_execute_graph(shgo_plan* plan, double* out, void* stream);
+
+/* Work schedule of the persistent launch, one entry per class id c = la(la+1)/2 + lb (la >= lb):
+ * order[28], the queue order of the classes (a permutation of 0..27; the queue hands out items
+ * longest first when the order is by decreasing item time), and slices[c] in {1, 2, 4}, the
+ * number of nucleus slices each (tile, group) item of class c is cut into (the slices' partial
+ * sums are coupled and added separately; the sum is the same up to rounding). get copies the
+ * plan's schedule out; set validates (SHGO_ERR_INVALID_ARG) and installs one, e.g. a schedule
+ * saved from an earlier autotune of the same workload. */
+#define SHGO_NUM_CLASSES 28
+shgo_status shgo_plan_get_schedule(const shgo_plan* plan, int32_t* order, int32_t* slices);
+shgo_status shgo_plan_set_schedule(shgo_plan* plan, const int32_t* order, const int32_t* slices);
+
+/* Autotuner of the batched launch. Runs the plan once with per-item timing to measure the mean
+ * item time of every class, builds SHGO_TUNE_CANDIDATES schedules -- 0: the model order, no
+ * slices; 1: classes by measured item time; 2, 3: measured order with the longest items split
+ * into nucleus slices so that none exceeds 1/2 (2) or 1/4 (3) of the mean work per wavefront --
+ * times `rounds` executions of each on `stream` (the call synchronizes the stream), and keeps the
+ * fastest. ms[SHGO_TUNE_CANDIDATES] (or NULL) receives each candidate's milliseconds per
+ * execution, *chosen (or NULL) the index kept. `out` is written as by shgo_execute. */
+#define SHGO_TUNE_CANDIDATES 4
+shgo_status shgo_plan_autotune(shgo_plan* plan, double* out, int32_t rounds, void* stream, double* ms,
+                               int32_t* chosen);
+
 /* Phase timing. With n_slots > 0, every later shgo_execute records HIP event pairs around
  * its two phases -- 0: pair build (normalisation, enumeration, screening, class sort, work
  * queue), 1: the integral kernel (one persistent launch over every class) -- cycling through

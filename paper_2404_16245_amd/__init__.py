@@ -28,8 +28,11 @@ SHGO_LMAX = 6
 
 EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
-            "shgo_plan_integrals", "shgo_execute", "shgo_execute_grad", "shgo_boys", "shgo_plan_set_timing",
-            "shgo_plan_phase_ms"]
+            "shgo_plan_integrals", "shgo_execute", "shgo_execute_graph", "shgo_execute_grad", "shgo_boys",
+            "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
+            "shgo_plan_autotune"]
+SHGO_NUM_CLASSES = 28
+SHGO_TUNE_CANDIDATES = 4
 SHGO_NUM_PHASES = 2
 
 
@@ -87,6 +90,14 @@ def load_library(path=LIB_PATH):
     lib.shgo_plan_integrals.restype = i64
     lib.shgo_execute.argtypes = [vp, vp, vp]
     lib.shgo_execute.restype = ctypes.c_int
+    lib.shgo_execute_graph.argtypes = [vp, vp, vp]
+    lib.shgo_execute_graph.restype = ctypes.c_int
+    lib.shgo_plan_get_schedule.argtypes = [vp, vp, vp]
+    lib.shgo_plan_get_schedule.restype = ctypes.c_int
+    lib.shgo_plan_set_schedule.argtypes = [vp, vp, vp]
+    lib.shgo_plan_set_schedule.restype = ctypes.c_int
+    lib.shgo_plan_autotune.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.shgo_plan_autotune.restype = ctypes.c_int
     lib.shgo_execute_grad.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.shgo_execute_grad.restype = ctypes.c_int
     lib.shgo_boys.argtypes = [vp, i64, vp, i32, vp, vp]
@@ -234,6 +245,43 @@ def shgo_execute(plan, out, stream=None):
         raise ValueError("out is smaller than the plan's output")
     _check(lib, plan.ctx, lib.shgo_execute(plan.handle, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
+
+
+def shgo_execute_graph(plan, out, stream=None):
+    """As shgo_execute, through a captured HIP graph (captured on the first call for ``out``)."""
+    lib = load_library()
+    _check(lib, plan.ctx, lib.shgo_execute_graph(plan.handle, _f64_device(out, "out", plan.output_size),
+                                                 _stream_handle(stream)))
+    return out
+
+
+def shgo_plan_get_schedule(plan):
+    """(order[28], slices[28]) of the plan's persistent launch."""
+    lib = load_library()
+    order = np.zeros(SHGO_NUM_CLASSES, dtype=np.int32)
+    slices = np.zeros(SHGO_NUM_CLASSES, dtype=np.int32)
+    _check(lib, plan.ctx, lib.shgo_plan_get_schedule(plan.handle, order.ctypes.data, slices.ctypes.data))
+    return order, slices
+
+
+def shgo_plan_set_schedule(plan, order, slices):
+    lib = load_library()
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    slices = np.ascontiguousarray(slices, dtype=np.int32)
+    if order.shape != (SHGO_NUM_CLASSES,) or slices.shape != (SHGO_NUM_CLASSES,):
+        raise ValueError("order and slices need one entry per class (28)")
+    _check(lib, plan.ctx, lib.shgo_plan_set_schedule(plan.handle, order.ctypes.data, slices.ctypes.data))
+
+
+def shgo_plan_autotune(plan, out, rounds=5, stream=None):
+    """Tune the plan's schedule; returns (ms per candidate [4], index kept). Synchronizes."""
+    lib = load_library()
+    ms = np.zeros(SHGO_TUNE_CANDIDATES)
+    chosen = np.zeros(1, dtype=np.int32)
+    _check(lib, plan.ctx, lib.shgo_plan_autotune(plan.handle, _f64_device(out, "out", plan.output_size),
+                                                 int(rounds), _stream_handle(stream), ms.ctypes.data,
+                                                 chosen.ctypes.data))
+    return ms, int(chosen[0])
 
 
 def _f64_device(t, name, n):

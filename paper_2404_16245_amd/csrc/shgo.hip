@@ -337,7 +337,9 @@ struct ClassMeta {
   int32_t order[kNumClasses];      // queue order: classes by decreasing cost per tile
   int64_t vacc_base[kNumClasses];  // first accumulator double of each class
   int32_t tile_base[kNumClasses];  // first tile counter of each class
+  int32_t slices[kNumClasses];     // nucleus slices per (tile, group) item: 1, 2 or 4
 };
+constexpr int kMaxSlices = 4;
 
 struct WorkArgs {
   DevBasis bs;
@@ -349,6 +351,7 @@ struct WorkArgs {
   int32_t* __restrict__ tile_cnt;  // groups finished per tile
   int32_t* __restrict__ queue;     // [0]: next work item
   int32_t* __restrict__ item_off;  // [kNumClasses + 1]: prefix of items per class in queue order
+  unsigned long long* __restrict__ item_ns;  // per-item durations (10 ns ticks) when tuning, else null
   ClassMeta meta;
 };
 // The work arguments live in device memory (one copy per plan) and are read through the scalar
@@ -410,7 +413,7 @@ __device__ __forceinline__ bool next_prim(const PairState& ps, WAP wa, int& i, i
 }
 
 template <int LA, int LB, int G>
-__device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_iters,
+__device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_iters, int c_begin, int c_end,
                                           double* __restrict__ Vp) {
   using Grp = GroupOf<LA, LB, G>;
   constexpr int LM = LA + LB;
@@ -429,7 +432,7 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_
       // nucleus loop: geometry in the pair frame, Boys row from LDS, then the group's step
       double nx = 0.0, ny = 0.0, nz = 0.0, nr2 = 0.0, nt = 0.0, nZ = 0.0, nrow[8];
       const NucPtr nucs = uniform_nuclei(wa->nuc);
-      const int n_nuc = __builtin_amdgcn_readfirstlane(wa->n_nuc);
+      const int c_lo = __builtin_amdgcn_readfirstlane(c_begin), n_nuc = __builtin_amdgcn_readfirstlane(c_end);
       auto geometry = [&](int c) {
         const double cx = nucs[c].x - Px, cy = nucs[c].y - Py, cz = nucs[c].z - Pz;
         const double u = fma(ps.cp, cx, ps.sp * cy);
@@ -456,8 +459,8 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_
       };
       if constexpr (Grp::NW <= kPrefetchMaxW) {
         // small groups have registers to spare: the next nucleus is fetched one step ahead
-        if (n_nuc > 0) geometry(0);
-        for (int c = 0; c < n_nuc; ++c) {
+        if (c_lo < n_nuc) geometry(c_lo);
+        for (int c = c_lo; c < n_nuc; ++c) {
           const double x = nx, y = ny, z = nz, r2 = nr2, t = nt, Zc = nZ;
           double row[8];
 #pragma unroll
@@ -466,7 +469,7 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_
           nucleus(x, y, z, r2, t, Zc, row);
         }
       } else {
-        for (int c = 0; c < n_nuc; ++c) {
+        for (int c = c_lo; c < n_nuc; ++c) {
           geometry(c);
           nucleus(nx, ny, nz, nr2, nt, nZ, nrow);
         }
@@ -493,14 +496,14 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_
 }
 
 template <int LA, int LB, int G>
-__device__ __forceinline__ void dispatch_group(int g, const PairState& ps, WAP wa, int wave_iters,
+__device__ __forceinline__ void dispatch_group(int g, const PairState& ps, WAP wa, int wave_iters, int c0, int c1,
                                                double* Vp) {
   if constexpr (G < ClassInfo<LA, LB>::Q) {
     if (g == G) {
-      run_group<LA, LB, G>(ps, wa, wave_iters, Vp);
+      run_group<LA, LB, G>(ps, wa, wave_iters, c0, c1, Vp);
       return;
     }
-    dispatch_group<LA, LB, G + 1>(g, ps, wa, wave_iters, Vp);
+    dispatch_group<LA, LB, G + 1>(g, ps, wa, wave_iters, c0, c1, Vp);
   }
 }
 
@@ -582,7 +585,10 @@ __device__ __attribute__((noinline)) void process_item(int j, const WorkArgs* wa
   constexpr int NAB = (2 * LA + 1) * (2 * LB + 1);
   constexpr int cls = class_id(LA, LB);
   const int lane = threadIdx.x & 63;
-  const int tile = j / Q, g = j - tile * Q;
+  const int S = wa->meta.slices[cls];
+  const int tile = j / (Q * S), rem = j - tile * Q * S, g = rem / S, sl_i = rem - g * S;
+  const int n_nuc = wa->n_nuc;
+  const int c0 = (int)((int64_t)n_nuc * sl_i / S), c1 = (int)((int64_t)n_nuc * (sl_i + 1) / S);
   const int start = wa->pr.key_off[cls * kKeysPerClass];
   const int end = wa->pr.key_off[(cls + 1) * kKeysPerClass];
   const int slot = start + tile * kTile + lane;
@@ -610,7 +616,7 @@ __device__ __attribute__((noinline)) void process_item(int j, const WorkArgs* wa
   for (int off = 32; off > 0; off >>= 1) iters = max(iters, __shfl_xor(iters, off));
 
   double* Vp = wa->vacc + wa->meta.vacc_base[cls] + (int64_t)tile * NAB * kTile + lane;
-  dispatch_group<LA, LB, 0>(g, ps, wa, iters, Vp);
+  dispatch_group<LA, LB, 0>(g, ps, wa, iters, c0, c1, Vp);
 
   // completion: release this group's atomic adds, count it, and let the last group finish
   int done = 0;
@@ -618,7 +624,7 @@ __device__ __attribute__((noinline)) void process_item(int j, const WorkArgs* wa
     done = __hip_atomic_fetch_add(wa->tile_cnt + wa->meta.tile_base[cls] + tile, 1, __ATOMIC_ACQ_REL,
                                   __HIP_MEMORY_SCOPE_AGENT);
   done = __shfl(done, 0);
-  if (done == Q - 1) {
+  if (done == Q * S - 1) {
     __threadfence();
     finish_tile<LA, LB>(ps, wa, out, slot, Vp);
   }
@@ -638,7 +644,7 @@ __device__ __forceinline__ void dispatch_class(int c, int j, const WorkArgs* wa,
   }
 }
 
-// Queue layout: for the k-th class in queue order, its tiles x groups items, tile-major.
+// Queue layout: for the k-th class in queue order, its tiles x groups x slices items, tile-major.
 __global__ void k_items(DevPairs pr, ClassMeta meta, int32_t* item_off) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int off = 0;
@@ -646,7 +652,7 @@ __global__ void k_items(DevPairs pr, ClassMeta meta, int32_t* item_off) {
     const int c = meta.order[k];
     const int count = pr.key_off[(c + 1) * kKeysPerClass] - pr.key_off[c * kKeysPerClass];
     item_off[k] = off;
-    off += (count + kTile - 1) / kTile * kClassGroups[c];
+    off += (count + kTile - 1) / kTile * kClassGroups[c] * meta.slices[c];
   }
   item_off[kNumClasses] = off;
 }
@@ -666,7 +672,10 @@ k_integrals(const WorkArgs* __restrict__ wa_ptr, double* __restrict__ out) {
     if (item >= total) break;
     int k = 0;
     while (wa->item_off[k + 1] <= item) ++k;
+    unsigned long long* const tick = wa->item_ns;
+    const unsigned long long t0 = tick ? wall_clock64() : 0ull;
     dispatch_class<0, 0>(wa->meta.order[k], item - wa->item_off[k], wa_ptr, out);
+    if (tick && lane == 0) tick[item] = wall_clock64() - t0;
   }
 }
 
@@ -991,6 +1000,11 @@ struct shgo_plan {
   int32_t* item_off = nullptr;
   WorkArgs* d_wa = nullptr;  // the integral kernel's arguments, in device memory
   double* d_energy = nullptr;  // gradient: E when the caller does not ask for it
+  // captured graph of one evaluation (shgo_execute_graph) and its output buffer
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double* graph_out = nullptr;
+  hipStream_t cap_stream = nullptr;
   // phase timing (off when slots == 0): events [slot][phase][start, end]
   int32_t slots = 0;
   int64_t exec_count = 0;
@@ -998,6 +1012,16 @@ struct shgo_plan {
 };
 
 namespace {
+
+constexpr int kTuneCandidates = 4;
+
+void drop_graph(shgo_plan* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->graph_out = nullptr;
+}
 
 shgo_status fail(shgo_context* ctx, shgo_status s, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -1043,6 +1067,47 @@ int64_t total_prims(const shgo_basis* b) {
   int64_t t = 0;
   for (int s = 0; s < b->n_shells; ++s) t = std::max<int64_t>(t, b->prim_offset[s] + b->n_prim[s]);
   return t;
+}
+
+// The integral kernel's arguments (device copy, read through the scalar cache). item_ns turns the
+// per-item timing of the kernel on (tuning runs) or off (null).
+hipError_t upload_args(shgo_plan* p, unsigned long long* item_ns) {
+  const WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, p->ctx->boys_tab, p->vacc, p->tile_cnt,
+                    p->tile_cnt + p->n_tiles, p->item_off, item_ns, p->meta};
+  return hipMemcpy(p->d_wa, &wa, sizeof(WorkArgs), hipMemcpyHostToDevice);
+}
+
+// Work items of the queue for the plan's candidate counts (an upper bound of the device count).
+int64_t max_items(const shgo_plan* p) {
+  int64_t n = 0;
+  for (int c = 0; c < kNumClasses; ++c)
+    n += ((int64_t)p->class_cand[c] + kTile - 1) / kTile * kClassGroups[c] * p->meta.slices[c];
+  return n;
+}
+
+// The launches of one evaluation on `st`: pair build (a1), then the persistent integral kernel.
+// With `timed`, HIP events bracket the two phases (never inside a graph capture).
+void enqueue(shgo_plan* p, double* out, hipStream_t st, bool timed) {
+  const int tb = 256;
+  auto blocks = [&](int64_t n) { return (int)((n + tb - 1) / tb); };
+  const int slot = timed && p->slots > 0 ? (int)(p->exec_count % p->slots) : -1;
+  auto mark = [&](int phase, int edge) {
+    if (slot >= 0) (void)hipEventRecord(p->events[((size_t)slot * SHGO_NUM_PHASES + phase) * 2 + edge], st);
+  };
+  mark(0, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(kNumKeys)), dim3(tb), 0, st, p->pr.key_count, (int64_t)kNumKeys, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(p->n_tiles + 1)), dim3(tb), 0, st, p->tile_cnt, p->n_tiles + 1, 0);
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks(p->vacc_len)), dim3(tb), 0, st, p->vacc, p->vacc_len);
+  if (p->n_shells > 0) hipLaunchKernelGGL(k_prim_weights, dim3(blocks(p->n_shells)), dim3(tb), 0, st, p->bs);
+  hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
+  hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
+  hipLaunchKernelGGL(k_items, dim3(1), dim3(64), 0, st, p->pr, p->meta, p->item_off);
+  mark(0, 1);
+  mark(1, 0);
+  hipLaunchKernelGGL(k_integrals, dim3(p->ctx->grid), dim3(kIntegralThreads), 0, st, (const WorkArgs*)p->d_wa, out);
+  mark(1, 1);
+  if (slot >= 0) p->exec_count++;
 }
 
 shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei* n, int full, int64_t n_pairs,
@@ -1144,6 +1209,7 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
         const int64_t tiles = ((int64_t)p->class_cand[c] + kTile - 1) / kTile;
         p->meta.vacc_base[c] = p->vacc_len;
         p->meta.tile_base[c] = (int32_t)p->n_tiles;
+        p->meta.slices[c] = 1;
         p->vacc_len += tiles * kTile * (2 * la + 1) * (2 * lb + 1);
         p->n_tiles += tiles;
         cost.push_back({-class_cost(la, lb, n->n_nuclei), c});
@@ -1189,9 +1255,7 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
   pr.pa = dpa;
   pr.pb = dpb;
   pr.blk_off = dblk;
-  const WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, ctx->boys_tab, p->vacc, p->tile_cnt,
-                    p->tile_cnt + p->n_tiles, p->item_off, p->meta};
-  e = hipMemcpy(p->d_wa, &wa, sizeof(WorkArgs), hipMemcpyHostToDevice);
+  e = upload_args(p, nullptr);
   if (e != hipSuccess) {
     shgo_plan_destroy(p);
     return fail(ctx, SHGO_ERR_DEVICE, std::string("upload failed: ") + hipGetErrorString(e));
@@ -1326,6 +1390,8 @@ shgo_status shgo_plan_pairs(shgo_context* ctx, const shgo_basis* basis, const sh
 void shgo_plan_destroy(shgo_plan* p) {
   if (!p) return;
   if (p->ctx) (void)hipSetDevice(p->ctx->device);
+  drop_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (hipEvent_t ev : p->events) (void)hipEventDestroy(ev);
   for (void* q : p->allocs) (void)hipFree(q);
   delete p;
@@ -1339,32 +1405,143 @@ shgo_status shgo_execute(shgo_plan* p, double* out, void* stream) {
   shgo_context* ctx = p->ctx;
   if (!out && p->out_size > 0) return fail(ctx, SHGO_ERR_INVALID_ARG, "null output");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
-  hipStream_t st = (hipStream_t)stream;
   if (p->n_cand == 0) return SHGO_OK;
-  const int tb = 256;
-  auto blocks = [&](int64_t n) { return (int)((n + tb - 1) / tb); };
-  const int slot = p->slots > 0 ? (int)(p->exec_count % p->slots) : -1;
-  auto mark = [&](int phase, int edge) {
-    if (slot >= 0) (void)hipEventRecord(p->events[((size_t)slot * SHGO_NUM_PHASES + phase) * 2 + edge], st);
-  };
-  // a1: normalisation, classification, class sort; workspace reset
-  mark(0, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(kNumKeys)), dim3(tb), 0, st, p->pr.key_count, (int64_t)kNumKeys, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(p->n_tiles + 1)), dim3(tb), 0, st, p->tile_cnt, p->n_tiles + 1, 0);
-  hipLaunchKernelGGL(k_fill_f64, dim3(blocks(p->vacc_len)), dim3(tb), 0, st, p->vacc, p->vacc_len);
-  if (p->n_shells > 0) hipLaunchKernelGGL(k_prim_weights, dim3(blocks(p->n_shells)), dim3(tb), 0, st, p->bs);
-  hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-  hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-  hipLaunchKernelGGL(k_items, dim3(1), dim3(64), 0, st, p->pr, p->meta, p->item_off);
-  mark(0, 1);
-  // a2-a8: one persistent launch over every class
-  mark(1, 0);
-  hipLaunchKernelGGL(k_integrals, dim3(ctx->grid), dim3(kIntegralThreads), 0, st, (const WorkArgs*)p->d_wa, out);
-  mark(1, 1);
-  p->exec_count++;
+  enqueue(p, out, (hipStream_t)stream, true);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return SHGO_OK;
+}
+
+shgo_status shgo_execute_graph(shgo_plan* p, double* out, void* stream) {
+  if (!p) return SHGO_ERR_INVALID_ARG;
+  shgo_context* ctx = p->ctx;
+  if (!out && p->out_size > 0) return fail(ctx, SHGO_ERR_INVALID_ARG, "null output");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+  if (p->n_cand == 0) return SHGO_OK;
+  if (!p->gexec || p->graph_out != out) {
+    drop_graph(p);
+    if (!p->cap_stream && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(ctx, SHGO_ERR_DEVICE, "hipStreamCreate failed");
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(ctx, SHGO_ERR_DEVICE, "hipStreamBeginCapture failed");
+    enqueue(p, out, p->cap_stream, false);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(p->cap_stream, &g) != hipSuccess || !g)
+      return fail(ctx, SHGO_ERR_DEVICE, "hipStreamEndCapture failed");
+    p->graph = g;
+    if (hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      drop_graph(p);
+      return fail(ctx, SHGO_ERR_DEVICE, "hipGraphInstantiate failed");
+    }
+    p->graph_out = out;
+  }
+  if (hipGraphLaunch(p->gexec, (hipStream_t)stream) != hipSuccess)
+    return fail(ctx, SHGO_ERR_DEVICE, "hipGraphLaunch failed");
+  return SHGO_OK;
+}
+
+shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* stream, double* ms, int32_t* chosen) {
+  if (!p || rounds < 1 || rounds > 1000) return SHGO_ERR_INVALID_ARG;
+  shgo_context* ctx = p->ctx;
+  if (!out && p->out_size > 0) return fail(ctx, SHGO_ERR_INVALID_ARG, "null output");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+  for (int i = 0; i < kTuneCandidates; ++i)
+    if (ms) ms[i] = -1.0;
+  if (chosen) *chosen = 0;
+  if (p->n_cand == 0) return SHGO_OK;
+  hipStream_t st = (hipStream_t)stream;
+  drop_graph(p);
+  // 1. one timed run with the model order and no slices: mean duration of each class's items
+  ClassMeta base = p->meta;
+  for (int c = 0; c < kNumClasses; ++c) p->meta.slices[c] = 1;
+  const int64_t nmax = max_items(p) * kMaxSlices;
+  unsigned long long* ticks = nullptr;
+  if (hipMalloc(&ticks, sizeof(unsigned long long) * (size_t)std::max<int64_t>(nmax, 1)) != hipSuccess)
+    return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "tuning buffer");
+  std::vector<unsigned long long> th((size_t)nmax);
+  std::vector<int32_t> ioff(kNumClasses + 1);
+  double item_ns[kNumClasses] = {0};
+  int64_t items_of[kNumClasses] = {0};
+  hipError_t e = upload_args(p, ticks);
+  if (e == hipSuccess) {
+    enqueue(p, out, st, false);
+    e = hipStreamSynchronize(st);
+  }
+  if (e == hipSuccess) e = hipMemcpy(ioff.data(), p->item_off, sizeof(int32_t) * ioff.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && ioff[kNumClasses] > 0)
+    e = hipMemcpy(th.data(), ticks, sizeof(unsigned long long) * (size_t)ioff[kNumClasses], hipMemcpyDeviceToHost);
+  (void)hipFree(ticks);
+  if (e != hipSuccess) {
+    p->meta = base;
+    (void)upload_args(p, nullptr);
+    return fail(ctx, SHGO_ERR_DEVICE, std::string("tuning run failed: ") + hipGetErrorString(e));
+  }
+  double total_ns = 0.0;
+  for (int k = 0; k < kNumClasses; ++k) {
+    const int c = p->meta.order[k];
+    for (int i = ioff[k]; i < ioff[k + 1]; ++i) item_ns[c] += 10.0 * (double)th[(size_t)i];
+    items_of[c] = ioff[k + 1] - ioff[k];
+    total_ns += item_ns[c];
+    if (items_of[c] > 0) item_ns[c] /= (double)items_of[c];
+  }
+  // 2. candidates: model order; measured order; measured order with the longest items split
+  //    into nucleus slices so that no item exceeds a share of the mean work per wavefront
+  const double waves = (double)ctx->grid * (kIntegralThreads / 64);
+  ClassMeta cand[kTuneCandidates];
+  cand[0] = base;
+  for (int c = 0; c < kNumClasses; ++c) cand[0].slices[c] = 1;
+  std::vector<std::pair<double, int>> by;
+  for (int c = 0; c < kNumClasses; ++c) by.push_back({-item_ns[c], c});
+  std::stable_sort(by.begin(), by.end());
+  cand[1] = cand[0];
+  for (int k = 0; k < kNumClasses; ++k) cand[1].order[k] = by[k].second;
+  for (int v = 2; v < kTuneCandidates; ++v) {
+    cand[v] = cand[1];
+    const double target = total_ns / waves / (v == 2 ? 2.0 : 4.0);
+    std::vector<std::pair<double, int>> by2;
+    for (int c = 0; c < kNumClasses; ++c) {
+      int sl = 1;
+      while (sl < kMaxSlices && item_ns[c] / sl > target && p->n_nuc >= 2 * sl) sl *= 2;
+      cand[v].slices[c] = sl;
+      by2.push_back({-item_ns[c] / sl, c});
+    }
+    std::stable_sort(by2.begin(), by2.end());
+    for (int k = 0; k < kNumClasses; ++k) cand[v].order[k] = by2[k].second;
+  }
+  // 3. time each candidate, keep the fastest
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    p->meta = base;
+    (void)upload_args(p, nullptr);
+    return fail(ctx, SHGO_ERR_DEVICE, "hipEventCreate failed");
+  }
+  int best = 0;
+  double best_ms = 0.0;
+  for (int v = 0; v < kTuneCandidates && e == hipSuccess; ++v) {
+    p->meta = cand[v];
+    e = upload_args(p, nullptr);
+    if (e != hipSuccess) break;
+    enqueue(p, out, st, false);  // warm
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < rounds; ++r) enqueue(p, out, st, false);
+    (void)hipEventRecord(e1, st);
+    e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    const double per = (double)t / rounds;
+    if (ms) ms[v] = per;
+    if (v == 0 || per < best_ms) {
+      best = v;
+      best_ms = per;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->meta = e == hipSuccess ? cand[best] : base;
+  const hipError_t e2 = upload_args(p, nullptr);
+  if (e != hipSuccess || e2 != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "tuning runs failed");
+  if (chosen) *chosen = best;
   return SHGO_OK;
 }
 
@@ -1399,6 +1576,36 @@ shgo_status shgo_execute_grad(shgo_plan* p, const double* D, double* dE_dnuclei,
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return SHGO_OK;
+}
+
+shgo_status shgo_plan_get_schedule(const shgo_plan* p, int32_t* order, int32_t* slices) {
+  if (!p || !order || !slices) return SHGO_ERR_INVALID_ARG;
+  for (int k = 0; k < kNumClasses; ++k) {
+    order[k] = p->meta.order[k];
+    slices[k] = p->meta.slices[k];
+  }
+  return SHGO_OK;
+}
+
+shgo_status shgo_plan_set_schedule(shgo_plan* p, const int32_t* order, const int32_t* slices) {
+  if (!p || !order || !slices) return SHGO_ERR_INVALID_ARG;
+  bool seen[kNumClasses] = {false};
+  for (int k = 0; k < kNumClasses; ++k) {
+    if (order[k] < 0 || order[k] >= kNumClasses || seen[order[k]])
+      return fail(p->ctx, SHGO_ERR_INVALID_ARG, "order must be a permutation of the class ids");
+    seen[order[k]] = true;
+    if (slices[k] != 1 && slices[k] != 2 && slices[k] != 4)
+      return fail(p->ctx, SHGO_ERR_INVALID_ARG, "slices must be 1, 2 or 4");
+  }
+  if (hipSetDevice(p->ctx->device) != hipSuccess) return fail(p->ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+  for (int k = 0; k < kNumClasses; ++k) {
+    p->meta.order[k] = order[k];
+    p->meta.slices[k] = slices[k];
+  }
+  drop_graph(p);
+  const hipError_t e = upload_args(p, nullptr);
+  if (e != hipSuccess) return fail(p->ctx, SHGO_ERR_DEVICE, std::string("upload failed: ") + hipGetErrorString(e));
   return SHGO_OK;
 }
 

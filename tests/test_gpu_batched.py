@@ -1,0 +1,129 @@
+"""Batched launch: graph capture, nucleus slicing, schedules and the autotuner, on screened
+contracted molecules, against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_16245_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-11, 1e-13
+
+
+@pytest.fixture(scope="module")
+def shgo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_16245_amd as m
+    m.load_library()
+    return m
+
+
+def assert_parity(got, ref, what):
+    err = np.abs(got - ref)
+    bad = err > ATOL + RTOL * np.abs(ref)
+    assert not bad.any(), f"{what}: {int(bad.sum())} elements off, max abs err {err.max():.3e}"
+
+
+def _plan(shgo, b, n, screen):
+    import torch
+    plan = shgo.shgo_plan_matrix(shgo.context(0), b, n, screen)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
+    return plan, out
+
+
+@pytest.fixture(scope="module")
+def molecule():
+    b, n = synth.molecule(seed=61, n_atoms=12, box=9.0, ls=(0, 1, 2, 3, 4), kmax=6)
+    return b, n, oracle.nuc_matrix(b, n, screen=1e-12).reshape(-1)
+
+
+def test_graph_replays_match_eager(shgo, molecule):
+    import torch
+    b, n, ref = molecule
+    plan, out_e = _plan(shgo, b, n, 1e-12)
+    shgo.shgo_execute(plan, out_e)
+    torch.cuda.synchronize()
+    eager = out_e.cpu().numpy()
+    assert_parity(eager, ref, "eager")
+    out_g = torch.full_like(out_e, float("nan"))
+    other = torch.empty_like(out_e)
+    for r in range(3):
+        shgo.shgo_execute_graph(plan, out_g)
+        torch.cuda.synchronize()
+        got = out_g.cpu().numpy()
+        assert not np.isnan(got).any(), f"replay {r}: {int(np.isnan(got).sum())} elements not written"
+        # the integral kernel adds group contributions atomically: equal up to rounding order
+        d = np.abs(got - eager)
+        assert np.all(d <= 1e-13 + 1e-12 * np.abs(eager)), f"replay {r}: max diff {d.max():.3e}"
+        assert_parity(got, ref, f"replay {r}")
+        out_g.fill_(float("nan"))
+        shgo.shgo_execute(plan, other)  # eager work between replays
+        torch.cuda.synchronize()
+        assert_parity(other.cpu().numpy(), ref, f"eager after replay {r}")
+
+
+@pytest.mark.parametrize("sl", [2, 4])
+def test_nucleus_slices_and_order(shgo, molecule, sl):
+    import torch
+    b, n, ref = molecule
+    plan, out = _plan(shgo, b, n, 1e-12)
+    order = np.random.default_rng(sl).permutation(28).astype(np.int32)
+    shgo.shgo_plan_set_schedule(plan, order, np.full(28, sl, np.int32))
+    o2, s2 = shgo.shgo_plan_get_schedule(plan)
+    assert np.array_equal(o2, order) and np.all(s2 == sl)
+    shgo.shgo_execute(plan, out)
+    torch.cuda.synchronize()
+    assert_parity(out.cpu().numpy(), ref, f"{sl} slices")
+
+
+def test_schedule_validation(shgo, molecule):
+    b, n, _ = molecule
+    plan, _ = _plan(shgo, b, n, 1e-12)
+    with pytest.raises(shgo.ShgoError) as e:
+        shgo.shgo_plan_set_schedule(plan, np.zeros(28, np.int32), np.ones(28, np.int32))
+    assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
+    with pytest.raises(shgo.ShgoError) as e:
+        shgo.shgo_plan_set_schedule(plan, np.arange(28, dtype=np.int32), np.full(28, 3, np.int32))
+    assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
+
+
+def test_autotune_keeps_results(shgo, molecule):
+    import torch
+    b, n, ref = molecule
+    plan, out = _plan(shgo, b, n, 1e-12)
+    ms, chosen = shgo.shgo_plan_autotune(plan, out, rounds=2)
+    assert 0 <= chosen < shgo.SHGO_TUNE_CANDIDATES and np.all(ms > 0)
+    assert ms[chosen] == ms.min()
+    out.fill_(float("nan"))
+    shgo.shgo_execute_graph(plan, out)
+    torch.cuda.synchronize()
+    assert_parity(out.cpu().numpy(), ref, "after tuning, graph")
+
+
+def test_batched_workload_sampled(shgo):
+    """The batched workload at full size (200 atoms, l <= 4, K <= 8, screened): every element of
+    a sample of shell pairs against the oracle, and exact symmetry."""
+    import torch
+    b, n = synth.batched_molecule(seed=3)
+    plan, out = _plan(shgo, b, n, 1e-12)
+    shgo.shgo_plan_autotune(plan, out, rounds=1)
+    shgo.shgo_execute_graph(plan, out)
+    torch.cuda.synchronize()
+    nbf = b.nbf()
+    V = out.cpu().numpy().reshape(nbf, nbf)
+    assert np.array_equal(V, V.T)
+    rng = np.random.default_rng(3)
+    pa, pb = synth.all_pairs(b.n_shells)
+    # half the sample from pairs on nearby atoms (large blocks), half uniform
+    d = np.linalg.norm(b.center[pa] - b.center[pb], axis=1)
+    near = np.nonzero(d < 3.0)[0]
+    sel = np.concatenate([rng.choice(near, 40, replace=False), rng.choice(len(pa), 40, replace=False)])
+    ref = oracle.split_blocks(oracle.nuc_blocks(b, n, pa[sel], pb[sel], screen=1e-12), b, pa[sel], pb[sel])
+    off = b.shell_offsets()
+    for i, k in enumerate(sel):
+        a, c = pa[k], pb[k]
+        blk = V[off[a]:off[a] + 2 * b.l[a] + 1, off[c]:off[c] + 2 * b.l[c] + 1]
+        assert_parity(blk, ref[i], f"pair ({a}, {c})")
