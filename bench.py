@@ -166,6 +166,66 @@ def cpu_baseline(basis, nuclei, pa, pb, target_s):
 
 
 # ----------------------------------------------------------------------------------------------
+# the batched and gradient forms, measured beside the plain line
+# ----------------------------------------------------------------------------------------------
+def _time_ms(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def measure_batched(shgo, synth, torch, steps):
+    """200-atom molecule (l <= 4, K 1..8, screened 1e-12), full V: autotuned schedule, one
+    hipGraph-captured evaluation per step."""
+    basis, nuclei = synth.batched_molecule(seed=3)
+    screen = 1e-12
+    ctx = shgo.context(0)
+    plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, screen)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
+    ms_eager = _time_ms(torch, lambda: shgo.shgo_execute(plan, out), steps, 2)
+    tune_ms, chosen = shgo.shgo_plan_autotune(plan, out, rounds=3)
+    ms = _time_ms(torch, lambda: shgo.shgo_execute_graph(plan, out), steps, 2)
+    pa, pb = synth.all_pairs(basis.n_shells)
+    _, flops = workload_flops(basis, nuclei, pa, pb, screen)
+    return {"workload": "200 atoms, 20-bohr box, l=0..4, K uniform 1..8, screened exp(-mu R^2) > 1e-12, full V, "
+                        "seed 3; autotuned schedule, hipGraph replay",
+            "nbf": basis.nbf(), "integrals_per_step": plan.integrals, "ms_per_step": ms,
+            "integrals_per_s": plan.integrals / (ms * 1e-3), "ms_per_step_eager_untuned": ms_eager,
+            "tune_candidates_ms": [float(x) for x in tune_ms], "tune_chosen": chosen,
+            "model_flops_per_step": flops, "fp64_model_tflops": flops / (ms * 1e-3) / 1e12,
+            "fp64_vector_peak_frac": flops / (ms * 1e-3) / FP64_VECTOR_PEAK}
+
+
+def measure_gradient(shgo, synth, torch, steps):
+    """500-atom molecule (l <= 3, K 1..6, screened 1e-12): dE/dR_nuclei and dE/dR_centers of
+    E = sum D V with a random symmetric D, by the adjoint kernel; the forward V beside it."""
+    basis, nuclei = synth.gradient_molecule(seed=5)
+    screen = 1e-12
+    D = torch.as_tensor(synth.density(basis.nbf(), seed=5), device="cuda")
+    ctx = shgo.context(0)
+    plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, screen)
+    dn = torch.empty((nuclei.n, 3), dtype=torch.float64, device="cuda")
+    dc = torch.empty((basis.n_shells, 3), dtype=torch.float64, device="cuda")
+    e = torch.empty(1, dtype=torch.float64, device="cuda")
+    ms_grad = _time_ms(torch, lambda: shgo.shgo_execute_grad(plan, D, dn, dc, e), steps, 1)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
+    ms_fwd = _time_ms(torch, lambda: shgo.shgo_execute(plan, out), steps, 1)
+    total = (dn.sum(0) + dc.sum(0)).abs().max().item()
+    scale = max(dn.abs().max().item(), dc.abs().max().item())
+    return {"workload": "500 atoms, 30-bohr box, l=0..3, K uniform 1..6, screened 1e-12, D iid N(0, 0.1^2) "
+                        "symmetric, seed 5", "nbf": basis.nbf(), "nuclei": nuclei.n,
+            "ms_per_gradient": ms_grad, "ms_per_forward": ms_fwd, "energy": e.item(),
+            "translation_sum_rule_rel": total / scale}
+
+
+# ----------------------------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +234,7 @@ def main():
     ap.add_argument("--workload", default="high_l_sweep", choices=["high_l_sweep", "small_molecule", "batched"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and gradient forms")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes (calibrates HBM counters)")
     args = ap.parse_args()
@@ -262,6 +323,11 @@ def main():
            "integrals_per_step": plan.integrals,
            "fp64_model_tflops": step_tflops, "fp64_vector_peak_frac": step_tflops / (FP64_VECTOR_PEAK / 1e12),
            "pair_build_ms": avg_phase_ms[0], "roofline": roofline}
+    if not args.no_forms and args.workload == "high_l_sweep":
+        log("bench: batched form")
+        res["batched"] = measure_batched(shgo, synth, torch, max(3, args.steps // 2))
+        log("bench: gradient form")
+        res["gradient"] = measure_gradient(shgo, synth, torch, 3)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(basis, nuclei, pa, pb, args.cpu_seconds)
