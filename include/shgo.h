@@ -136,22 +136,26 @@ shgo_status shgo_execute_grad(shgo_plan* plan, const double* D, double* dE_dnucl
  * nodes (buffers are cleared by fill kernels) and no timing events. */
 shgo_status shgo_execute_graph(shgo_plan* plan, double* out, void* stream);
 
-/* Work schedule of the persistent launch, one entry per class id c = la(la+1)/2 + lb (la >= lb):
- * order[28], the queue order of the classes (a permutation of 0..27; the queue hands out items
- * longest first when the order is by decreasing item time), and slices[c] in {1, 2, 4}, the
- * number of nucleus slices each (tile, group) item of class c is cut into (the slices' partial
- * sums are coupled and added separately; the sum is the same up to rounding). get copies the
- * plan's schedule out; set validates (SHGO_ERR_INVALID_ARG) and installs one, e.g. a schedule
- * saved from an earlier autotune of the same workload. */
+/* Work schedule of the persistent launch, one entry per class id c = la(la+1)/2 + lb (la >= lb).
+ * A work item is a block of tiles[c] tiles of 64 class-sorted shell pairs, run by one workgroup
+ * (eight wavefronts take its (tile, group) tasks and add into one LDS accumulator).
+ *   order[28]  queue order of the classes (a permutation of 0..27; longest items first when the
+ *              order is by decreasing time per tile)
+ *   tiles[28]  tiles per work item of each class, 1 <= tiles[c] <= shgo_max_tiles(c) (the LDS
+ *              accumulator holds tiles x (2la+1)(2lb+1) x 64 doubles, at most 152 KB)
+ * get copies the plan's schedule out; set validates (SHGO_ERR_INVALID_ARG) and installs one, e.g. a
+ * schedule saved from an earlier autotune of the same workload. Results do not depend on the
+ * schedule beyond rounding. */
 #define SHGO_NUM_CLASSES 28
-shgo_status shgo_plan_get_schedule(const shgo_plan* plan, int32_t* order, int32_t* slices);
-shgo_status shgo_plan_set_schedule(shgo_plan* plan, const int32_t* order, const int32_t* slices);
+int32_t shgo_max_tiles(int32_t class_id); /* -1 for an invalid class id */
+shgo_status shgo_plan_get_schedule(const shgo_plan* plan, int32_t* order, int32_t* tiles);
+shgo_status shgo_plan_set_schedule(shgo_plan* plan, const int32_t* order, const int32_t* tiles);
 
-/* Autotuner of the batched launch. Runs the plan once with per-item timing to measure the mean
- * item time of every class, builds SHGO_TUNE_CANDIDATES schedules -- 0: the model order, no
- * slices; 1: classes by measured item time; 2, 3: measured order with the longest items split
- * into nucleus slices so that none exceeds 1/2 (2) or 1/4 (3) of the mean work per wavefront --
- * times `rounds` executions of each on `stream` (the call synchronizes the stream), and keeps the
+/* Autotuner of the batched launch. Runs the plan once with per-item timing to measure each
+ * class's time per tile, builds SHGO_TUNE_CANDIDATES schedules -- 0: the model order with the
+ * default tiles per item; 1: classes by measured time per tile; 2: the measured order with the
+ * largest tile blocks the LDS allows; 3: the measured order with one tile per item -- times
+ * `rounds` executions of each on `stream` (the call synchronizes the stream), and keeps the
  * fastest. ms[SHGO_TUNE_CANDIDATES] (or NULL) receives each candidate's milliseconds per
  * execution, *chosen (or NULL) the index kept. `out` is written as by shgo_execute. */
 #define SHGO_TUNE_CANDIDATES 4

@@ -30,7 +30,7 @@ EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_erro
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
             "shgo_plan_integrals", "shgo_execute", "shgo_execute_graph", "shgo_execute_grad", "shgo_boys",
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
-            "shgo_plan_autotune"]
+            "shgo_plan_autotune", "shgo_max_tiles"]
 SHGO_NUM_CLASSES = 28
 SHGO_TUNE_CANDIDATES = 4
 SHGO_NUM_PHASES = 2
@@ -96,6 +96,8 @@ def load_library(path=LIB_PATH):
     lib.shgo_plan_get_schedule.restype = ctypes.c_int
     lib.shgo_plan_set_schedule.argtypes = [vp, vp, vp]
     lib.shgo_plan_set_schedule.restype = ctypes.c_int
+    lib.shgo_max_tiles.argtypes = [i32]
+    lib.shgo_max_tiles.restype = i32
     lib.shgo_plan_autotune.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.shgo_plan_autotune.restype = ctypes.c_int
     lib.shgo_execute_grad.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -255,22 +257,27 @@ def shgo_execute_graph(plan, out, stream=None):
     return out
 
 
+def shgo_max_tiles(class_id):
+    """Largest tiles-per-item the LDS accumulator allows for a class (-1 if invalid)."""
+    return int(load_library().shgo_max_tiles(int(class_id)))
+
+
 def shgo_plan_get_schedule(plan):
-    """(order[28], slices[28]) of the plan's persistent launch."""
+    """(order[28], tiles[28]) of the plan's persistent launch."""
     lib = load_library()
     order = np.zeros(SHGO_NUM_CLASSES, dtype=np.int32)
-    slices = np.zeros(SHGO_NUM_CLASSES, dtype=np.int32)
-    _check(lib, plan.ctx, lib.shgo_plan_get_schedule(plan.handle, order.ctypes.data, slices.ctypes.data))
-    return order, slices
+    tiles = np.zeros(SHGO_NUM_CLASSES, dtype=np.int32)
+    _check(lib, plan.ctx, lib.shgo_plan_get_schedule(plan.handle, order.ctypes.data, tiles.ctypes.data))
+    return order, tiles
 
 
-def shgo_plan_set_schedule(plan, order, slices):
+def shgo_plan_set_schedule(plan, order, tiles):
     lib = load_library()
     order = np.ascontiguousarray(order, dtype=np.int32)
-    slices = np.ascontiguousarray(slices, dtype=np.int32)
-    if order.shape != (SHGO_NUM_CLASSES,) or slices.shape != (SHGO_NUM_CLASSES,):
-        raise ValueError("order and slices need one entry per class (28)")
-    _check(lib, plan.ctx, lib.shgo_plan_set_schedule(plan.handle, order.ctypes.data, slices.ctypes.data))
+    tiles = np.ascontiguousarray(tiles, dtype=np.int32)
+    if order.shape != (SHGO_NUM_CLASSES,) or tiles.shape != (SHGO_NUM_CLASSES,):
+        raise ValueError("order and tiles need one entry per class (28)")
+    _check(lib, plan.ctx, lib.shgo_plan_set_schedule(plan.handle, order.ctypes.data, tiles.ctypes.data))
 
 
 def shgo_plan_autotune(plan, out, rounds=5, stream=None):

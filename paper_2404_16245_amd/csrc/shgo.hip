@@ -45,7 +45,9 @@ constexpr int kNumClasses = (SHGO_LMAX + 1) * (SHGO_LMAX + 2) / 2;  // (la, lb) 
 constexpr int kKeysPerClass = 256;
 constexpr int kTile = SHGO_TILE;
 constexpr int kNumKeys = kNumClasses * kKeysPerClass;
-constexpr int kIntegralThreads = 512;  // one workgroup per CU: 2 waves per SIMD share the LDS table
+constexpr int kIntegralThreads = 512;  // one workgroup per CU: 8 wavefronts share a tile's accumulator
+constexpr int kAccDoubles = 19456;     // LDS accumulator of a work item (152 KB): tiles x NA*NB x 64
+constexpr int kMaxTilesPerItem = 8;
 constexpr int kPrefetchMaxW = 32;      // groups up to this many W doubles prefetch the next nucleus
 
 __host__ __device__ constexpr int class_id(int la, int lb) { return la * (la + 1) / 2 + lb; }
@@ -57,8 +59,6 @@ struct alignas(32) Nuc {
 // constant address space lets the compiler use scalar loads.
 typedef const __attribute__((address_space(4))) Nuc* NucPtr;
 
-// Boys table staged in LDS by every workgroup of the integral kernel (84.6 KB).
-__shared__ double s_boys[kBoysPoints * kBoysOrders];
 
 __device__ __forceinline__ NucPtr uniform_nuclei(const Nuc* p) {
   const uint64_t v = (uint64_t)p;
@@ -328,18 +328,28 @@ __global__ void k_scatter(DevBasis bs, DevPairs pr) {
 // ---------------------------------------------------------------------------------------------
 // a2-a8: the persistent integral kernel
 // ---------------------------------------------------------------------------------------------
-// Work item = (class, tile of SHGO_TILE class-sorted shell pairs, group of |M| families). Every
-// wavefront pulls items from one queue (classes in decreasing cost per tile), runs the group's
-// primitive-pair and nucleus loops for the tile's pairs (one pair per lane) and adds its part of
-// each block V' to the tile's accumulator in HBM with atomic adds. The wavefront that completes
-// the last group of a tile rotates the tile's blocks back to the laboratory frame and writes them.
+// Work item = (class, block of up to T tiles of SHGO_TILE class-sorted shell pairs). Every
+// workgroup (one per CU, eight wavefronts) pulls items from one queue (classes in decreasing cost
+// per tile). Its wavefronts take the item's (tile, group of half-families) tasks from an LDS
+// counter, run the group's primitive-pair and nucleus loops for the tile's pairs (one pair per
+// lane) and add the group's part of each block V' into the item's accumulator in LDS. After a
+// workgroup barrier each tile's blocks are rotated back to the laboratory frame and written.
+// Nothing crosses a workgroup: no global atomics on partial sums and no device-scope fences.
 struct ClassMeta {
-  int32_t order[kNumClasses];      // queue order: classes by decreasing cost per tile
-  int64_t vacc_base[kNumClasses];  // first accumulator double of each class
-  int32_t tile_base[kNumClasses];  // first tile counter of each class
-  int32_t slices[kNumClasses];     // nucleus slices per (tile, group) item: 1, 2 or 4
+  int32_t order[kNumClasses];  // queue order: classes by decreasing cost per tile
+  int32_t tiles[kNumClasses];  // tiles per work item, 1..8, within the LDS accumulator
 };
-constexpr int kMaxSlices = 4;
+
+__host__ __device__ constexpr int class_nab(int c) {
+  int la = 0;
+  while ((la + 1) * (la + 2) / 2 <= c) ++la;
+  const int lb = c - la * (la + 1) / 2;
+  return (2 * la + 1) * (2 * lb + 1);
+}
+__host__ __device__ constexpr int class_max_tiles(int c) {
+  return kAccDoubles / (class_nab(c) * SHGO_TILE) < kMaxTilesPerItem ? kAccDoubles / (class_nab(c) * SHGO_TILE)
+                                                                      : kMaxTilesPerItem;
+}
 
 struct WorkArgs {
   DevBasis bs;
@@ -347,8 +357,6 @@ struct WorkArgs {
   const Nuc* __restrict__ nuc;
   int32_t n_nuc;
   const double* __restrict__ boys_tab;
-  double* __restrict__ vacc;       // tile accumulators: [tile][NA*NB][SHGO_TILE]
-  int32_t* __restrict__ tile_cnt;  // groups finished per tile
   int32_t* __restrict__ queue;     // [0]: next work item
   int32_t* __restrict__ item_off;  // [kNumClasses + 1]: prefix of items per class in queue order
   unsigned long long* __restrict__ item_ns;  // per-item durations (10 ns ticks) when tuning, else null
@@ -443,7 +451,7 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_
         nt = p * nr2;
         nZ = nucs[c].Z;
         const int i = min((int)(nt * 16.0 + 0.5), kBoysPoints - 1);
-        const double* __restrict__ r = s_boys + i * kBoysOrders + LM;
+        const double* __restrict__ r = wa->boys_tab + i * kBoysOrders + LM;
 #pragma unroll
         for (int k = 0; k < 8; ++k) nrow[k] = r[k];
       };
@@ -535,8 +543,6 @@ __device__ __forceinline__ void finish_tile(const PairState& ps, WAP wa, double*
 #pragma unroll
     for (int j = 0; j < NB; ++j) Vp[(r * NB + j) * kTile] = v[j];
   }
-  // the rotated rows must be read back from L2, not from a stale vector-L1 line
-  __threadfence();
   for (int col = 0; col < NB; ++col) {
     double v[NA];
 #pragma unroll
@@ -576,24 +582,10 @@ __device__ __forceinline__ void finish_tile(const PairState& ps, WAP wa, double*
   }
 }
 
-// One work item of class (LA, LB): tile j / Q, group j % Q. Kept out of line so that every
-// class is compiled and register-allocated on its own.
-template <int LA, int LB>
-__device__ __attribute__((noinline)) void process_item(int j, const WorkArgs* wa_ptr, double* __restrict__ out) {
-  const WAP wa = uniform_args(wa_ptr);
-  constexpr int Q = ClassInfo<LA, LB>::Q;
-  constexpr int NAB = (2 * LA + 1) * (2 * LB + 1);
-  constexpr int cls = class_id(LA, LB);
-  const int lane = threadIdx.x & 63;
-  const int S = wa->meta.slices[cls];
-  const int tile = j / (Q * S), rem = j - tile * Q * S, g = rem / S, sl_i = rem - g * S;
-  const int n_nuc = wa->n_nuc;
-  const int c0 = (int)((int64_t)n_nuc * sl_i / S), c1 = (int)((int64_t)n_nuc * (sl_i + 1) / S);
-  const int start = wa->pr.key_off[cls * kKeysPerClass];
-  const int end = wa->pr.key_off[(cls + 1) * kKeysPerClass];
-  const int slot = start + tile * kTile + lane;
+extern __shared__ double s_acc[];  // the work item's accumulator [tile][NA*NB][SHGO_TILE]
 
-  PairState ps;
+template <int LA, int LB>
+__device__ __forceinline__ void load_pair(PairState& ps, WAP wa, int slot, int end) {
   ps.active = slot < end;
   const int sl = ps.active ? slot : end - 1;
   ps.s1 = wa->pr.s1[sl];
@@ -609,73 +601,102 @@ __device__ __attribute__((noinline)) void process_item(int j, const WorkArgs* wa
   ps.K1 = wa->bs.nprim[ps.s1];
   ps.K2 = wa->bs.nprim[ps.s2];
   frame_of(ps);
-  // primitive-pair iterations of this wavefront (keys saturate at 255; then every candidate
-  // primitive pair is visited and the screened ones skipped)
-  int iters = ps.active ? (ps.nsurv >= kKeysPerClass - 1 ? ps.K1 * ps.K2 : ps.nsurv) : 0;
+}
+
+// One work item of class (LA, LB): tile block b, run by the whole workgroup. Kept out of line
+// so that every class is compiled and register-allocated on its own.
+template <int LA, int LB>
+__device__ __attribute__((noinline)) void process_block(int b, const WorkArgs* wa_ptr, double* __restrict__ out,
+                                                        int* task_ctr) {
+  const WAP wa = uniform_args(wa_ptr);
+  constexpr int Q = ClassInfo<LA, LB>::Q;
+  constexpr int NAB = (2 * LA + 1) * (2 * LB + 1);
+  constexpr int cls = class_id(LA, LB);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int T = wa->meta.tiles[cls];
+  const int start = wa->pr.key_off[cls * kKeysPerClass];
+  const int end = wa->pr.key_off[(cls + 1) * kKeysPerClass];
+  const int tiles = (end - start + kTile - 1) / kTile;
+  const int t0 = b * T, nt = min(T, tiles - t0);
+  for (int i = threadIdx.x; i < nt * NAB * kTile; i += blockDim.x) s_acc[i] = 0.0;
+  __syncthreads();
+  // (tile, group) tasks, tile-major, handed to the wavefronts by an LDS counter
+  const int n_nuc = wa->n_nuc;
+  while (true) {
+    int task = 0;
+    if (lane == 0) task = atomicAdd(task_ctr, 1);
+    task = __shfl(task, 0);
+    if (task >= nt * Q) break;
+    const int t = task / Q, g = task - t * Q;
+    PairState ps;
+    load_pair<LA, LB>(ps, wa, start + (t0 + t) * kTile + lane, end);
+    // primitive-pair iterations of this wavefront (keys saturate at 255; then every candidate
+    // primitive pair is visited and the screened ones skipped)
+    int iters = ps.active ? (ps.nsurv >= kKeysPerClass - 1 ? ps.K1 * ps.K2 : ps.nsurv) : 0;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) iters = max(iters, __shfl_xor(iters, off));
-
-  double* Vp = wa->vacc + wa->meta.vacc_base[cls] + (int64_t)tile * NAB * kTile + lane;
-  dispatch_group<LA, LB, 0>(g, ps, wa, iters, c0, c1, Vp);
-
-  // completion: release this group's atomic adds, count it, and let the last group finish
-  int done = 0;
-  if (lane == 0)
-    done = __hip_atomic_fetch_add(wa->tile_cnt + wa->meta.tile_base[cls] + tile, 1, __ATOMIC_ACQ_REL,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  done = __shfl(done, 0);
-  if (done == Q * S - 1) {
-    __threadfence();
-    finish_tile<LA, LB>(ps, wa, out, slot, Vp);
+    for (int off = 32; off > 0; off >>= 1) iters = max(iters, __shfl_xor(iters, off));
+    dispatch_group<LA, LB, 0>(g, ps, wa, iters, 0, n_nuc, s_acc + t * NAB * kTile + lane);
+  }
+  __syncthreads();
+  // every tile of the block back to the laboratory frame, one wavefront per tile
+  for (int t = wave; t < nt; t += kIntegralThreads / 64) {
+    PairState ps;
+    const int slot = start + (t0 + t) * kTile + lane;
+    load_pair<LA, LB>(ps, wa, slot, end);
+    finish_tile<LA, LB>(ps, wa, out, slot, s_acc + t * NAB * kTile + lane);
   }
 }
 
 template <int LA, int LB>
-__device__ __forceinline__ void dispatch_class(int c, int j, const WorkArgs* wa, double* out) {
+__device__ __forceinline__ void dispatch_class(int c, int j, const WorkArgs* wa, double* out, int* task_ctr) {
   if constexpr (LA <= SHGO_LMAX) {
     if (c == class_id(LA, LB)) {
-      process_item<LA, LB>(j, wa, out);
+      process_block<LA, LB>(j, wa, out, task_ctr);
       return;
     }
     if constexpr (LB < LA)
-      dispatch_class<LA, LB + 1>(c, j, wa, out);
+      dispatch_class<LA, LB + 1>(c, j, wa, out, task_ctr);
     else
-      dispatch_class<LA + 1, 0>(c, j, wa, out);
+      dispatch_class<LA + 1, 0>(c, j, wa, out, task_ctr);
   }
 }
 
-// Queue layout: for the k-th class in queue order, its tiles x groups x slices items, tile-major.
+// Queue layout: for the k-th class in queue order, its tile blocks (tiles[c] tiles each).
 __global__ void k_items(DevPairs pr, ClassMeta meta, int32_t* item_off) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int off = 0;
   for (int k = 0; k < kNumClasses; ++k) {
     const int c = meta.order[k];
     const int count = pr.key_off[(c + 1) * kKeysPerClass] - pr.key_off[c * kKeysPerClass];
+    const int tiles = (count + kTile - 1) / kTile;
     item_off[k] = off;
-    off += (count + kTile - 1) / kTile * kClassGroups[c] * meta.slices[c];
+    off += (tiles + meta.tiles[c] - 1) / meta.tiles[c];
   }
   item_off[kNumClasses] = off;
 }
 
-// Every wavefront loops: take the next item, run it; the loop ends once the queue is drained.
+// Every workgroup loops: take the next item, run it with its eight wavefronts; the loop ends
+// once the queue is drained.
 __global__ void __launch_bounds__(kIntegralThreads) __attribute__((amdgpu_waves_per_eu(2)))
 k_integrals(const WorkArgs* __restrict__ wa_ptr, double* __restrict__ out) {
   const WAP wa = uniform_args(wa_ptr);
-  for (int i = threadIdx.x; i < kBoysPoints * kBoysOrders; i += blockDim.x) s_boys[i] = wa->boys_tab[i];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
+  __shared__ int s_item, s_task;
   const int total = wa->item_off[kNumClasses];
   while (true) {
-    int item = 0;
-    if (lane == 0) item = atomicAdd(wa->queue, 1);
-    item = __shfl(item, 0);
+    if (threadIdx.x == 0) {
+      s_item = atomicAdd(wa->queue, 1);
+      s_task = 0;
+    }
+    __syncthreads();
+    const int item = s_item;
     if (item >= total) break;
     int k = 0;
     while (wa->item_off[k + 1] <= item) ++k;
     unsigned long long* const tick = wa->item_ns;
     const unsigned long long t0 = tick ? wall_clock64() : 0ull;
-    dispatch_class<0, 0>(wa->meta.order[k], item - wa->item_off[k], wa_ptr, out);
-    if (tick && lane == 0) tick[item] = wall_clock64() - t0;
+    dispatch_class<0, 0>(wa->meta.order[k], item - wa->item_off[k], wa_ptr, out, &s_task);
+    if (tick && threadIdx.x == 0) tick[item] = wall_clock64() - t0;
+    __syncthreads();
   }
 }
 
@@ -993,10 +1014,7 @@ struct shgo_plan {
   Nuc* nuc = nullptr;
   // persistent-kernel workspace
   ClassMeta meta{};
-  double* vacc = nullptr;
-  int64_t vacc_len = 0;
-  int32_t* tile_cnt = nullptr;  // [n_tiles] tile counters, then the queue head
-  int64_t n_tiles = 0;
+  int32_t* queue = nullptr;  // head of the persistent kernel's work queue
   int32_t* item_off = nullptr;
   WorkArgs* d_wa = nullptr;  // the integral kernel's arguments, in device memory
   double* d_energy = nullptr;  // gradient: E when the caller does not ask for it
@@ -1072,8 +1090,7 @@ int64_t total_prims(const shgo_basis* b) {
 // The integral kernel's arguments (device copy, read through the scalar cache). item_ns turns the
 // per-item timing of the kernel on (tuning runs) or off (null).
 hipError_t upload_args(shgo_plan* p, unsigned long long* item_ns) {
-  const WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, p->ctx->boys_tab, p->vacc, p->tile_cnt,
-                    p->tile_cnt + p->n_tiles, p->item_off, item_ns, p->meta};
+  const WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, p->ctx->boys_tab, p->queue, p->item_off, item_ns, p->meta};
   return hipMemcpy(p->d_wa, &wa, sizeof(WorkArgs), hipMemcpyHostToDevice);
 }
 
@@ -1081,9 +1098,20 @@ hipError_t upload_args(shgo_plan* p, unsigned long long* item_ns) {
 int64_t max_items(const shgo_plan* p) {
   int64_t n = 0;
   for (int c = 0; c < kNumClasses; ++c)
-    n += ((int64_t)p->class_cand[c] + kTile - 1) / kTile * kClassGroups[c] * p->meta.slices[c];
+    n += (((int64_t)p->class_cand[c] + kTile - 1) / kTile + p->meta.tiles[c] - 1) / p->meta.tiles[c];
   return n;
 }
+
+// LDS accumulator the plan's schedule needs: the largest tiles x NA*NB x 64 over its classes.
+size_t acc_bytes(const shgo_plan* p) {
+  size_t m = sizeof(double);
+  for (int c = 0; c < kNumClasses; ++c)
+    if (p->class_cand[c] > 0) m = std::max(m, sizeof(double) * (size_t)p->meta.tiles[c] * class_nab(c) * kTile);
+  return m;
+}
+
+// Default tiles per work item: enough (tile, group) tasks for the eight wavefronts, within LDS.
+int default_tiles(int c) { return std::max(1, std::min(class_max_tiles(c), (8 + kClassGroups[c] - 1) / kClassGroups[c])); }
 
 // The launches of one evaluation on `st`: pair build (a1), then the persistent integral kernel.
 // With `timed`, HIP events bracket the two phases (never inside a graph capture).
@@ -1096,8 +1124,7 @@ void enqueue(shgo_plan* p, double* out, hipStream_t st, bool timed) {
   };
   mark(0, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks(kNumKeys)), dim3(tb), 0, st, p->pr.key_count, (int64_t)kNumKeys, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(p->n_tiles + 1)), dim3(tb), 0, st, p->tile_cnt, p->n_tiles + 1, 0);
-  hipLaunchKernelGGL(k_fill_f64, dim3(blocks(p->vacc_len)), dim3(tb), 0, st, p->vacc, p->vacc_len);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, p->queue, (int64_t)1, 0);
   if (p->n_shells > 0) hipLaunchKernelGGL(k_prim_weights, dim3(blocks(p->n_shells)), dim3(tb), 0, st, p->bs);
   hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
   hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr);
@@ -1105,7 +1132,8 @@ void enqueue(shgo_plan* p, double* out, hipStream_t st, bool timed) {
   hipLaunchKernelGGL(k_items, dim3(1), dim3(64), 0, st, p->pr, p->meta, p->item_off);
   mark(0, 1);
   mark(1, 0);
-  hipLaunchKernelGGL(k_integrals, dim3(p->ctx->grid), dim3(kIntegralThreads), 0, st, (const WorkArgs*)p->d_wa, out);
+  hipLaunchKernelGGL(k_integrals, dim3(p->ctx->grid), dim3(kIntegralThreads), acc_bytes(p), st,
+                     (const WorkArgs*)p->d_wa, out);
   mark(1, 1);
   if (slot >= 0) p->exec_count++;
 }
@@ -1199,26 +1227,20 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
   e = e != hipSuccess ? e : dalloc(p, &pr.key_count, (size_t)kNumKeys);
   e = e != hipSuccess ? e : dalloc(p, &pr.rank, (size_t)p->n_cand);
   e = e != hipSuccess ? e : dalloc(p, &pr.key_off, (size_t)kNumKeys + 1);
-  // persistent-kernel workspace: tile accumulators sized by the per-class candidate counts,
-  // and the queue order (classes by decreasing cost per tile)
+  // persistent-kernel schedule: tiles per work item and the queue order (classes by decreasing
+  // cost per tile)
   {
     std::vector<std::pair<double, int>> cost;
     for (int la = 0; la <= SHGO_LMAX; ++la)
       for (int lb = 0; lb <= la; ++lb) {
         const int c = class_id(la, lb);
-        const int64_t tiles = ((int64_t)p->class_cand[c] + kTile - 1) / kTile;
-        p->meta.vacc_base[c] = p->vacc_len;
-        p->meta.tile_base[c] = (int32_t)p->n_tiles;
-        p->meta.slices[c] = 1;
-        p->vacc_len += tiles * kTile * (2 * la + 1) * (2 * lb + 1);
-        p->n_tiles += tiles;
+        p->meta.tiles[c] = default_tiles(c);
         cost.push_back({-class_cost(la, lb, n->n_nuclei), c});
       }
     std::stable_sort(cost.begin(), cost.end());
     for (int k = 0; k < kNumClasses; ++k) p->meta.order[k] = cost[k].second;
   }
-  e = e != hipSuccess ? e : dalloc(p, &p->vacc, (size_t)p->vacc_len);
-  e = e != hipSuccess ? e : dalloc(p, &p->tile_cnt, (size_t)p->n_tiles + 1);
+  e = e != hipSuccess ? e : dalloc(p, &p->queue, 1);
   e = e != hipSuccess ? e : dalloc(p, &p->item_off, (size_t)kNumClasses + 1);
   e = e != hipSuccess ? e : dalloc(p, &p->d_wa, 1);
   e = e != hipSuccess ? e : dalloc(p, &p->d_energy, 1);
@@ -1336,8 +1358,11 @@ shgo_status shgo_create(int device, shgo_context** out) {
     return SHGO_ERR_DEVICE;
   }
   int n_cu = 0, per_cu = 0;
-  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrals, kIntegralThreads, 0) != hipSuccess) {
+  if (hipFuncSetAttribute((const void*)k_integrals, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(sizeof(double) * kAccDoubles)) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrals, kIntegralThreads,
+                                                   sizeof(double) * kAccDoubles) != hipSuccess) {
     shgo_destroy(c);
     return SHGO_ERR_DEVICE;
   }
@@ -1451,17 +1476,17 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
   if (p->n_cand == 0) return SHGO_OK;
   hipStream_t st = (hipStream_t)stream;
   drop_graph(p);
-  // 1. one timed run with the model order and no slices: mean duration of each class's items
+  // 1. one timed run with the model order and the default tiles: mean duration of each
+  //    class's items, per tile
   ClassMeta base = p->meta;
-  for (int c = 0; c < kNumClasses; ++c) p->meta.slices[c] = 1;
-  const int64_t nmax = max_items(p) * kMaxSlices;
+  for (int c = 0; c < kNumClasses; ++c) p->meta.tiles[c] = default_tiles(c);
+  const int64_t nmax = max_items(p);
   unsigned long long* ticks = nullptr;
   if (hipMalloc(&ticks, sizeof(unsigned long long) * (size_t)std::max<int64_t>(nmax, 1)) != hipSuccess)
     return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "tuning buffer");
-  std::vector<unsigned long long> th((size_t)nmax);
+  std::vector<unsigned long long> th((size_t)std::max<int64_t>(nmax, 1));
   std::vector<int32_t> ioff(kNumClasses + 1);
   double item_ns[kNumClasses] = {0};
-  int64_t items_of[kNumClasses] = {0};
   hipError_t e = upload_args(p, ticks);
   if (e == hipSuccess) {
     enqueue(p, out, st, false);
@@ -1476,37 +1501,25 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
     (void)upload_args(p, nullptr);
     return fail(ctx, SHGO_ERR_DEVICE, std::string("tuning run failed: ") + hipGetErrorString(e));
   }
-  double total_ns = 0.0;
   for (int k = 0; k < kNumClasses; ++k) {
     const int c = p->meta.order[k];
-    for (int i = ioff[k]; i < ioff[k + 1]; ++i) item_ns[c] += 10.0 * (double)th[(size_t)i];
-    items_of[c] = ioff[k + 1] - ioff[k];
-    total_ns += item_ns[c];
-    if (items_of[c] > 0) item_ns[c] /= (double)items_of[c];
+    double sum = 0.0;
+    for (int i = ioff[k]; i < ioff[k + 1]; ++i) sum += 10.0 * (double)th[(size_t)i];
+    const int n_items = ioff[k + 1] - ioff[k];
+    if (n_items > 0) item_ns[c] = sum / n_items / p->meta.tiles[c];  // per tile
   }
-  // 2. candidates: model order; measured order; measured order with the longest items split
-  //    into nucleus slices so that no item exceeds a share of the mean work per wavefront
-  const double waves = (double)ctx->grid * (kIntegralThreads / 64);
+  // 2. candidates: the model order; classes by measured time per tile; the measured order with
+  //    the largest tile blocks the LDS allows; the measured order with one tile per item
   ClassMeta cand[kTuneCandidates];
-  cand[0] = base;
-  for (int c = 0; c < kNumClasses; ++c) cand[0].slices[c] = 1;
+  for (int v = 0; v < kTuneCandidates; ++v) cand[v] = p->meta;
   std::vector<std::pair<double, int>> by;
   for (int c = 0; c < kNumClasses; ++c) by.push_back({-item_ns[c], c});
   std::stable_sort(by.begin(), by.end());
-  cand[1] = cand[0];
-  for (int k = 0; k < kNumClasses; ++k) cand[1].order[k] = by[k].second;
-  for (int v = 2; v < kTuneCandidates; ++v) {
-    cand[v] = cand[1];
-    const double target = total_ns / waves / (v == 2 ? 2.0 : 4.0);
-    std::vector<std::pair<double, int>> by2;
-    for (int c = 0; c < kNumClasses; ++c) {
-      int sl = 1;
-      while (sl < kMaxSlices && item_ns[c] / sl > target && p->n_nuc >= 2 * sl) sl *= 2;
-      cand[v].slices[c] = sl;
-      by2.push_back({-item_ns[c] / sl, c});
-    }
-    std::stable_sort(by2.begin(), by2.end());
-    for (int k = 0; k < kNumClasses; ++k) cand[v].order[k] = by2[k].second;
+  for (int v = 1; v < kTuneCandidates; ++v)
+    for (int k = 0; k < kNumClasses; ++k) cand[v].order[k] = by[k].second;
+  for (int c = 0; c < kNumClasses; ++c) {
+    cand[2].tiles[c] = class_max_tiles(c);
+    cand[3].tiles[c] = 1;
   }
   // 3. time each candidate, keep the fastest
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1579,29 +1592,33 @@ shgo_status shgo_execute_grad(shgo_plan* p, const double* D, double* dE_dnuclei,
   return SHGO_OK;
 }
 
-shgo_status shgo_plan_get_schedule(const shgo_plan* p, int32_t* order, int32_t* slices) {
-  if (!p || !order || !slices) return SHGO_ERR_INVALID_ARG;
+int32_t shgo_max_tiles(int32_t class_id) {
+  return class_id >= 0 && class_id < kNumClasses ? class_max_tiles(class_id) : -1;
+}
+
+shgo_status shgo_plan_get_schedule(const shgo_plan* p, int32_t* order, int32_t* tiles) {
+  if (!p || !order || !tiles) return SHGO_ERR_INVALID_ARG;
   for (int k = 0; k < kNumClasses; ++k) {
     order[k] = p->meta.order[k];
-    slices[k] = p->meta.slices[k];
+    tiles[k] = p->meta.tiles[k];
   }
   return SHGO_OK;
 }
 
-shgo_status shgo_plan_set_schedule(shgo_plan* p, const int32_t* order, const int32_t* slices) {
-  if (!p || !order || !slices) return SHGO_ERR_INVALID_ARG;
+shgo_status shgo_plan_set_schedule(shgo_plan* p, const int32_t* order, const int32_t* tiles) {
+  if (!p || !order || !tiles) return SHGO_ERR_INVALID_ARG;
   bool seen[kNumClasses] = {false};
   for (int k = 0; k < kNumClasses; ++k) {
     if (order[k] < 0 || order[k] >= kNumClasses || seen[order[k]])
       return fail(p->ctx, SHGO_ERR_INVALID_ARG, "order must be a permutation of the class ids");
     seen[order[k]] = true;
-    if (slices[k] != 1 && slices[k] != 2 && slices[k] != 4)
-      return fail(p->ctx, SHGO_ERR_INVALID_ARG, "slices must be 1, 2 or 4");
+    if (tiles[k] < 1 || tiles[k] > class_max_tiles(k))
+      return fail(p->ctx, SHGO_ERR_INVALID_ARG, "tiles[c] must be within 1..shgo_max_tiles(c)");
   }
   if (hipSetDevice(p->ctx->device) != hipSuccess) return fail(p->ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
   for (int k = 0; k < kNumClasses; ++k) {
     p->meta.order[k] = order[k];
-    p->meta.slices[k] = slices[k];
+    p->meta.tiles[k] = tiles[k];
   }
   drop_graph(p);
   const hipError_t e = upload_args(p, nullptr);

@@ -1,4 +1,4 @@
-"""Batched launch: graph capture, nucleus slicing, schedules and the autotuner, on screened
+"""Batched launch: graph capture, tiles per work item, schedules and the autotuner, on screened
 contracted molecules, against the oracle."""
 import numpy as np
 import pytest
@@ -65,18 +65,21 @@ def test_graph_replays_match_eager(shgo, molecule):
         assert_parity(other.cpu().numpy(), ref, f"eager after replay {r}")
 
 
-@pytest.mark.parametrize("sl", [2, 4])
-def test_nucleus_slices_and_order(shgo, molecule, sl):
+@pytest.mark.parametrize("tiles", ["one", "max", "mixed"])
+def test_tiles_per_item_and_order(shgo, molecule, tiles):
     import torch
     b, n, ref = molecule
     plan, out = _plan(shgo, b, n, 1e-12)
-    order = np.random.default_rng(sl).permutation(28).astype(np.int32)
-    shgo.shgo_plan_set_schedule(plan, order, np.full(28, sl, np.int32))
-    o2, s2 = shgo.shgo_plan_get_schedule(plan)
-    assert np.array_equal(o2, order) and np.all(s2 == sl)
+    tmax = np.array([shgo.shgo_max_tiles(c) for c in range(28)], np.int32)
+    t = {"one": np.ones(28, np.int32), "max": tmax,
+         "mixed": np.minimum(tmax, np.arange(28, dtype=np.int32) % 3 + 1)}[tiles]
+    order = np.random.default_rng(len(tiles)).permutation(28).astype(np.int32)
+    shgo.shgo_plan_set_schedule(plan, order, t)
+    o2, t2 = shgo.shgo_plan_get_schedule(plan)
+    assert np.array_equal(o2, order) and np.array_equal(t2, t)
     shgo.shgo_execute(plan, out)
     torch.cuda.synchronize()
-    assert_parity(out.cpu().numpy(), ref, f"{sl} slices")
+    assert_parity(out.cpu().numpy(), ref, f"tiles {tiles}")
 
 
 def test_schedule_validation(shgo, molecule):
@@ -86,7 +89,10 @@ def test_schedule_validation(shgo, molecule):
         shgo.shgo_plan_set_schedule(plan, np.zeros(28, np.int32), np.ones(28, np.int32))
     assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
     with pytest.raises(shgo.ShgoError) as e:
-        shgo.shgo_plan_set_schedule(plan, np.arange(28, dtype=np.int32), np.full(28, 3, np.int32))
+        shgo.shgo_plan_set_schedule(plan, np.arange(28, dtype=np.int32), np.full(28, 8, np.int32))
+    assert e.value.status == shgo.SHGO_ERR_INVALID_ARG  # (6,6) blocks allow one tile per item
+    with pytest.raises(shgo.ShgoError) as e:
+        shgo.shgo_plan_set_schedule(plan, np.arange(28, dtype=np.int32), np.zeros(28, np.int32))
     assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
 
 

@@ -27,6 +27,16 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(shgo.EXPORTED)
 
 
+def test_max_tiles_follow_the_accumulator():
+    # tiles x (2la+1)(2lb+1) x 64 doubles within 19456, at most 8
+    for la in range(7):
+        for lb in range(la + 1):
+            c = la * (la + 1) // 2 + lb
+            nab = (2 * la + 1) * (2 * lb + 1)
+            assert shgo.shgo_max_tiles(c) == min(8, 19456 // (nab * 64))
+    assert shgo.shgo_max_tiles(28) == -1 and shgo.shgo_max_tiles(-1) == -1
+
+
 def test_status_strings():
     for s in range(7):
         assert shgo.shgo_status_string(s)
