@@ -140,9 +140,10 @@ shgo_status shgo_execute_graph(shgo_plan* plan, double* out, void* stream);
  * A work item is a block of tiles[c] tiles of 64 class-sorted shell pairs, run by one workgroup
  * (eight wavefronts take its (tile, group) tasks and add into one LDS accumulator).
  *   order[28]  queue order of the classes (a permutation of 0..27; longest items first when the
- *              order is by decreasing time per tile)
- *   tiles[28]  tiles per work item of each class, 1 <= tiles[c] <= shgo_max_tiles(c) (the LDS
- *              accumulator holds tiles x (2la+1)(2lb+1) x 64 doubles, at most 152 KB)
+ *              order is by decreasing time per item)
+ *   tiles[28]  tiles per work item of each class, 1 <= tiles[c] <= shgo_max_tiles(c) (the LDS of
+ *              a work item holds per tile (2la+1)(2lb+1) x 65 accumulator doubles and 256 frame
+ *              doubles, at most 20464 doubles in all)
  * get copies the plan's schedule out; set validates (SHGO_ERR_INVALID_ARG) and installs one, e.g. a
  * schedule saved from an earlier autotune of the same workload. Results do not depend on the
  * schedule beyond rounding. */
@@ -153,8 +154,8 @@ shgo_status shgo_plan_set_schedule(shgo_plan* plan, const int32_t* order, const 
 
 /* Autotuner of the batched launch. Runs the plan once with per-item timing to measure each
  * class's time per tile, builds SHGO_TUNE_CANDIDATES schedules -- 0: the model order with the
- * default tiles per item; 1: classes by measured time per tile; 2: the measured order with the
- * largest tile blocks the LDS allows; 3: the measured order with one tile per item -- times
+ * default tiles per item; 1: classes by measured time per item; 2: the measured order with twice
+ * the default tiles where the LDS allows; 3: the measured order with one tile per item -- times
  * `rounds` executions of each on `stream` (the call synchronizes the stream), and keeps the
  * fastest. ms[SHGO_TUNE_CANDIDATES] (or NULL) receives each candidate's milliseconds per
  * execution, *chosen (or NULL) the index kept. `out` is written as by shgo_execute. */

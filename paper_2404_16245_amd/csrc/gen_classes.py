@@ -565,7 +565,7 @@ def emit_group(LA, LB, gi, group):
         blocks.setdefault((abs(t[0]), abs(t[1])), []).append(t)
     o.append(f"  static __device__ __forceinline__ void couple(const double (&W)[NW], const double (&ta)[{LA + 1}],")
     o.append(f"                                                 const double (&tb)[{LB + 1}], double* __restrict__ Vp) {{")
-    o.append("    // Vp: this lane's entry (0, 0) of the tile accumulator; entries are SHGO_TILE apart")
+    o.append("    // Vp: this lane's entry (0, 0) of the tile accumulator; entries are SHGO_ACC_STRIDE apart")
     for (aa, ab), ts in sorted(blocks.items()):
         outs = sorted(set((t[0], t[1]) for t in ts))
         name = {mm: f"v{i}" for i, mm in enumerate(outs)}
@@ -605,7 +605,7 @@ def emit_group(LA, LB, gi, group):
                     o.append(f"        {name[mm]} = fma(ta[{LA - l1}], u{k}, {name[mm]});")
             o.append("      }")
         for mm in outs:
-            o.append(f"      atomicAdd(Vp + {(mm[0] + LA) * NB + (mm[1] + LB)} * SHGO_TILE, {name[mm]});")
+            o.append(f"      atomicAdd(Vp + {(mm[0] + LA) * NB + (mm[1] + LB)} * SHGO_ACC_STRIDE, {name[mm]});")
         o.append("    }")
     o.append("  }")
     o.append("};")

@@ -9,14 +9,18 @@
 //
 // Device design (one process, one GPU):
 //   a1  k_prim_weights, k_classify, k_scan_keys, k_scatter: per-shell normalisation, shell-pair
-//       enumeration, screening, counting sort by class (LA >= LB) and surviving primitive pairs.
-//   a2-a8  k_class<LA,LB>: one workgroup = 64 shell pairs x Q wavefronts; wavefront g owns the
-//       |M| families of group g. Work is done in the frame whose z axis is A->B, where the shift
-//       of Eq. 7 keeps m (only Y^lambda_0 of a z-directed vector survives). Per primitive pair and
-//       nucleus (nuclei read through the scalar cache): C = Q(c - P), Boys F_m, real solid
-//       harmonics S^L_M(C), W(L,M,k) += Z G_{L,k} S^L_M in registers; then the product-rule and
-//       shift coefficients map W onto the block V' (LDS, atomic adds); finally the block is
-//       rotated back with D^T = Z(phi) J^T Z(theta) J and written out.
+//       enumeration, screening, counting sort by class (LA >= LB) and surviving primitive pairs,
+//       the work-item list and each pair's output destination.
+//   a2-a8  k_integrals: persistent, one workgroup of eight wavefronts per CU. A work item is a
+//       block of tiles of 64 class-sorted shell pairs (one per lane); its (tile, group) tasks go
+//       to the wavefronts, group g owning some half-families |M| of W. Work is done in the frame
+//       whose z axis is A->B, where the shift of Eq. 7 keeps m (only Y^lambda_0 of a z-directed
+//       vector survives). Per primitive pair and nucleus (nuclei read through the scalar cache):
+//       C = c - P in the frame, Boys F_m, monic solid-harmonic recurrences, W(L,M,k) += Z G_{L,k} Q
+//       in registers; then the product-rule and shift coefficients map W onto the block V' in the
+//       item's LDS accumulator (atomic adds); after a barrier the blocks are rotated back with
+//       D^T = Z(phi) J^T Z(theta) J by all wavefronts and written with coalesced stores.
+//   P3  k_grad<LA,LB>: the adjoint of the above for dE/d(centers, nuclei) of E = sum D V.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,6 +34,7 @@
 
 #include "shgo.h"
 #define SHGO_TILE 64  // shell pairs per tile: one per lane of a wavefront
+#define SHGO_ACC_STRIDE (SHGO_TILE + 1)  // doubles between entries of a tile accumulator
 #include "generated/shgo_classes.inc"
 #include "generated/shgo_grad.inc"
 
@@ -46,8 +51,13 @@ constexpr int kKeysPerClass = 256;
 constexpr int kTile = SHGO_TILE;
 constexpr int kNumKeys = kNumClasses * kKeysPerClass;
 constexpr int kIntegralThreads = 512;  // one workgroup per CU: 8 wavefronts share a tile's accumulator
-constexpr int kAccDoubles = 19456;     // LDS accumulator of a work item (152 KB): tiles x NA*NB x 64
 constexpr int kMaxTilesPerItem = 8;
+constexpr int kAccStride = SHGO_ACC_STRIDE;
+constexpr int kFrameDoubles = 4 * kTile;  // pair frames of one tile: cos/sin of theta and phi
+// Dynamic LDS of a work item, in doubles: per tile an accumulator of NA*NB x kAccStride doubles and
+// its frames. The kernel's static LDS (queue words and the item offsets) takes the last 128 bytes
+// of the CU's 160 KB.
+constexpr int kLdsDoubles = (163840 - 128) / 8;
 constexpr int kPrefetchMaxW = 32;      // groups up to this many W doubles prefetch the next nucleus
 
 __host__ __device__ constexpr int class_id(int la, int lb) { return la * (la + 1) / 2 + lb; }
@@ -94,7 +104,15 @@ struct DevPairs {
   int32_t* key_count;      // [kNumKeys]
   int32_t* rank;           // [n_cand] position inside the key's bucket
   int32_t* key_off;        // [kNumKeys + 1]
+  int64_t* dst0;           // [n_cand] sorted: output row offset of s1 (matrix) or block offset (list)
+  int64_t* dst1;           // [n_cand] sorted: output offset of s2 (matrix) or 1 if the listed pair is (s2, s1)
   double screen;
+};
+
+// Schedule of the persistent integral kernel.
+struct ClassMeta {
+  int32_t order[kNumClasses];  // queue order: classes by decreasing cost per tile
+  int32_t tiles[kNumClasses];  // tiles per work item, 1..8, within the LDS accumulator
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -213,10 +231,6 @@ __global__ void k_prim_weights(DevBasis b) {
   }
 }
 
-__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
 
 // (a, b) with a <= b from the linear index of the upper triangle in row-major order.
 __device__ __forceinline__ void tri_pair(int64_t i, int n, int& a, int& b) {
@@ -278,8 +292,9 @@ __global__ void __launch_bounds__(256) k_classify(DevBasis bs, DevPairs pr) {
 }
 
 // Exclusive scan of key_count into key_off (one workgroup of 1024 threads).
-__global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr) {
+__global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta, int32_t* item_off, int32_t* queue) {
   __shared__ int part[1024];
+  __shared__ int cls_off[kNumClasses + 1];
   constexpr int per = (kNumKeys + 1023) / 1024;
   const int t = threadIdx.x;
   int loc[per];
@@ -287,6 +302,7 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr) {
   for (int j = 0; j < per; ++j) {
     const int k = t * per + j;
     loc[j] = k < kNumKeys ? pr.key_count[k] : 0;
+    if (k < kNumKeys) pr.key_count[k] = 0;  // cleared for the next evaluation's k_classify
     s += loc[j];
   }
   part[t] = s;
@@ -300,10 +316,30 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr) {
   int run = part[t] - s;
   for (int j = 0; j < per; ++j) {
     const int k = t * per + j;
-    if (k < kNumKeys) pr.key_off[k] = run;
+    if (k < kNumKeys) {
+      pr.key_off[k] = run;
+      if (k % kKeysPerClass == 0) cls_off[k / kKeysPerClass] = run;
+    }
     run += loc[j];
   }
-  if (t == 1023) pr.key_off[kNumKeys] = part[1023];
+  if (t == 1023) {
+    pr.key_off[kNumKeys] = part[1023];
+    cls_off[kNumClasses] = part[1023];
+  }
+  __syncthreads();
+  // work-item list of the integral kernel: for the k-th class in queue order, its blocks of
+  // tiles[c] tiles; and the queue head back to zero
+  if (t == 0) {
+    int off = 0;
+    for (int k = 0; k < kNumClasses; ++k) {
+      const int c = meta.order[k];
+      const int tiles = (cls_off[c + 1] - cls_off[c] + kTile - 1) / kTile;
+      item_off[k] = off;
+      off += (tiles + meta.tiles[c] - 1) / meta.tiles[c];
+    }
+    item_off[kNumClasses] = off;
+    queue[0] = 0;
+  }
 }
 
 __global__ void k_scatter(DevBasis bs, DevPairs pr) {
@@ -323,6 +359,13 @@ __global__ void k_scatter(DevBasis bs, DevPairs pr) {
   pr.s2[slot] = sw ? a : b;
   pr.orig[slot] = (int32_t)i;
   pr.nsurv[slot] = key % kKeysPerClass;
+  if (pr.full) {
+    pr.dst0[slot] = bs.bf_off[sw ? b : a];
+    pr.dst1[slot] = bs.bf_off[sw ? a : b];
+  } else {
+    pr.dst0[slot] = pr.blk_off[i];
+    pr.dst1[slot] = sw ? 1 : 0;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -335,10 +378,6 @@ __global__ void k_scatter(DevBasis bs, DevPairs pr) {
 // lane) and add the group's part of each block V' into the item's accumulator in LDS. After a
 // workgroup barrier each tile's blocks are rotated back to the laboratory frame and written.
 // Nothing crosses a workgroup: no global atomics on partial sums and no device-scope fences.
-struct ClassMeta {
-  int32_t order[kNumClasses];  // queue order: classes by decreasing cost per tile
-  int32_t tiles[kNumClasses];  // tiles per work item, 1..8, within the LDS accumulator
-};
 
 __host__ __device__ constexpr int class_nab(int c) {
   int la = 0;
@@ -346,9 +385,9 @@ __host__ __device__ constexpr int class_nab(int c) {
   const int lb = c - la * (la + 1) / 2;
   return (2 * la + 1) * (2 * lb + 1);
 }
+__host__ __device__ constexpr int class_tile_doubles(int c) { return class_nab(c) * kAccStride + kFrameDoubles; }
 __host__ __device__ constexpr int class_max_tiles(int c) {
-  return kAccDoubles / (class_nab(c) * SHGO_TILE) < kMaxTilesPerItem ? kAccDoubles / (class_nab(c) * SHGO_TILE)
-                                                                      : kMaxTilesPerItem;
+  return kLdsDoubles / class_tile_doubles(c) < kMaxTilesPerItem ? kLdsDoubles / class_tile_doubles(c) : kMaxTilesPerItem;
 }
 
 struct WorkArgs {
@@ -526,63 +565,11 @@ __device__ __forceinline__ void angles(double c1, double s1, double (&c)[L + 1],
   }
 }
 
-// Rotate the accumulated blocks of a tile back to the laboratory frame
-// (V = D_a^T V' D_b, D^T = Z(phi) J^T Z(theta) J; rows in place, then columns) and write them.
-template <int LA, int LB>
-__device__ __forceinline__ void finish_tile(const PairState& ps, WAP wa, double* __restrict__ out, int slot,
-                                            double* Vp) {
-  constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1;
-  double cth[LA + 1], sth[LA + 1], cph[LA + 1], sph[LA + 1];
-  angles<LA>(ps.ct, ps.st, cth, sth);
-  angles<LA>(ps.cp, ps.sp, cph, sph);
-  for (int r = 0; r < NA; ++r) {
-    double v[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) v[j] = Vp[(r * NB + j) * kTile];
-    Rot<LB>::apply(v, cth, sth, cph, sph);
-#pragma unroll
-    for (int j = 0; j < NB; ++j) Vp[(r * NB + j) * kTile] = v[j];
-  }
-  for (int col = 0; col < NB; ++col) {
-    double v[NA];
-#pragma unroll
-    for (int i = 0; i < NA; ++i) v[i] = Vp[(i * NB + col) * kTile];
-    Rot<LA>::apply(v, cth, sth, cph, sph);
-    if (!ps.active) continue;
-    if (wa->pr.full) {
-      const int64_t r0 = wa->bs.bf_off[ps.s1], c0 = wa->bs.bf_off[ps.s2], n = wa->bs.nbf;
-      if (ps.s1 != ps.s2) {
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-          out[(r0 + i) * n + c0 + col] = v[i];
-          out[(c0 + col) * n + r0 + i] = v[i];
-        }
-      } else {
-        // diagonal block: the upper triangle is mirrored so that V is exactly symmetric
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-          if (i <= col) {
-            out[(r0 + i) * n + c0 + col] = v[i];
-            out[(c0 + col) * n + r0 + i] = v[i];
-          }
-        }
-      }
-    } else {
-      const int o = wa->pr.orig[slot];
-      const int64_t bo = wa->pr.blk_off[o];
-      const bool sw = wa->pr.pa[o] != ps.s1;
-#pragma unroll
-      for (int i = 0; i < NA; ++i) {
-        if (sw)
-          out[bo + (int64_t)col * NA + i] = v[i];
-        else
-          out[bo + (int64_t)i * NB + col] = v[i];
-      }
-    }
-  }
-}
-
-extern __shared__ double s_acc[];  // the work item's accumulator [tile][NA*NB][SHGO_TILE]
+// Dynamic LDS of the integral kernel, for a work item of nt tiles:
+//   accumulator [tile][NA*NB][kAccStride]  V' of each pair (lane-contiguous; one pad double per row
+//               keeps a pair's strided reads free of bank conflicts)
+//   frames      [tile][4][SHGO_TILE]       cos/sin of theta and phi of each pair
+extern __shared__ double s_lds[];
 
 template <int LA, int LB>
 __device__ __forceinline__ void load_pair(PairState& ps, WAP wa, int slot, int end) {
@@ -607,18 +594,26 @@ __device__ __forceinline__ void load_pair(PairState& ps, WAP wa, int slot, int e
 // so that every class is compiled and register-allocated on its own.
 template <int LA, int LB>
 __device__ __attribute__((noinline)) void process_block(int b, const WorkArgs* wa_ptr, double* __restrict__ out,
-                                                        int* task_ctr) {
+                                                        int* task_ctr, int* next_item) {
   const WAP wa = uniform_args(wa_ptr);
   constexpr int Q = ClassInfo<LA, LB>::Q;
-  constexpr int NAB = (2 * LA + 1) * (2 * LB + 1);
+  constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, NAB = NA * NB;
   constexpr int cls = class_id(LA, LB);
+  constexpr int kWaves = kIntegralThreads / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int T = wa->meta.tiles[cls];
   const int start = wa->pr.key_off[cls * kKeysPerClass];
   const int end = wa->pr.key_off[(cls + 1) * kKeysPerClass];
   const int tiles = (end - start + kTile - 1) / kTile;
   const int t0 = b * T, nt = min(T, tiles - t0);
-  for (int i = threadIdx.x; i < nt * NAB * kTile; i += blockDim.x) s_acc[i] = 0.0;
+  double* const acc = s_lds;
+  double* const frm = s_lds + nt * NAB * kAccStride;
+  {
+    double2* const a2 = (double2*)acc;
+    const int n = nt * NAB * kAccStride;
+    for (int i = threadIdx.x; i < n / 2; i += kIntegralThreads) a2[i] = make_double2(0.0, 0.0);
+    if ((n & 1) && threadIdx.x == 0) acc[n - 1] = 0.0;
+  }
   __syncthreads();
   // (tile, group) tasks, tile-major, handed to the wavefronts by an LDS counter
   const int n_nuc = wa->n_nuc;
@@ -630,49 +625,132 @@ __device__ __attribute__((noinline)) void process_block(int b, const WorkArgs* w
     const int t = task / Q, g = task - t * Q;
     PairState ps;
     load_pair<LA, LB>(ps, wa, start + (t0 + t) * kTile + lane, end);
+    if (g == 0) {
+      double* const f = frm + t * 4 * kTile + lane;
+      f[0] = ps.ct;
+      f[kTile] = ps.st;
+      f[2 * kTile] = ps.cp;
+      f[3 * kTile] = ps.sp;
+    }
     // primitive-pair iterations of this wavefront (keys saturate at 255; then every candidate
     // primitive pair is visited and the screened ones skipped)
     int iters = ps.active ? (ps.nsurv >= kKeysPerClass - 1 ? ps.K1 * ps.K2 : ps.nsurv) : 0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) iters = max(iters, __shfl_xor(iters, off));
-    dispatch_group<LA, LB, 0>(g, ps, wa, iters, 0, n_nuc, s_acc + t * NAB * kTile + lane);
+    dispatch_group<LA, LB, 0>(g, ps, wa, iters, 0, n_nuc, acc + t * NAB * kAccStride + lane);
   }
   __syncthreads();
-  // every tile of the block back to the laboratory frame, one wavefront per tile
-  for (int t = wave; t < nt; t += kIntegralThreads / 64) {
-    PairState ps;
-    const int slot = start + (t0 + t) * kTile + lane;
-    load_pair<LA, LB>(ps, wa, slot, end);
-    finish_tile<LA, LB>(ps, wa, out, slot, s_acc + t * NAB * kTile + lane);
+  // the workgroup's next work item, fetched now so that the atomic's latency hides behind the
+  // rotations and stored for the caller at the end (every thread has read the current one)
+  int next = 0;
+  if (threadIdx.x == 0) next = atomicAdd(wa->queue, 1);
+  // Back to the laboratory frame, V = D_a^T V' D_b with D^T = Z(phi) J^T Z(theta) J: the rows of
+  // every tile, then its columns, as (tile, row) and (tile, column) tasks over all wavefronts.
+  for (int k = wave; k < nt * NA; k += kWaves) {
+    const int t = k / NA, r = k - t * NA;
+    const double* f = frm + t * 4 * kTile + lane;
+    double cth[LA + 1], sth[LA + 1], cph[LA + 1], sph[LA + 1];
+    angles<LA>(f[0], f[kTile], cth, sth);
+    angles<LA>(f[2 * kTile], f[3 * kTile], cph, sph);
+    double* V = acc + (t * NAB + r * NB) * kAccStride + lane;
+    double v[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) v[j] = V[j * kAccStride];
+    Rot<LB>::apply(v, cth, sth, cph, sph);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) V[j * kAccStride] = v[j];
   }
+  __syncthreads();
+  for (int k = wave; k < nt * NB; k += kWaves) {
+    const int t = k / NB, col = k - t * NB;
+    const double* f = frm + t * 4 * kTile + lane;
+    double cth[LA + 1], sth[LA + 1], cph[LA + 1], sph[LA + 1];
+    angles<LA>(f[0], f[kTile], cth, sth);
+    angles<LA>(f[2 * kTile], f[3 * kTile], cph, sph);
+    double* V = acc + (t * NAB + col) * kAccStride + lane;
+    double v[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) v[i] = V[i * NB * kAccStride];
+    Rot<LA>::apply(v, cth, sth, cph, sph);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) V[i * NB * kAccStride] = v[i];
+  }
+  __syncthreads();
+  // Output: consecutive threads take consecutive entries of one pair's block, so every store
+  // instruction covers a few contiguous lines. Destinations come from the pair build (dst0, dst1);
+  // four entries per thread and round keep four destination loads in flight.
+  const int base = start + t0 * kTile;
+  const int n_out = nt * kTile * NAB;
+  constexpr int kU = 4;
+  if (wa->pr.full) {
+    const int64_t n = wa->bs.nbf;
+    // rows of the (s1, s2) block (entry e = i NB + col), then of the mirrored (s2, s1) block
+    // (entry e = col NA + i)
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j0 = threadIdx.x; j0 < n_out; j0 += kU * kIntegralThreads) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int j = j0 + u * kIntegralThreads;
+          const int tp = j / NAB, e = j - tp * NAB;  // tp = tile * 64 + pair
+          const int slot = base + tp;
+          if (j < n_out && slot < end) {
+            const int64_t r0 = wa->pr.dst0[slot], c0 = wa->pr.dst1[slot];
+            int i, col;
+            if (pass == 0) {
+              i = e / NB;
+              col = e - i * NB;
+            } else {
+              col = e / NA;
+              i = e - col * NA;
+            }
+            const double v = acc[((tp >> 6) * NAB + i * NB + col) * kAccStride + (tp & 63)];
+            if (r0 != c0 || i <= col) {
+              if (pass == 0)
+                out[(r0 + i) * n + c0 + col] = v;
+              else
+                out[(c0 + col) * n + r0 + i] = v;
+            }
+          }
+        }
+      }
+    }
+  } else {
+    // pair blocks: (s1, s2) order, or transposed where the listed pair is (s2, s1)
+    for (int j0 = threadIdx.x; j0 < n_out; j0 += kU * kIntegralThreads) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * kIntegralThreads;
+        const int tp = j / NAB, e = j - tp * NAB;
+        const int slot = base + tp;
+        if (j < n_out && slot < end) {
+          const int64_t bo = wa->pr.dst0[slot];
+          const bool sw = wa->pr.dst1[slot] != 0;
+          int src = e;
+          if (sw) {  // output entry e = col NA + i holds V(i, col)
+            const int col = e / NA, i = e - col * NA;
+            src = i * NB + col;
+          }
+          out[bo + e] = acc[((tp >> 6) * NAB + src) * kAccStride + (tp & 63)];
+        }
+      }
+    }
+  }
+  if (threadIdx.x == 0) *next_item = next;
 }
 
 template <int LA, int LB>
-__device__ __forceinline__ void dispatch_class(int c, int j, const WorkArgs* wa, double* out, int* task_ctr) {
+__device__ __forceinline__ void dispatch_class(int c, int j, const WorkArgs* wa, double* out, int* task_ctr,
+                                               int* next_item) {
   if constexpr (LA <= SHGO_LMAX) {
     if (c == class_id(LA, LB)) {
-      process_block<LA, LB>(j, wa, out, task_ctr);
+      process_block<LA, LB>(j, wa, out, task_ctr, next_item);
       return;
     }
     if constexpr (LB < LA)
-      dispatch_class<LA, LB + 1>(c, j, wa, out, task_ctr);
+      dispatch_class<LA, LB + 1>(c, j, wa, out, task_ctr, next_item);
     else
-      dispatch_class<LA + 1, 0>(c, j, wa, out, task_ctr);
+      dispatch_class<LA + 1, 0>(c, j, wa, out, task_ctr, next_item);
   }
-}
-
-// Queue layout: for the k-th class in queue order, its tile blocks (tiles[c] tiles each).
-__global__ void k_items(DevPairs pr, ClassMeta meta, int32_t* item_off) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int off = 0;
-  for (int k = 0; k < kNumClasses; ++k) {
-    const int c = meta.order[k];
-    const int count = pr.key_off[(c + 1) * kKeysPerClass] - pr.key_off[c * kKeysPerClass];
-    const int tiles = (count + kTile - 1) / kTile;
-    item_off[k] = off;
-    off += (tiles + meta.tiles[c] - 1) / meta.tiles[c];
-  }
-  item_off[kNumClasses] = off;
 }
 
 // Every workgroup loops: take the next item, run it with its eight wavefronts; the loop ends
@@ -681,20 +759,20 @@ __global__ void __launch_bounds__(kIntegralThreads) __attribute__((amdgpu_waves_
 k_integrals(const WorkArgs* __restrict__ wa_ptr, double* __restrict__ out) {
   const WAP wa = uniform_args(wa_ptr);
   __shared__ int s_item, s_task;
+  __shared__ int s_ioff[kNumClasses + 1];  // first item of each class in queue order
+  if (threadIdx.x <= kNumClasses) s_ioff[threadIdx.x] = wa->item_off[threadIdx.x];
+  if (threadIdx.x == 0) s_item = atomicAdd(wa->queue, 1);
   const int total = wa->item_off[kNumClasses];
   while (true) {
-    if (threadIdx.x == 0) {
-      s_item = atomicAdd(wa->queue, 1);
-      s_task = 0;
-    }
+    if (threadIdx.x == 0) s_task = 0;
     __syncthreads();
     const int item = s_item;
     if (item >= total) break;
     int k = 0;
-    while (wa->item_off[k + 1] <= item) ++k;
+    while (s_ioff[k + 1] <= item) ++k;
     unsigned long long* const tick = wa->item_ns;
     const unsigned long long t0 = tick ? wall_clock64() : 0ull;
-    dispatch_class<0, 0>(wa->meta.order[k], item - wa->item_off[k], wa_ptr, out, &s_task);
+    dispatch_class<0, 0>(wa->meta.order[k], item - s_ioff[k], wa_ptr, out, &s_task, &s_item);
     if (tick && threadIdx.x == 0) tick[item] = wall_clock64() - t0;
     __syncthreads();
   }
@@ -1102,11 +1180,12 @@ int64_t max_items(const shgo_plan* p) {
   return n;
 }
 
-// LDS accumulator the plan's schedule needs: the largest tiles x NA*NB x 64 over its classes.
+// Dynamic LDS the plan's schedule needs: the largest tiles x (accumulator + frames) over its
+// classes.
 size_t acc_bytes(const shgo_plan* p) {
   size_t m = sizeof(double);
   for (int c = 0; c < kNumClasses; ++c)
-    if (p->class_cand[c] > 0) m = std::max(m, sizeof(double) * (size_t)p->meta.tiles[c] * class_nab(c) * kTile);
+    if (p->class_cand[c] > 0) m = std::max(m, sizeof(double) * (size_t)p->meta.tiles[c] * class_tile_doubles(c));
   return m;
 }
 
@@ -1123,13 +1202,11 @@ void enqueue(shgo_plan* p, double* out, hipStream_t st, bool timed) {
     if (slot >= 0) (void)hipEventRecord(p->events[((size_t)slot * SHGO_NUM_PHASES + phase) * 2 + edge], st);
   };
   mark(0, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(kNumKeys)), dim3(tb), 0, st, p->pr.key_count, (int64_t)kNumKeys, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, p->queue, (int64_t)1, 0);
+  // key_count is zero here: cleared at plan creation and by every k_scan_keys after reading it
   if (p->n_shells > 0) hipLaunchKernelGGL(k_prim_weights, dim3(blocks(p->n_shells)), dim3(tb), 0, st, p->bs);
   hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-  hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr);
+  hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->queue);
   hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-  hipLaunchKernelGGL(k_items, dim3(1), dim3(64), 0, st, p->pr, p->meta, p->item_off);
   mark(0, 1);
   mark(1, 0);
   hipLaunchKernelGGL(k_integrals, dim3(p->ctx->grid), dim3(kIntegralThreads), acc_bytes(p), st,
@@ -1227,6 +1304,8 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
   e = e != hipSuccess ? e : dalloc(p, &pr.key_count, (size_t)kNumKeys);
   e = e != hipSuccess ? e : dalloc(p, &pr.rank, (size_t)p->n_cand);
   e = e != hipSuccess ? e : dalloc(p, &pr.key_off, (size_t)kNumKeys + 1);
+  e = e != hipSuccess ? e : dalloc(p, &pr.dst0, (size_t)p->n_cand);
+  e = e != hipSuccess ? e : dalloc(p, &pr.dst1, (size_t)p->n_cand);
   // persistent-kernel schedule: tiles per work item and the queue order (classes by decreasing
   // cost per tile)
   {
@@ -1248,6 +1327,8 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
     shgo_plan_destroy(p);
     return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "device allocation failed");
   }
+  // the key counters start at zero; every k_scan_keys clears them again after reading
+  e = hipMemset(pr.key_count, 0, sizeof(int32_t) * kNumKeys);
   std::vector<int64_t> poff_h(b->n_shells);
   for (int s = 0; s < b->n_shells; ++s) poff_h[s] = b->prim_offset[s];
   std::vector<Nuc> nh(n->n_nuclei);
@@ -1359,10 +1440,10 @@ shgo_status shgo_create(int device, shgo_context** out) {
   }
   int n_cu = 0, per_cu = 0;
   if (hipFuncSetAttribute((const void*)k_integrals, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(sizeof(double) * kAccDoubles)) != hipSuccess ||
+                          (int)(sizeof(double) * kLdsDoubles)) != hipSuccess ||
       hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_integrals, kIntegralThreads,
-                                                   sizeof(double) * kAccDoubles) != hipSuccess) {
+                                                   sizeof(double) * kLdsDoubles) != hipSuccess) {
     shgo_destroy(c);
     return SHGO_ERR_DEVICE;
   }
@@ -1506,10 +1587,11 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
     double sum = 0.0;
     for (int i = ioff[k]; i < ioff[k + 1]; ++i) sum += 10.0 * (double)th[(size_t)i];
     const int n_items = ioff[k + 1] - ioff[k];
-    if (n_items > 0) item_ns[c] = sum / n_items / p->meta.tiles[c];  // per tile
+    if (n_items > 0) item_ns[c] = sum / n_items;  // per item of the default tiles
   }
-  // 2. candidates: the model order; classes by measured time per tile; the measured order with
-  //    the largest tile blocks the LDS allows; the measured order with one tile per item
+  // 2. candidates: the model order; classes by measured time per item (longest first); the
+  //    measured order with twice the default tiles where the LDS allows; the measured order with
+  //    one tile per item
   ClassMeta cand[kTuneCandidates];
   for (int v = 0; v < kTuneCandidates; ++v) cand[v] = p->meta;
   std::vector<std::pair<double, int>> by;
@@ -1518,7 +1600,7 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
   for (int v = 1; v < kTuneCandidates; ++v)
     for (int k = 0; k < kNumClasses; ++k) cand[v].order[k] = by[k].second;
   for (int c = 0; c < kNumClasses; ++c) {
-    cand[2].tiles[c] = class_max_tiles(c);
+    if (2 * p->meta.tiles[c] <= class_max_tiles(c)) cand[2].tiles[c] = 2 * p->meta.tiles[c];
     cand[3].tiles[c] = 1;
   }
   // 3. time each candidate, keep the fastest
@@ -1579,10 +1661,9 @@ shgo_status shgo_execute_grad(shgo_plan* p, const double* D, double* dE_dnuclei,
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(tb), 0, st, e_out, (int64_t)1);
   if (p->n_cand > 0 && p->n_nuc > 0) {
     // shell-pair build (a1), as for the integrals
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks(kNumKeys)), dim3(tb), 0, st, p->pr.key_count, (int64_t)kNumKeys, 0);
     if (p->n_shells > 0) hipLaunchKernelGGL(k_prim_weights, dim3(blocks(p->n_shells)), dim3(tb), 0, st, p->bs);
     hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-    hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr);
+    hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->queue);
     hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
     s = grad_all<0, 0>(p, ga, st, true);
     if (s != SHGO_OK) return s;
