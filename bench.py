@@ -283,7 +283,7 @@ def main():
     if not args.no_tune:
         # one-time schedule tuning of the plan (not part of the timed steps)
         ms_c, chosen = shgo.shgo_plan_autotune(plan, out, rounds=5)
-        order, slices = shgo.shgo_plan_get_schedule(plan)
+        weights, slices = shgo.shgo_plan_get_schedule(plan)
         tune = {"candidates_ms": [float(x) for x in ms_c], "chosen": chosen,
                 "tiles_per_item": {int(c): int(v) for c, v in enumerate(slices)}}
     if args.copy_bytes > 0:

@@ -137,28 +137,31 @@ shgo_status shgo_execute_grad(shgo_plan* plan, const double* D, double* dE_dnucl
 shgo_status shgo_execute_graph(shgo_plan* plan, double* out, void* stream);
 
 /* Work schedule of the persistent launch, one entry per class id c = la(la+1)/2 + lb (la >= lb).
- * A work item is a block of tiles[c] tiles of 64 class-sorted shell pairs, run by one workgroup
- * (eight wavefronts take its (tile, group) tasks and add into one LDS accumulator).
- *   order[28]  queue order of the classes (a permutation of 0..27; longest items first when the
- *              order is by decreasing time per item)
+ * A work item is a block of tiles[c] tiles of 64 class-sorted shell pairs, run by one workgroup:
+ * its eight wavefronts take (tile, slice of at most 8 primitive-pair iterations, group) tasks and
+ * add into one LDS accumulator. Items are dispatched longest first, by the estimate
+ * weight[c] x (primitive-pair iterations of the item's longest tile) x (its tiles).
+ *   weight[28] relative time of one primitive-pair iteration of a tile of the class, 1..1e6 (the
+ *              default comes from an operation-count model, largest 1024)
  *   tiles[28]  tiles per work item of each class, 1 <= tiles[c] <= shgo_max_tiles(c) (the LDS of
  *              a work item holds per tile (2la+1)(2lb+1) x 65 accumulator doubles and 256 frame
- *              doubles, at most 20464 doubles in all)
+ *              doubles, at most 20448 doubles in all)
  * get copies the plan's schedule out; set validates (SHGO_ERR_INVALID_ARG) and installs one, e.g. a
  * schedule saved from an earlier autotune of the same workload. Results do not depend on the
  * schedule beyond rounding. */
 #define SHGO_NUM_CLASSES 28
 int32_t shgo_max_tiles(int32_t class_id); /* -1 for an invalid class id */
-shgo_status shgo_plan_get_schedule(const shgo_plan* plan, int32_t* order, int32_t* tiles);
-shgo_status shgo_plan_set_schedule(shgo_plan* plan, const int32_t* order, const int32_t* tiles);
+shgo_status shgo_plan_get_schedule(const shgo_plan* plan, float* weight, int32_t* tiles);
+shgo_status shgo_plan_set_schedule(shgo_plan* plan, const float* weight, const int32_t* tiles);
 
-/* Autotuner of the batched launch. Runs the plan once with per-item timing to measure each
- * class's time per tile, builds SHGO_TUNE_CANDIDATES schedules -- 0: the model order with the
- * default tiles per item; 1: classes by measured time per item; 2: the measured order with twice
- * the default tiles where the LDS allows; 3: the measured order with one tile per item -- times
- * `rounds` executions of each on `stream` (the call synchronizes the stream), and keeps the
- * fastest. ms[SHGO_TUNE_CANDIDATES] (or NULL) receives each candidate's milliseconds per
- * execution, *chosen (or NULL) the index kept. `out` is written as by shgo_execute. */
+/* Autotuner of the batched launch. Runs the plan once with the model weights, the default tiles
+ * and per-item timing, which measures each class's time per unit of the item estimate; builds
+ * SHGO_TUNE_CANDIDATES schedules -- 0: the model weights with the default tiles; 1: the measured
+ * weights with the default tiles; 2: the measured weights with twice the default tiles where the
+ * LDS allows; 3: the measured weights with one tile per item -- times `rounds` executions of each on
+ * `stream` (the call synchronizes the stream), and keeps the fastest. ms[SHGO_TUNE_CANDIDATES] (or
+ * NULL) receives each candidate's milliseconds per execution, *chosen (or NULL) the index kept.
+ * `out` is written as by shgo_execute. */
 #define SHGO_TUNE_CANDIDATES 4
 shgo_status shgo_plan_autotune(shgo_plan* plan, double* out, int32_t rounds, void* stream, double* ms,
                                int32_t* chosen);

@@ -263,21 +263,21 @@ def shgo_max_tiles(class_id):
 
 
 def shgo_plan_get_schedule(plan):
-    """(order[28], tiles[28]) of the plan's persistent launch."""
+    """(weight[28] float32, tiles[28] int32) of the plan's persistent launch."""
     lib = load_library()
-    order = np.zeros(SHGO_NUM_CLASSES, dtype=np.int32)
+    weight = np.zeros(SHGO_NUM_CLASSES, dtype=np.float32)
     tiles = np.zeros(SHGO_NUM_CLASSES, dtype=np.int32)
-    _check(lib, plan.ctx, lib.shgo_plan_get_schedule(plan.handle, order.ctypes.data, tiles.ctypes.data))
-    return order, tiles
+    _check(lib, plan.ctx, lib.shgo_plan_get_schedule(plan.handle, weight.ctypes.data, tiles.ctypes.data))
+    return weight, tiles
 
 
-def shgo_plan_set_schedule(plan, order, tiles):
+def shgo_plan_set_schedule(plan, weight, tiles):
     lib = load_library()
-    order = np.ascontiguousarray(order, dtype=np.int32)
+    weight = np.ascontiguousarray(weight, dtype=np.float32)
     tiles = np.ascontiguousarray(tiles, dtype=np.int32)
-    if order.shape != (SHGO_NUM_CLASSES,) or tiles.shape != (SHGO_NUM_CLASSES,):
-        raise ValueError("order and tiles need one entry per class (28)")
-    _check(lib, plan.ctx, lib.shgo_plan_set_schedule(plan.handle, order.ctypes.data, tiles.ctypes.data))
+    if weight.shape != (SHGO_NUM_CLASSES,) or tiles.shape != (SHGO_NUM_CLASSES,):
+        raise ValueError("weight and tiles need one entry per class (28)")
+    _check(lib, plan.ctx, lib.shgo_plan_set_schedule(plan.handle, weight.ctypes.data, tiles.ctypes.data))
 
 
 def shgo_plan_autotune(plan, out, rounds=5, stream=None):

@@ -8,7 +8,7 @@
 // Y^L_M(c-P) 2 pi k!/p^{k+1} sum_j T^j/j! F_{L+j}(T)), sum over nuclei, contraction.
 //
 // Device design (one process, one GPU):
-//   a1  k_prim_weights, k_classify, k_scan_keys, k_scatter: per-shell normalisation, shell-pair
+//   a1  k_classify, k_scan_keys, k_scatter: per-shell normalisation (extra k_classify workgroups), shell-pair
 //       enumeration, screening, counting sort by class (LA >= LB) and surviving primitive pairs,
 //       the work-item list and each pair's output destination.
 //   a2-a8  k_integrals: persistent, one workgroup of eight wavefronts per CU. A work item is a
@@ -55,9 +55,9 @@ constexpr int kMaxTilesPerItem = 8;
 constexpr int kAccStride = SHGO_ACC_STRIDE;
 constexpr int kFrameDoubles = 4 * kTile;  // pair frames of one tile: cos/sin of theta and phi
 // Dynamic LDS of a work item, in doubles: per tile an accumulator of NA*NB x kAccStride doubles and
-// its frames. The kernel's static LDS (queue words and the item offsets) takes the last 128 bytes
-// of the CU's 160 KB.
-constexpr int kLdsDoubles = (163840 - 128) / 8;
+// its frames. The kernel's static LDS (queue words, per-tile iteration counts) fits in the last
+// 256 bytes of the CU's 160 KB.
+constexpr int kLdsDoubles = (163840 - 256) / 8;
 constexpr int kPrefetchMaxW = 32;      // groups up to this many W doubles prefetch the next nucleus
 
 __host__ __device__ constexpr int class_id(int la, int lb) { return la * (la + 1) / 2 + lb; }
@@ -84,7 +84,7 @@ struct DevBasis {
   const int64_t* prim_off; // [n]
   const double* expo;      // [nprim total]
   const double* coef;      // [nprim total]
-  double* w;               // [nprim total] normalised weights (written by k_prim_weights)
+  double* w;               // [nprim total] normalised weights (written by k_classify)
   const int64_t* bf_off;   // [n] first basis function of each shell
   int32_t n_shells;
   int64_t nbf;
@@ -111,9 +111,12 @@ struct DevPairs {
 
 // Schedule of the persistent integral kernel.
 struct ClassMeta {
-  int32_t order[kNumClasses];  // queue order: classes by decreasing cost per tile
-  int32_t tiles[kNumClasses];  // tiles per work item, 1..8, within the LDS accumulator
+  float weight[kNumClasses];   // relative time of one primitive-pair iteration of a tile of the class
+  int32_t tiles[kNumClasses];  // tiles per work item, 1..8, within the LDS of a workgroup
+  int32_t groups[kNumClasses]; // wavefront groups of the class (fixed by the generated code)
 };
+constexpr int kCostBuckets = 128;  // work items are dispatched by cost bucket, 4 per octave
+constexpr int kSliceIters = 8;     // primitive-pair iterations per task of a long tile
 
 // ---------------------------------------------------------------------------------------------
 // Boys function (device)
@@ -206,31 +209,37 @@ __global__ void k_boys(int64_t n, const double* __restrict__ T, double* __restri
 // ---------------------------------------------------------------------------------------------
 // Normalised weight of primitive k of a shell: w_k = d_k N_k / sqrt(sum_kk' d_k d_k' <phi_k|phi_k'>)
 // with N(l,a)^2 = 2^l (2a)^{l+3/2}/((2l-1)!! pi^{3/2}) and, for normalised primitives,
-// <phi_k|phi_k'> = n_k n_k' / (a_k + a_k')^{l+3/2}, n_k = (2 a_k)^{(l+3/2)/2}.
-__global__ void k_prim_weights(DevBasis b) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= b.n_shells) return;
+// <phi_k|phi_k'> = n_k n_k' / (a_k + a_k')^{l+3/2}, n_k = (2 a_k)^{(l+3/2)/2}. The half-integer
+// powers are products of integer powers and square roots.
+__device__ __forceinline__ double ipow(double x, int n) {
+  double r = 1.0;
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+__device__ __forceinline__ double pow_half_q(double x, int l) {  // x^{(l+3/2)/2}
+  const double s = sqrt(x);
+  return ipow(x, l >> 1) * ((l & 1) ? s : 1.0) * sqrt(x * s);
+}
+__device__ __forceinline__ double pow_q(double y, int l) {  // y^{l+3/2}
+  return ipow(y, l) * y * sqrt(y);
+}
+__device__ void prim_weights_of(const DevBasis& b, int s) {
   const int l = b.l[s], K = b.nprim[s];
   const int64_t o = b.prim_off[s];
-  const double q = l + 1.5;
   double dfac = 1.0;
   for (int i = 2 * l - 1; i > 1; i -= 2) dfac *= i;
   const double cn = sqrt(ldexp(1.0, l) / (dfac * 5.5683279968317078453));  // pi^{3/2}
   double ss = 0.0;
   for (int k = 0; k < K; ++k) {
-    const double ak = b.expo[o + k], nk = pow(2.0 * ak, 0.5 * q), dk = b.coef[o + k];
+    const double ak = b.expo[o + k], nk = pow_half_q(2.0 * ak, l), dk = b.coef[o + k];
     for (int j = 0; j < K; ++j) {
-      const double aj = b.expo[o + j], nj = pow(2.0 * aj, 0.5 * q);
-      ss += dk * b.coef[o + j] * nk * nj / pow(ak + aj, q);
+      const double aj = b.expo[o + j], nj = pow_half_q(2.0 * aj, l);
+      ss += dk * b.coef[o + j] * nk * nj / pow_q(ak + aj, l);
     }
   }
   const double inv = 1.0 / sqrt(ss);
-  for (int k = 0; k < K; ++k) {
-    const double ak = b.expo[o + k];
-    b.w[o + k] = b.coef[o + k] * cn * pow(2.0 * ak, 0.5 * q) * inv;
-  }
+  for (int k = 0; k < K; ++k) b.w[o + k] = b.coef[o + k] * cn * pow_half_q(2.0 * b.expo[o + k], l) * inv;
 }
-
 
 // (a, b) with a <= b from the linear index of the upper triangle in row-major order.
 __device__ __forceinline__ void tri_pair(int64_t i, int n, int& a, int& b) {
@@ -250,10 +259,16 @@ __device__ __forceinline__ bool keep_prim(double a, double b, double R2, double 
 
 // Classification in workgroups of 256 candidates: the key of each candidate, its rank among
 // the workgroup's candidates with the same key (LDS atomics), and one global atomic per
-// (workgroup, key) that reserves the workgroup's range inside the key's bucket.
-__global__ void __launch_bounds__(256) k_classify(DevBasis bs, DevPairs pr) {
-  __shared__ int hist[kNumKeys];
-  __shared__ int base[kNumKeys];
+// (workgroup, key) that reserves the workgroup's range inside the key's bucket. Workgroups from
+// classify_blocks on compute the shells' normalised primitive weights instead (independent work,
+// in the same launch).
+__global__ void __launch_bounds__(256) k_classify(DevBasis bs, DevPairs pr, int classify_blocks) {
+  if ((int)blockIdx.x >= classify_blocks) {
+    const int s = ((int)blockIdx.x - classify_blocks) * blockDim.x + threadIdx.x;
+    if (s < bs.n_shells) prim_weights_of(bs, s);
+    return;
+  }
+  __shared__ int hist[kNumKeys];  // counts, then the workgroup's base in each key's bucket
   for (int b = threadIdx.x; b < kNumKeys; b += blockDim.x) hist[b] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -283,18 +298,54 @@ __global__ void __launch_bounds__(256) k_classify(DevBasis bs, DevPairs pr) {
   }
   __syncthreads();
   for (int b = threadIdx.x; b < kNumKeys; b += blockDim.x)
-    if (hist[b] > 0) base[b] = atomicAdd(&pr.key_count[b], hist[b]);
+    if (hist[b] > 0) hist[b] = atomicAdd(&pr.key_count[b], hist[b]);
   __syncthreads();
   if (i < pr.n_cand) {
     pr.key[i] = key;
-    pr.rank[i] = base[key] + rank;
+    pr.rank[i] = hist[key] + rank;
   }
 }
 
 // Exclusive scan of key_count into key_off (one workgroup of 1024 threads).
-__global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta, int32_t* item_off, int32_t* queue) {
+// Cost bucket of work item i (class c = the one whose items start at or below i): the class's
+// weight times the primitive-pair iterations of the item's longest tile (the surviving-pair count
+// of its last slot, keys being sorted within the class) times its tiles, over the wavefronts its
+// tasks keep busy; four buckets per octave.
+__device__ int item_bucket(int i, const int* ioff, const int* koff, const ClassMeta& meta, int& c, int& blk) {
+  c = 0;
+  while (ioff[c + 1] <= i) ++c;
+  blk = i - ioff[c];
+  const int T = meta.tiles[c];
+  const int start = koff[c * kKeysPerClass], end = koff[(c + 1) * kKeysPerClass];
+  const int tiles = (end - start + kTile - 1) / kTile;
+  const int nt = min(T, tiles - blk * T);
+  const int last = min(start + (blk * T + nt) * kTile, end) - 1;
+  int lo = 0, hi = kKeysPerClass - 1;  // largest key k of the class with koff <= last
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (koff[c * kKeysPerClass + mid] <= last)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  // eight wavefronts share the item's (tile, slice, group) tasks
+  const int m = max(lo, 1);
+  const int tasks = nt * meta.groups[c] * max(1, (m + kSliceIters - 1) / kSliceIters);
+  const float cost = meta.weight[c] * (float)m * (float)nt / (float)min(8, tasks);
+  if (!(cost >= 1.0f)) return 0;
+  return min(kCostBuckets - 1, (int)(4.0f * log2f(cost)));
+}
+
+// Exclusive scan of key_count into key_off (one workgroup of 1024 threads), then the work-item
+// list of the integral kernel: every class's blocks of tiles[c] tiles, sorted by decreasing cost
+// bucket (a counting sort in LDS), so that the persistent kernel takes the longest items first.
+// Also clears key_count for the next evaluation and resets the queue head.
+__global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta, int32_t* item_off, int32_t* items,
+                                                    int32_t* queue) {
   __shared__ int part[1024];
-  __shared__ int cls_off[kNumClasses + 1];
+  __shared__ int koff[kNumKeys + 1];
+  __shared__ int ioff[kNumClasses + 1];  // first item of each class, in class-id order
+  __shared__ int bcount[kCostBuckets];
   constexpr int per = (kNumKeys + 1023) / 1024;
   const int t = threadIdx.x;
   int loc[per];
@@ -306,6 +357,7 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta,
     s += loc[j];
   }
   part[t] = s;
+  if (t < kCostBuckets) bcount[t] = 0;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
     const int v = t >= off ? part[t - off] : 0;
@@ -318,27 +370,43 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta,
     const int k = t * per + j;
     if (k < kNumKeys) {
       pr.key_off[k] = run;
-      if (k % kKeysPerClass == 0) cls_off[k / kKeysPerClass] = run;
+      koff[k] = run;
     }
     run += loc[j];
   }
   if (t == 1023) {
     pr.key_off[kNumKeys] = part[1023];
-    cls_off[kNumClasses] = part[1023];
+    koff[kNumKeys] = part[1023];
   }
   __syncthreads();
-  // work-item list of the integral kernel: for the k-th class in queue order, its blocks of
-  // tiles[c] tiles; and the queue head back to zero
   if (t == 0) {
     int off = 0;
-    for (int k = 0; k < kNumClasses; ++k) {
-      const int c = meta.order[k];
-      const int tiles = (cls_off[c + 1] - cls_off[c] + kTile - 1) / kTile;
-      item_off[k] = off;
+    for (int c = 0; c < kNumClasses; ++c) {
+      const int tiles = (koff[(c + 1) * kKeysPerClass] - koff[c * kKeysPerClass] + kTile - 1) / kTile;
+      ioff[c] = off;
       off += (tiles + meta.tiles[c] - 1) / meta.tiles[c];
     }
-    item_off[kNumClasses] = off;
+    ioff[kNumClasses] = off;
+    item_off[0] = off;
     queue[0] = 0;
+  }
+  __syncthreads();
+  const int total = ioff[kNumClasses];
+  int c, blk;
+  for (int i = t; i < total; i += 1024) atomicAdd(&bcount[item_bucket(i, ioff, koff, meta, c, blk)], 1);
+  __syncthreads();
+  if (t == 0) {  // bucket starts, most expensive bucket first
+    int pos = 0;
+    for (int b = kCostBuckets - 1; b >= 0; --b) {
+      const int n = bcount[b];
+      bcount[b] = pos;
+      pos += n;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < total; i += 1024) {
+    const int b = item_bucket(i, ioff, koff, meta, c, blk);
+    items[atomicAdd(&bcount[b], 1)] = (c << 24) | blk;
   }
 }
 
@@ -397,7 +465,8 @@ struct WorkArgs {
   int32_t n_nuc;
   const double* __restrict__ boys_tab;
   int32_t* __restrict__ queue;     // [0]: next work item
-  int32_t* __restrict__ item_off;  // [kNumClasses + 1]: prefix of items per class in queue order
+  int32_t* __restrict__ item_off;  // [0]: number of work items
+  int32_t* __restrict__ items;     // work items, longest first: class << 24 | tile block
   unsigned long long* __restrict__ item_ns;  // per-item durations (10 ns ticks) when tuning, else null
   ClassMeta meta;
 };
@@ -459,13 +528,17 @@ __device__ __forceinline__ bool next_prim(const PairState& ps, WAP wa, int& i, i
   }
 }
 
+// Primitive-pair iterations [it_begin, it_end) of group G for the wavefront's 64 pairs: the pair's
+// surviving primitive pairs in order, the first it_begin skipped.
 template <int LA, int LB, int G>
-__device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_iters, int c_begin, int c_end,
+__device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int it_begin, int it_end, int c_begin, int c_end,
                                           double* __restrict__ Vp) {
   using Grp = GroupOf<LA, LB, G>;
   constexpr int LM = LA + LB;
   int pi = 0, pj = -1;
-  for (int it = 0; it < wave_iters; ++it) {
+  if (ps.active)
+    for (int it = 0; it < it_begin; ++it) (void)next_prim(ps, wa, pi, pj);
+  for (int it = it_begin; it < it_end; ++it) {
     const bool have = ps.active && next_prim(ps, wa, pi, pj);
     if (have) {
       const double a = wa->bs.expo[ps.o1 + pi], b = wa->bs.expo[ps.o2 + pj];
@@ -543,14 +616,14 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int wave_
 }
 
 template <int LA, int LB, int G>
-__device__ __forceinline__ void dispatch_group(int g, const PairState& ps, WAP wa, int wave_iters, int c0, int c1,
+__device__ __forceinline__ void dispatch_group(int g, const PairState& ps, WAP wa, int it0, int it1, int c0, int c1,
                                                double* Vp) {
   if constexpr (G < ClassInfo<LA, LB>::Q) {
     if (g == G) {
-      run_group<LA, LB, G>(ps, wa, wave_iters, c0, c1, Vp);
+      run_group<LA, LB, G>(ps, wa, it0, it1, c0, c1, Vp);
       return;
     }
-    dispatch_group<LA, LB, G + 1>(g, ps, wa, wave_iters, c0, c1, Vp);
+    dispatch_group<LA, LB, G + 1>(g, ps, wa, it0, it1, c0, c1, Vp);
   }
 }
 
@@ -570,6 +643,7 @@ __device__ __forceinline__ void angles(double c1, double s1, double (&c)[L + 1],
 //               keeps a pair's strided reads free of bank conflicts)
 //   frames      [tile][4][SHGO_TILE]       cos/sin of theta and phi of each pair
 extern __shared__ double s_lds[];
+__shared__ int s_tile_iters[kMaxTilesPerItem];  // primitive-pair iterations of each tile of the item
 
 template <int LA, int LB>
 __device__ __forceinline__ void load_pair(PairState& ps, WAP wa, int slot, int end) {
@@ -614,30 +688,48 @@ __device__ __attribute__((noinline)) void process_block(int b, const WorkArgs* w
     for (int i = threadIdx.x; i < n / 2; i += kIntegralThreads) a2[i] = make_double2(0.0, 0.0);
     if ((n & 1) && threadIdx.x == 0) acc[n - 1] = 0.0;
   }
+  // primitive-pair iterations of each tile (the most over its pairs; keys saturate at 255 and then
+  // every candidate primitive pair is visited, the screened ones skipped): wavefront w, tile w
+  if (wave < nt) {
+    const int slot = start + (t0 + wave) * kTile + lane;
+    int it = 0;
+    if (slot < end) {
+      it = wa->pr.nsurv[slot];
+      if (it >= kKeysPerClass - 1) it = wa->bs.nprim[wa->pr.s1[slot]] * wa->bs.nprim[wa->pr.s2[slot]];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) it = max(it, __shfl_xor(it, off));
+    if (lane == 0) s_tile_iters[wave] = it;
+  }
   __syncthreads();
-  // (tile, group) tasks, tile-major, handed to the wavefronts by an LDS counter
+  // tasks (tile, slice of at most kSliceIters primitive-pair iterations, group), tile-major, handed
+  // to the wavefronts by an LDS counter
   const int n_nuc = wa->n_nuc;
   while (true) {
     int task = 0;
     if (lane == 0) task = atomicAdd(task_ctr, 1);
     task = __shfl(task, 0);
-    if (task >= nt * Q) break;
-    const int t = task / Q, g = task - t * Q;
+    int u = task / Q;
+    const int g = task - u * Q;
+    int t = 0, m = 0;
+    for (; t < nt; ++t) {
+      m = s_tile_iters[t];
+      const int slices = max(1, (m + kSliceIters - 1) / kSliceIters);
+      if (u < slices) break;
+      u -= slices;
+    }
+    if (t >= nt) break;
     PairState ps;
     load_pair<LA, LB>(ps, wa, start + (t0 + t) * kTile + lane, end);
-    if (g == 0) {
+    if (g == 0 && u == 0) {
       double* const f = frm + t * 4 * kTile + lane;
       f[0] = ps.ct;
       f[kTile] = ps.st;
       f[2 * kTile] = ps.cp;
       f[3 * kTile] = ps.sp;
     }
-    // primitive-pair iterations of this wavefront (keys saturate at 255; then every candidate
-    // primitive pair is visited and the screened ones skipped)
-    int iters = ps.active ? (ps.nsurv >= kKeysPerClass - 1 ? ps.K1 * ps.K2 : ps.nsurv) : 0;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) iters = max(iters, __shfl_xor(iters, off));
-    dispatch_group<LA, LB, 0>(g, ps, wa, iters, 0, n_nuc, acc + t * NAB * kAccStride + lane);
+    const int it0 = u * kSliceIters;
+    dispatch_group<LA, LB, 0>(g, ps, wa, it0, min(m, it0 + kSliceIters), 0, n_nuc, acc + t * NAB * kAccStride + lane);
   }
   __syncthreads();
   // the workgroup's next work item, fetched now so that the atomic's latency hides behind the
@@ -759,21 +851,18 @@ __global__ void __launch_bounds__(kIntegralThreads) __attribute__((amdgpu_waves_
 k_integrals(const WorkArgs* __restrict__ wa_ptr, double* __restrict__ out) {
   const WAP wa = uniform_args(wa_ptr);
   __shared__ int s_item, s_task;
-  __shared__ int s_ioff[kNumClasses + 1];  // first item of each class in queue order
-  if (threadIdx.x <= kNumClasses) s_ioff[threadIdx.x] = wa->item_off[threadIdx.x];
   if (threadIdx.x == 0) s_item = atomicAdd(wa->queue, 1);
-  const int total = wa->item_off[kNumClasses];
+  const int total = wa->item_off[0];
   while (true) {
     if (threadIdx.x == 0) s_task = 0;
     __syncthreads();
-    const int item = s_item;
-    if (item >= total) break;
-    int k = 0;
-    while (s_ioff[k + 1] <= item) ++k;
+    const int q = s_item;
+    if (q >= total) break;
+    const int item = wa->items[q];
     unsigned long long* const tick = wa->item_ns;
     const unsigned long long t0 = tick ? wall_clock64() : 0ull;
-    dispatch_class<0, 0>(wa->meta.order[k], item - s_ioff[k], wa_ptr, out, &s_task, &s_item);
-    if (tick && threadIdx.x == 0) tick[item] = wall_clock64() - t0;
+    dispatch_class<0, 0>(item >> 24, item & 0xffffff, wa_ptr, out, &s_task, &s_item);
+    if (tick && threadIdx.x == 0) tick[q] = wall_clock64() - t0;
     __syncthreads();
   }
 }
@@ -1069,6 +1158,15 @@ double class_cost(int la, int lb, int n_nuc) {
   return (double)n_nuc * (60.0 + 4.0 * (lm + 1) * (lm + 1) + 2.0 * nw) + 40.0 + 30.0 * nw;
 }
 
+// Class weights of the work-item order from the cost model, scaled so that the largest is 1024.
+void model_weights(int n_nuc, float* w) {
+  double mx = 0.0;
+  for (int la = 0; la <= SHGO_LMAX; ++la)
+    for (int lb = 0; lb <= la; ++lb) mx = std::max(mx, class_cost(la, lb, n_nuc));
+  for (int la = 0; la <= SHGO_LMAX; ++la)
+    for (int lb = 0; lb <= la; ++lb) w[class_id(la, lb)] = (float)(1024.0 * class_cost(la, lb, n_nuc) / mx);
+}
+
 }  // namespace
 
 struct shgo_context {
@@ -1093,7 +1191,8 @@ struct shgo_plan {
   // persistent-kernel workspace
   ClassMeta meta{};
   int32_t* queue = nullptr;  // head of the persistent kernel's work queue
-  int32_t* item_off = nullptr;
+  int32_t* item_off = nullptr;  // [0]: number of work items
+  int32_t* items = nullptr;     // work items, longest first (capacity: one tile per item)
   WorkArgs* d_wa = nullptr;  // the integral kernel's arguments, in device memory
   double* d_energy = nullptr;  // gradient: E when the caller does not ask for it
   // captured graph of one evaluation (shgo_execute_graph) and its output buffer
@@ -1168,7 +1267,7 @@ int64_t total_prims(const shgo_basis* b) {
 // The integral kernel's arguments (device copy, read through the scalar cache). item_ns turns the
 // per-item timing of the kernel on (tuning runs) or off (null).
 hipError_t upload_args(shgo_plan* p, unsigned long long* item_ns) {
-  const WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, p->ctx->boys_tab, p->queue, p->item_off, item_ns, p->meta};
+  const WorkArgs wa{p->bs, p->pr, p->nuc, p->n_nuc, p->ctx->boys_tab, p->queue, p->item_off, p->items, item_ns, p->meta};
   return hipMemcpy(p->d_wa, &wa, sizeof(WorkArgs), hipMemcpyHostToDevice);
 }
 
@@ -1203,9 +1302,9 @@ void enqueue(shgo_plan* p, double* out, hipStream_t st, bool timed) {
   };
   mark(0, 0);
   // key_count is zero here: cleared at plan creation and by every k_scan_keys after reading it
-  if (p->n_shells > 0) hipLaunchKernelGGL(k_prim_weights, dim3(blocks(p->n_shells)), dim3(tb), 0, st, p->bs);
-  hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-  hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->queue);
+  hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand) + blocks(p->n_shells)), dim3(tb), 0, st, p->bs, p->pr,
+                     blocks(p->n_cand));
+  hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->items, p->queue);
   hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
   mark(0, 1);
   mark(1, 0);
@@ -1306,21 +1405,19 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
   e = e != hipSuccess ? e : dalloc(p, &pr.key_off, (size_t)kNumKeys + 1);
   e = e != hipSuccess ? e : dalloc(p, &pr.dst0, (size_t)p->n_cand);
   e = e != hipSuccess ? e : dalloc(p, &pr.dst1, (size_t)p->n_cand);
-  // persistent-kernel schedule: tiles per work item and the queue order (classes by decreasing
-  // cost per tile)
-  {
-    std::vector<std::pair<double, int>> cost;
-    for (int la = 0; la <= SHGO_LMAX; ++la)
-      for (int lb = 0; lb <= la; ++lb) {
-        const int c = class_id(la, lb);
-        p->meta.tiles[c] = default_tiles(c);
-        cost.push_back({-class_cost(la, lb, n->n_nuclei), c});
-      }
-    std::stable_sort(cost.begin(), cost.end());
-    for (int k = 0; k < kNumClasses; ++k) p->meta.order[k] = cost[k].second;
+  // persistent-kernel schedule: tiles per work item and the model weight of each class
+  model_weights(n->n_nuclei, p->meta.weight);
+  for (int c = 0; c < kNumClasses; ++c) {
+    p->meta.tiles[c] = default_tiles(c);
+    p->meta.groups[c] = kClassGroups[c];
   }
   e = e != hipSuccess ? e : dalloc(p, &p->queue, 1);
   e = e != hipSuccess ? e : dalloc(p, &p->item_off, (size_t)kNumClasses + 1);
+  {
+    int64_t cap = 0;
+    for (int c = 0; c < kNumClasses; ++c) cap += ((int64_t)p->class_cand[c] + kTile - 1) / kTile;
+    e = e != hipSuccess ? e : dalloc(p, &p->items, (size_t)std::max<int64_t>(cap, 1));
+  }
   e = e != hipSuccess ? e : dalloc(p, &p->d_wa, 1);
   e = e != hipSuccess ? e : dalloc(p, &p->d_energy, 1);
   if (e != hipSuccess) {
@@ -1557,50 +1654,70 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
   if (p->n_cand == 0) return SHGO_OK;
   hipStream_t st = (hipStream_t)stream;
   drop_graph(p);
-  // 1. one timed run with the model order and the default tiles: mean duration of each
-  //    class's items, per tile
+  // 1. one timed run with the model weights and the default tiles: each class's measured time per
+  //    unit of the items' estimate (iterations of the longest tile x tiles / busy wavefronts)
   ClassMeta base = p->meta;
+  model_weights(p->n_nuc, p->meta.weight);
   for (int c = 0; c < kNumClasses; ++c) p->meta.tiles[c] = default_tiles(c);
+  const ClassMeta model = p->meta;
   const int64_t nmax = max_items(p);
   unsigned long long* ticks = nullptr;
   if (hipMalloc(&ticks, sizeof(unsigned long long) * (size_t)std::max<int64_t>(nmax, 1)) != hipSuccess)
     return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "tuning buffer");
   std::vector<unsigned long long> th((size_t)std::max<int64_t>(nmax, 1));
-  std::vector<int32_t> ioff(kNumClasses + 1);
-  double item_ns[kNumClasses] = {0};
+  std::vector<int32_t> it((size_t)std::max<int64_t>(nmax, 1)), koff(kNumKeys + 1);
+  int32_t n_items = 0;
   hipError_t e = upload_args(p, ticks);
   if (e == hipSuccess) {
     enqueue(p, out, st, false);
     e = hipStreamSynchronize(st);
   }
-  if (e == hipSuccess) e = hipMemcpy(ioff.data(), p->item_off, sizeof(int32_t) * ioff.size(), hipMemcpyDeviceToHost);
-  if (e == hipSuccess && ioff[kNumClasses] > 0)
-    e = hipMemcpy(th.data(), ticks, sizeof(unsigned long long) * (size_t)ioff[kNumClasses], hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&n_items, p->item_off, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && (n_items < 0 || n_items > nmax)) e = hipErrorUnknown;
+  if (e == hipSuccess && n_items > 0) {
+    e = hipMemcpy(th.data(), ticks, sizeof(unsigned long long) * (size_t)n_items, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(it.data(), p->items, sizeof(int32_t) * (size_t)n_items, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(koff.data(), p->pr.key_off, sizeof(int32_t) * koff.size(), hipMemcpyDeviceToHost);
+  }
   (void)hipFree(ticks);
   if (e != hipSuccess) {
     p->meta = base;
     (void)upload_args(p, nullptr);
     return fail(ctx, SHGO_ERR_DEVICE, std::string("tuning run failed: ") + hipGetErrorString(e));
   }
-  for (int k = 0; k < kNumClasses; ++k) {
-    const int c = p->meta.order[k];
-    double sum = 0.0;
-    for (int i = ioff[k]; i < ioff[k + 1]; ++i) sum += 10.0 * (double)th[(size_t)i];
-    const int n_items = ioff[k + 1] - ioff[k];
-    if (n_items > 0) item_ns[c] = sum / n_items;  // per item of the default tiles
+  double sum_ns[kNumClasses] = {0}, units[kNumClasses] = {0};
+  for (int q = 0; q < n_items; ++q) {
+    const int c = it[q] >> 24, blk = it[q] & 0xffffff;
+    if (c < 0 || c >= kNumClasses) continue;
+    const int T = model.tiles[c];
+    const int start = koff[c * kKeysPerClass], end = koff[(c + 1) * kKeysPerClass];
+    const int tiles = (end - start + kTile - 1) / kTile;
+    const int nt = std::min(T, tiles - blk * T);
+    const int last = std::min(start + (blk * T + nt) * kTile, end) - 1;
+    int m = 0;
+    while (m + 1 < kKeysPerClass && koff[c * kKeysPerClass + m + 1] <= last) ++m;
+    m = std::max(m, 1);
+    const int tasks = nt * kClassGroups[c] * std::max(1, (m + kSliceIters - 1) / kSliceIters);
+    sum_ns[c] += 10.0 * (double)th[(size_t)q];
+    units[c] += (double)m * nt / std::min(8, tasks);
   }
-  // 2. candidates: the model order; classes by measured time per item (longest first); the
-  //    measured order with twice the default tiles where the LDS allows; the measured order with
-  //    one tile per item
+  // measured weights, scaled like the model's (largest 1024); classes without items keep theirs
+  float measured[kNumClasses];
+  double mx = 0.0;
+  for (int c = 0; c < kNumClasses; ++c)
+    if (units[c] > 0.0) mx = std::max(mx, sum_ns[c] / units[c]);
+  for (int c = 0; c < kNumClasses; ++c)
+    measured[c] = units[c] > 0.0 && mx > 0.0 ? (float)std::max(1.0, 1024.0 * sum_ns[c] / units[c] / mx) : model.weight[c];
+  // 2. candidates: the model weights; the measured weights; the measured weights with twice the
+  //    default tiles where the LDS allows; the measured weights with one tile per item
   ClassMeta cand[kTuneCandidates];
-  for (int v = 0; v < kTuneCandidates; ++v) cand[v] = p->meta;
-  std::vector<std::pair<double, int>> by;
-  for (int c = 0; c < kNumClasses; ++c) by.push_back({-item_ns[c], c});
-  std::stable_sort(by.begin(), by.end());
-  for (int v = 1; v < kTuneCandidates; ++v)
-    for (int k = 0; k < kNumClasses; ++k) cand[v].order[k] = by[k].second;
+  for (int v = 0; v < kTuneCandidates; ++v) {
+    cand[v] = model;
+    if (v > 0)
+      for (int c = 0; c < kNumClasses; ++c) cand[v].weight[c] = measured[c];
+  }
   for (int c = 0; c < kNumClasses; ++c) {
-    if (2 * p->meta.tiles[c] <= class_max_tiles(c)) cand[2].tiles[c] = 2 * p->meta.tiles[c];
+    if (2 * model.tiles[c] <= class_max_tiles(c)) cand[2].tiles[c] = 2 * model.tiles[c];
     cand[3].tiles[c] = 1;
   }
   // 3. time each candidate, keep the fastest
@@ -1661,9 +1778,9 @@ shgo_status shgo_execute_grad(shgo_plan* p, const double* D, double* dE_dnuclei,
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(tb), 0, st, e_out, (int64_t)1);
   if (p->n_cand > 0 && p->n_nuc > 0) {
     // shell-pair build (a1), as for the integrals
-    if (p->n_shells > 0) hipLaunchKernelGGL(k_prim_weights, dim3(blocks(p->n_shells)), dim3(tb), 0, st, p->bs);
-    hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-    hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->queue);
+    hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand) + blocks(p->n_shells)), dim3(tb), 0, st, p->bs, p->pr,
+                       blocks(p->n_cand));
+    hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->items, p->queue);
     hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
     s = grad_all<0, 0>(p, ga, st, true);
     if (s != SHGO_OK) return s;
@@ -1677,29 +1794,27 @@ int32_t shgo_max_tiles(int32_t class_id) {
   return class_id >= 0 && class_id < kNumClasses ? class_max_tiles(class_id) : -1;
 }
 
-shgo_status shgo_plan_get_schedule(const shgo_plan* p, int32_t* order, int32_t* tiles) {
-  if (!p || !order || !tiles) return SHGO_ERR_INVALID_ARG;
-  for (int k = 0; k < kNumClasses; ++k) {
-    order[k] = p->meta.order[k];
-    tiles[k] = p->meta.tiles[k];
+shgo_status shgo_plan_get_schedule(const shgo_plan* p, float* weight, int32_t* tiles) {
+  if (!p || !weight || !tiles) return SHGO_ERR_INVALID_ARG;
+  for (int c = 0; c < kNumClasses; ++c) {
+    weight[c] = p->meta.weight[c];
+    tiles[c] = p->meta.tiles[c];
   }
   return SHGO_OK;
 }
 
-shgo_status shgo_plan_set_schedule(shgo_plan* p, const int32_t* order, const int32_t* tiles) {
-  if (!p || !order || !tiles) return SHGO_ERR_INVALID_ARG;
-  bool seen[kNumClasses] = {false};
-  for (int k = 0; k < kNumClasses; ++k) {
-    if (order[k] < 0 || order[k] >= kNumClasses || seen[order[k]])
-      return fail(p->ctx, SHGO_ERR_INVALID_ARG, "order must be a permutation of the class ids");
-    seen[order[k]] = true;
-    if (tiles[k] < 1 || tiles[k] > class_max_tiles(k))
+shgo_status shgo_plan_set_schedule(shgo_plan* p, const float* weight, const int32_t* tiles) {
+  if (!p || !weight || !tiles) return SHGO_ERR_INVALID_ARG;
+  for (int c = 0; c < kNumClasses; ++c) {
+    if (!(weight[c] >= 1.0f && weight[c] <= 1.0e6f))
+      return fail(p->ctx, SHGO_ERR_INVALID_ARG, "weight[c] must be within 1..1e6");
+    if (tiles[c] < 1 || tiles[c] > class_max_tiles(c))
       return fail(p->ctx, SHGO_ERR_INVALID_ARG, "tiles[c] must be within 1..shgo_max_tiles(c)");
   }
   if (hipSetDevice(p->ctx->device) != hipSuccess) return fail(p->ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
-  for (int k = 0; k < kNumClasses; ++k) {
-    p->meta.order[k] = order[k];
-    p->meta.tiles[k] = tiles[k];
+  for (int c = 0; c < kNumClasses; ++c) {
+    p->meta.weight[c] = weight[c];
+    p->meta.tiles[c] = tiles[c];
   }
   drop_graph(p);
   const hipError_t e = upload_args(p, nullptr);

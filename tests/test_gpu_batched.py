@@ -66,17 +66,18 @@ def test_graph_replays_match_eager(shgo, molecule):
 
 
 @pytest.mark.parametrize("tiles", ["one", "max", "mixed"])
-def test_tiles_per_item_and_order(shgo, molecule, tiles):
+def test_tiles_per_item_and_weights(shgo, molecule, tiles):
     import torch
     b, n, ref = molecule
     plan, out = _plan(shgo, b, n, 1e-12)
     tmax = np.array([shgo.shgo_max_tiles(c) for c in range(28)], np.int32)
     t = {"one": np.ones(28, np.int32), "max": tmax,
          "mixed": np.minimum(tmax, np.arange(28, dtype=np.int32) % 3 + 1)}[tiles]
-    order = np.random.default_rng(len(tiles)).permutation(28).astype(np.int32)
-    shgo.shgo_plan_set_schedule(plan, order, t)
-    o2, t2 = shgo.shgo_plan_get_schedule(plan)
-    assert np.array_equal(o2, order) and np.array_equal(t2, t)
+    # any positive weights give the same integrals; they only order the work items
+    weight = np.random.default_rng(len(tiles)).uniform(1.0, 1e6, 28).astype(np.float32)
+    shgo.shgo_plan_set_schedule(plan, weight, t)
+    w2, t2 = shgo.shgo_plan_get_schedule(plan)
+    assert np.array_equal(w2, weight) and np.array_equal(t2, t)
     shgo.shgo_execute(plan, out)
     torch.cuda.synchronize()
     assert_parity(out.cpu().numpy(), ref, f"tiles {tiles}")
@@ -85,14 +86,16 @@ def test_tiles_per_item_and_order(shgo, molecule, tiles):
 def test_schedule_validation(shgo, molecule):
     b, n, _ = molecule
     plan, _ = _plan(shgo, b, n, 1e-12)
+    ones = np.ones(28, np.float32)
+    for w in (np.zeros(28, np.float32), np.full(28, np.nan, np.float32), np.full(28, 2e6, np.float32)):
+        with pytest.raises(shgo.ShgoError) as e:
+            shgo.shgo_plan_set_schedule(plan, w, np.ones(28, np.int32))
+        assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
     with pytest.raises(shgo.ShgoError) as e:
-        shgo.shgo_plan_set_schedule(plan, np.zeros(28, np.int32), np.ones(28, np.int32))
-    assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
-    with pytest.raises(shgo.ShgoError) as e:
-        shgo.shgo_plan_set_schedule(plan, np.arange(28, dtype=np.int32), np.full(28, 8, np.int32))
+        shgo.shgo_plan_set_schedule(plan, ones, np.full(28, 8, np.int32))
     assert e.value.status == shgo.SHGO_ERR_INVALID_ARG  # (6,6) blocks allow one tile per item
     with pytest.raises(shgo.ShgoError) as e:
-        shgo.shgo_plan_set_schedule(plan, np.arange(28, dtype=np.int32), np.zeros(28, np.int32))
+        shgo.shgo_plan_set_schedule(plan, ones, np.zeros(28, np.int32))
     assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
 
 

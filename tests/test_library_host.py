@@ -28,12 +28,12 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_max_tiles_follow_the_accumulator():
-    # tiles x ((2la+1)(2lb+1) x 65 + 256) doubles within 20464 (160 KB less 128 bytes), at most 8
+    # tiles x ((2la+1)(2lb+1) x 65 + 256) doubles within 20448 (160 KB less 256 bytes), at most 8
     for la in range(7):
         for lb in range(la + 1):
             c = la * (la + 1) // 2 + lb
             nab = (2 * la + 1) * (2 * lb + 1)
-            assert shgo.shgo_max_tiles(c) == min(8, 20464 // (nab * 65 + 256))
+            assert shgo.shgo_max_tiles(c) == min(8, 20448 // (nab * 65 + 256))
     assert shgo.shgo_max_tiles(28) == -1 and shgo.shgo_max_tiles(-1) == -1
 
 
