@@ -119,6 +119,53 @@ constexpr int kCostBuckets = 128;  // work items are dispatched by cost bucket, 
 constexpr int kSliceIters = 8;     // primitive-pair iterations per task of a long tile
 
 // ---------------------------------------------------------------------------------------------
+// Exponential (device)
+// ---------------------------------------------------------------------------------------------
+// The polynomial constants of an exponential inside the integral kernel's loops would otherwise be
+// kept in vector registers across the loop and, under the kernel's register pressure, spilled and
+// reloaded on every iteration. These helpers take the constant as a scalar operand (one per
+// instruction, the constant-bus limit), materialised in scalar registers.
+__device__ __forceinline__ double fma_vvs(double a, double b, double c) {  // a * b + c, c scalar
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+__device__ __forceinline__ double mul_vs(double a, double b) {  // a * b, b scalar
+  double r;
+  asm("v_mul_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+__device__ __forceinline__ double add_vs(double a, double b) {  // a + b, b scalar
+  double r;
+  asm("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+
+// e^{-t} for t >= 0 (0 once it underflows): Cody-Waite reduction t = n ln 2 - r with the two-part
+// ln 2 of fdlibm (n ln2_hi exact), |r| <= ln(2)/2, and the Taylor polynomial of e^r to degree 13
+// (remainder below 5e-18 relative) by Horner's rule, then the exponent n.
+__device__ __forceinline__ double exp_neg(double t) {
+  const double x = -fmin(t, 746.0);
+  const double n = rint(x * 1.4426950408889634074);  // log2(e)
+  double r = fma(n, -6.93147180369123816490e-01, x);
+  r = fma(n, -1.90821492927058770002e-10, r);
+  double q = add_vs(mul_vs(r, 1.6059043836821614599e-10), 2.0876756987868098979e-09);  // 1/13!, 1/12!
+  q = fma_vvs(q, r, 2.5052108385441718775e-08);  // 1/11!
+  q = fma_vvs(q, r, 2.7557319223985890653e-07);  // 1/10!
+  q = fma_vvs(q, r, 2.7557319223985890653e-06);  // 1/9!
+  q = fma_vvs(q, r, 2.4801587301587301587e-05);  // 1/8!
+  q = fma_vvs(q, r, 1.9841269841269841270e-04);  // 1/7!
+  q = fma_vvs(q, r, 1.3888888888888888889e-03);  // 1/6!
+  q = fma_vvs(q, r, 8.3333333333333333333e-03);  // 1/5!
+  q = fma_vvs(q, r, 4.1666666666666666667e-02);  // 1/4!
+  q = fma_vvs(q, r, 1.6666666666666666667e-01);  // 1/3!
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  q = fma(q, r, 1.0);
+  return ldexp(q, (int)n);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Boys function (device)
 // ---------------------------------------------------------------------------------------------
 // F_m(t) for m = 0..M. Below kBoysTcut: Taylor expansion of F_M about the nearest grid point,
@@ -128,7 +175,7 @@ constexpr int kSliceIters = 8;     // primitive-pair iterations per task of a lo
 // then the upward recursion F_{m+1} = ((2m+1) F_m - e^{-t})/(2t), stable for t > m.
 template <int M>
 __device__ __forceinline__ void boys(double t, double (&F)[M + 1], const double* __restrict__ tab) {
-  const double e = exp(-t);
+  const double e = exp_neg(t);
   if (t < kBoysTcut) {
     const int i = (int)(t * 16.0 + 0.5);
     const double d = -(t - 0.0625 * (double)i);
@@ -254,7 +301,7 @@ __device__ __forceinline__ void tri_pair(int64_t i, int n, int& a, int& b) {
 
 __device__ __forceinline__ bool keep_prim(double a, double b, double R2, double screen) {
   if (!(screen > 0.0)) return true;
-  return exp(-a * b / (a + b) * R2) > screen;
+  return exp_neg(a * b / (a + b) * R2) > screen;
 }
 
 // Classification in workgroups of 256 candidates: the key of each candidate, its rank among
@@ -395,14 +442,17 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta,
   int c, blk;
   for (int i = t; i < total; i += 1024) atomicAdd(&bcount[item_bucket(i, ioff, koff, meta, c, blk)], 1);
   __syncthreads();
-  if (t == 0) {  // bucket starts, most expensive bucket first
-    int pos = 0;
-    for (int b = kCostBuckets - 1; b >= 0; --b) {
-      const int n = bcount[b];
-      bcount[b] = pos;
-      pos += n;
-    }
+  // bucket starts, most expensive bucket first: inclusive scan of the counts in descending bucket
+  // order (part[r] for rank r = kCostBuckets - 1 - bucket), then shifted to exclusive starts
+  if (t < kCostBuckets) part[t] = bcount[kCostBuckets - 1 - t];
+  __syncthreads();
+  for (int off = 1; off < kCostBuckets; off <<= 1) {
+    const int v = t < kCostBuckets && t >= off ? part[t - off] : 0;
+    __syncthreads();
+    if (t < kCostBuckets) part[t] += v;
+    __syncthreads();
   }
+  if (t < kCostBuckets) bcount[kCostBuckets - 1 - t] = part[t] - bcount[kCostBuckets - 1 - t];
   __syncthreads();
   for (int i = t; i < total; i += 1024) {
     const int b = item_bucket(i, ioff, koff, meta, c, blk);
@@ -568,7 +618,7 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int it_be
         for (int k = 0; k < 8; ++k) nrow[k] = r[k];
       };
       auto nucleus = [&](double x, double y, double z, double r2, double t, double Zc, const double (&row)[8]) {
-        const double e = exp(-t);
+        const double e = exp_neg(t);
         double F[LM + 1];
         boys_row<LM>(t, e, row, F);
         double tj[LB + 1];
@@ -595,7 +645,7 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int it_be
         }
       }
       // prefactor -w_a w_b exp(-mu R^2) and 2 pi k!/p^{k+1}
-      const double K = exp(-a * b * ip * ps.R * ps.R);
+      const double K = exp_neg(a * b * ip * ps.R * ps.R);
       const double pre = -wa->bs.w[ps.o1 + pi] * wa->bs.w[ps.o2 + pj] * K;
       double fk[LB + 1];
       fk[0] = pre * 6.283185307179586477 * ip;
@@ -1022,7 +1072,7 @@ __global__ void __launch_bounds__(kGradThreads) k_grad(GradArgs ga) {
         const double p = a + b, ip = 1.0 / p, mu = a * b * ip;
         const double P[3] = {(a * ps.A[0] + b * ps.B[0]) * ip, (a * ps.A[1] + b * ps.B[1]) * ip,
                              (a * ps.A[2] + b * ps.B[2]) * ip};
-        const double K = exp(-mu * R * R);
+        const double K = exp_neg(mu * R * R);
         const double pre = -ga.bs.w[o1 + pi] * ga.bs.w[o2 + pj] * K;
         const double ta = b * R * ip, tb = -a * R * ip;
         if (lane <= LA) {
