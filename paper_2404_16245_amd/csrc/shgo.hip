@@ -44,8 +44,8 @@ namespace {
 // Constants and small types
 // ---------------------------------------------------------------------------------------------
 constexpr int kBoysOrders = 22;    // F_0..F_21 stored per grid point (mmax <= 14 with 8 Taylor terms)
-constexpr int kBoysPoints = 481;   // grid t_i = i/16, i = 0..480
-constexpr double kBoysTcut = 30.0; // below: table + downward recursion; above: asymptote + upward
+constexpr int kBoysPoints = 1153;  // grid t_i = i/16, i = 0..1152
+constexpr double kBoysTcut = 72.0; // below: table; above: asymptotic form (e^{-t} < 6e-32)
 constexpr int kNumClasses = (SHGO_LMAX + 1) * (SHGO_LMAX + 2) / 2;  // (la, lb) with la >= lb
 constexpr int kKeysPerClass = 256;
 constexpr int kTile = SHGO_TILE;
@@ -207,37 +207,51 @@ __device__ __forceinline__ void boys(double t, double (&F)[M + 1], const double*
   }
 }
 
-// The same evaluation with the Taylor row F_{M..M+7}(t_i) already loaded (row[k], k < 8) and
-// e = exp(-t): used by the integral kernels, which fetch the row of the next nucleus early.
+// x^N by repeated squaring (depth log2 N).
+template <int N>
+__device__ __forceinline__ double pow_n(double x) {
+  if constexpr (N == 0) {
+    return 1.0;
+  } else if constexpr (N == 1) {
+    return x;
+  } else {
+    const double h = pow_n<N / 2>(x);
+    return (N & 1) ? h * h * x : h * h;
+  }
+}
+// Gamma(M + 1/2) / 2 = sqrt(pi) (2M-1)!! / 2^{M+1}
+__host__ __device__ constexpr double half_gamma_half(int M) {
+  double c = 0.88622692545275801365;
+  for (int k = 1; k <= M; ++k) c *= (2.0 * k - 1.0) * 0.5;
+  return c;
+}
+
+// The same evaluation for the integral kernel, with the Taylor row F_{M..M+7}(t_i) of the nearest
+// grid point (clamped to the table) already loaded and e = exp(-t), and no divergent branch: F_M
+// is the table's Taylor series below kBoysTcut and the leading asymptotic term
+// Gamma(M+1/2) / (2 t^{M+1/2}) above it (the neglected part is below e^{-t}/t, 1e-17 relative for
+// M <= 12 at t = 72), selected per lane; then the downward recursion, stable for every t.
 template <int M>
 __device__ __forceinline__ void boys_row(double t, double e, const double (&row)[8], double (&F)[M + 1]) {
-  if (t < kBoysTcut) {
-    const int i = (int)(t * 16.0 + 0.5);
-    const double d = -(t - 0.0625 * (double)i);
-    double f = row[7];
-    f = fma(f, d * (1.0 / 7.0), row[6]);
-    f = fma(f, d * (1.0 / 6.0), row[5]);
-    f = fma(f, d * (1.0 / 5.0), row[4]);
-    f = fma(f, d * (1.0 / 4.0), row[3]);
-    f = fma(f, d * (1.0 / 3.0), row[2]);
-    f = fma(f, d * (1.0 / 2.0), row[1]);
-    f = fma(f, d, row[0]);
-    F[M] = f;
-    const double t2 = 2.0 * t;
+  const int i = (int)(fmin(t, kBoysTcut) * 16.0 + 0.5);
+  const double d = -(t - 0.0625 * (double)i);
+  double f = row[7];
+  f = fma(f, d * (1.0 / 7.0), row[6]);
+  f = fma(f, d * (1.0 / 6.0), row[5]);
+  f = fma(f, d * (1.0 / 5.0), row[4]);
+  f = fma(f, d * (1.0 / 4.0), row[3]);
+  f = fma(f, d * (1.0 / 3.0), row[2]);
+  f = fma(f, d * (1.0 / 2.0), row[1]);
+  f = fma(f, d, row[0]);
+  // 1/sqrt(t) from the hardware estimate and two Newton steps (each doubles the bits)
+  double rs = __builtin_amdgcn_rsq(t);
+  rs = rs * fma(-0.5 * t * rs, rs, 1.5);
+  rs = rs * fma(-0.5 * t * rs, rs, 1.5);
+  const double fa = half_gamma_half(M) * rs * pow_n<M>(rs * rs);
+  F[M] = t < kBoysTcut ? f : fa;
+  const double t2 = 2.0 * t;
 #pragma unroll
-    for (int m = M - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
-  } else {
-    double rs = __builtin_amdgcn_rsq(t);
-    rs = rs * fma(-0.5 * t * rs, rs, 1.5);
-    rs = rs * fma(-0.5 * t * rs, rs, 1.5);
-    const double it = rs * rs;
-    const double f0 = 0.88622692545275801365 * rs;
-    const double corr = 0.5 * e * it * fma(it, fma(it, 0.75, -0.5), 1.0);
-    F[0] = f0 - corr;
-    const double h = 0.5 * it;
-#pragma unroll
-    for (int m = 0; m < M; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -e) * h;
-  }
+  for (int m = M - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
 }
 
 template <int M>
@@ -612,7 +626,7 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int it_be
         nr2 = fma(cx, cx, fma(cy, cy, cz * cz));
         nt = p * nr2;
         nZ = nucs[c].Z;
-        const int i = min((int)(nt * 16.0 + 0.5), kBoysPoints - 1);
+        const int i = (int)(fmin(nt, kBoysTcut) * 16.0 + 0.5);  // 0 .. kBoysPoints - 1
         const double* __restrict__ r = wa->boys_tab + i * kBoysOrders + LM;
 #pragma unroll
         for (int k = 0; k < 8; ++k) nrow[k] = r[k];
@@ -1180,7 +1194,7 @@ size_t grad_lds_bytes(int n_nuc) {
 // ---------------------------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------------------------
-// Boys table F_m(i/16), m < kBoysOrders, by the convergent series in long double.
+// Boys table F_m(i/16), m < kBoysOrders, by the convergent series in long double (positive terms).
 std::vector<double> boys_table() {
   std::vector<double> tab((size_t)kBoysPoints * kBoysOrders);
   for (int i = 0; i < kBoysPoints; ++i) {
