@@ -521,16 +521,26 @@ def emit_group(LA, LB, gi, group):
     # (c_L = prod of the sectoral and vertical recurrence coefficients); c_L is applied in scale().
     o.append("  static __device__ __forceinline__ void step(double (&W)[NW], double x, double y, double z, double r2,")
     o.append(f"                                               double Z, const double (&F)[{LM + 1}], const double (&tj)[{LB + 1}]) {{")
-    o.append("    double sc = Z, ss = 0.0;")
-    cur_sect = 0
+    # sectoral seeds Z (x + iy)^mu of the group's families: powers of two by squaring, the rest as
+    # products of those (depth log2 mu instead of a chain of mu complex multiplications)
+    needed = sorted(set(mu for (mu, sg) in group if mu > 0))
+    if needed:
+        o.append("    const double zr1 = x, zi1 = y;")
+        k = 2
+        while k <= max(needed):
+            h = k // 2
+            o.append(f"    const double zr{k} = fma(zr{h}, zr{h}, -zi{h} * zi{h}), zi{k} = 2.0 * zr{h} * zi{h};")
+            k *= 2
+        for mu in needed:
+            bits = [1 << b for b in range(mu.bit_length()) if mu >> b & 1]
+            ar, ai = f"zr{bits[0]}", f"zi{bits[0]}"
+            for j, b in enumerate(bits[1:]):
+                o.append(f"    const double pr{mu}_{j} = fma({ar}, zr{b}, -{ai} * zi{b}), "
+                         f"pi{mu}_{j} = fma({ar}, zi{b}, {ai} * zr{b});")
+                ar, ai = f"pr{mu}_{j}", f"pi{mu}_{j}"
+            o.append(f"    const double sc{mu} = Z * {ar}, ss{mu} = Z * {ai};")
     for (mu, sg) in group:
-        while cur_sect < mu:
-            if cur_sect == 0:
-                o.append("    sc = Z * x; ss = Z * y;")
-            else:
-                o.append("    { const double nc = fma(x, sc, -y * ss); ss = fma(y, sc, x * ss); sc = nc; }")
-            cur_sect += 1
-        q = "sc" if sg > 0 else "ss"
+        q = "Z" if mu == 0 else (f"sc{mu}" if sg > 0 else f"ss{mu}")
         o.append(f"    {{ // half-family M = {sg * mu}")
         o.append(f"      double cq = {q}, pq = 0.0;")
         for L in range(mu, LM + 1):
