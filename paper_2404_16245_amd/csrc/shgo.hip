@@ -318,12 +318,13 @@ __device__ __forceinline__ bool keep_prim(double a, double b, double R2, double 
   return exp_neg(a * b / (a + b) * R2) > screen;
 }
 
-// Classification in workgroups of 256 candidates: the key of each candidate, its rank among
+// Classification in workgroups of 1024 candidates: the key of each candidate, its rank among
 // the workgroup's candidates with the same key (LDS atomics), and one global atomic per
 // (workgroup, key) that reserves the workgroup's range inside the key's bucket. Workgroups from
 // classify_blocks on compute the shells' normalised primitive weights instead (independent work,
 // in the same launch).
-__global__ void __launch_bounds__(256) k_classify(DevBasis bs, DevPairs pr, int classify_blocks) {
+constexpr int kClassifyThreads = 1024;
+__global__ void __launch_bounds__(kClassifyThreads) k_classify(DevBasis bs, DevPairs pr, int classify_blocks) {
   if ((int)blockIdx.x >= classify_blocks) {
     const int s = ((int)blockIdx.x - classify_blocks) * blockDim.x + threadIdx.x;
     if (s < bs.n_shells) prim_weights_of(bs, s);
@@ -373,8 +374,15 @@ __global__ void __launch_bounds__(256) k_classify(DevBasis bs, DevPairs pr, int 
 // of its last slot, keys being sorted within the class) times its tiles, over the wavefronts its
 // tasks keep busy; four buckets per octave.
 __device__ int item_bucket(int i, const int* ioff, const int* koff, const ClassMeta& meta, int& c, int& blk) {
-  c = 0;
-  while (ioff[c + 1] <= i) ++c;
+  int lo_c = 0, hi_c = kNumClasses - 1;  // the last class whose items start at or below i
+  while (lo_c < hi_c) {
+    const int mid = (lo_c + hi_c + 1) >> 1;
+    if (ioff[mid] <= i)
+      lo_c = mid;
+    else
+      hi_c = mid - 1;
+  }
+  c = lo_c;
   blk = i - ioff[c];
   const int T = meta.tiles[c];
   const int start = koff[c * kKeysPerClass], end = koff[(c + 1) * kKeysPerClass];
@@ -440,16 +448,19 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta,
     koff[kNumKeys] = part[1023];
   }
   __syncthreads();
-  if (t == 0) {
+  if (t < kNumClasses) {  // items of class t
+    const int tiles = (koff[(t + 1) * kKeysPerClass] - koff[t * kKeysPerClass] + kTile - 1) / kTile;
+    part[t] = (tiles + meta.tiles[t] - 1) / meta.tiles[t];
+  }
+  __syncthreads();
+  if (t <= kNumClasses) {  // first item of class t (t = kNumClasses: the total)
     int off = 0;
-    for (int c = 0; c < kNumClasses; ++c) {
-      const int tiles = (koff[(c + 1) * kKeysPerClass] - koff[c * kKeysPerClass] + kTile - 1) / kTile;
-      ioff[c] = off;
-      off += (tiles + meta.tiles[c] - 1) / meta.tiles[c];
+    for (int c = 0; c < t; ++c) off += part[c];
+    ioff[t] = off;
+    if (t == kNumClasses) {
+      item_off[0] = off;
+      queue[0] = 0;
     }
-    ioff[kNumClasses] = off;
-    item_off[0] = off;
-    queue[0] = 0;
   }
   __syncthreads();
   const int total = ioff[kNumClasses];
@@ -1366,8 +1377,9 @@ void enqueue(shgo_plan* p, double* out, hipStream_t st, bool timed) {
   };
   mark(0, 0);
   // key_count is zero here: cleared at plan creation and by every k_scan_keys after reading it
-  hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand) + blocks(p->n_shells)), dim3(tb), 0, st, p->bs, p->pr,
-                     blocks(p->n_cand));
+  const int cb = (int)((p->n_cand + kClassifyThreads - 1) / kClassifyThreads);
+  const int wb = (int)((p->n_shells + kClassifyThreads - 1) / kClassifyThreads);
+  hipLaunchKernelGGL(k_classify, dim3(cb + wb), dim3(kClassifyThreads), 0, st, p->bs, p->pr, cb);
   hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->items, p->queue);
   hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
   mark(0, 1);
@@ -1842,8 +1854,9 @@ shgo_status shgo_execute_grad(shgo_plan* p, const double* D, double* dE_dnuclei,
   hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(tb), 0, st, e_out, (int64_t)1);
   if (p->n_cand > 0 && p->n_nuc > 0) {
     // shell-pair build (a1), as for the integrals
-    hipLaunchKernelGGL(k_classify, dim3(blocks(p->n_cand) + blocks(p->n_shells)), dim3(tb), 0, st, p->bs, p->pr,
-                       blocks(p->n_cand));
+    const int cb = (int)((p->n_cand + kClassifyThreads - 1) / kClassifyThreads);
+    const int wb = (int)((p->n_shells + kClassifyThreads - 1) / kClassifyThreads);
+    hipLaunchKernelGGL(k_classify, dim3(cb + wb), dim3(kClassifyThreads), 0, st, p->bs, p->pr, cb);
     hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->items, p->queue);
     hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
     s = grad_all<0, 0>(p, ga, st, true);
