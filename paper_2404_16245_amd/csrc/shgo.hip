@@ -779,11 +779,17 @@ __device__ __attribute__((noinline)) void process_block(int b, const WorkArgs* w
   __syncthreads();
   // tasks (tile, slice of at most kSliceIters primitive-pair iterations, group), tile-major, handed
   // to the wavefronts by an LDS counter
+  // The first task of wavefront w is task w (groups are generated heaviest first, and the older
+  // wavefronts of a SIMD issue first), the rest come from the counter, which starts at kWaves.
   const int n_nuc = wa->n_nuc;
+  bool first = true;
   while (true) {
-    int task = 0;
-    if (lane == 0) task = atomicAdd(task_ctr, 1);
-    task = __shfl(task, 0);
+    int task = wave;
+    if (!first) {
+      if (lane == 0) task = atomicAdd(task_ctr, 1);
+      task = __shfl(task, 0);
+    }
+    first = false;
     int u = task / Q;
     const int g = task - u * Q;
     int t = 0, m = 0;
@@ -929,7 +935,7 @@ k_integrals(const WorkArgs* __restrict__ wa_ptr, double* __restrict__ out) {
   if (threadIdx.x == 0) s_item = atomicAdd(wa->queue, 1);
   const int total = wa->item_off[0];
   while (true) {
-    if (threadIdx.x == 0) s_task = 0;
+    if (threadIdx.x == 0) s_task = kIntegralThreads / 64;
     __syncthreads();
     const int q = s_item;
     if (q >= total) break;
