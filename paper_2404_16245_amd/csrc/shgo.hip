@@ -850,10 +850,19 @@ __device__ __attribute__((noinline)) void process_block(int b, const WorkArgs* w
   }
   __syncthreads();
   // Output: consecutive threads take consecutive entries of one pair's block, so every store
-  // instruction covers a few contiguous lines. Destinations come from the pair build (dst0, dst1);
-  // four entries per thread and round keep four destination loads in flight.
+  // instruction covers a few contiguous lines. The pairs' destinations from the pair build (dst0,
+  // dst1) are first copied into the frames area, which the rotations no longer need.
   const int base = start + t0 * kTile;
   const int n_out = nt * kTile * NAB;
+  int64_t* const dst = (int64_t*)frm;  // [tile * 64 + pair][2]
+  for (int j = threadIdx.x; j < nt * kTile; j += kIntegralThreads) {
+    const int slot = base + j;
+    if (slot < end) {
+      dst[2 * j] = wa->pr.dst0[slot];
+      dst[2 * j + 1] = wa->pr.dst1[slot];
+    }
+  }
+  __syncthreads();
   constexpr int kU = 4;
   if (wa->pr.full) {
     const int64_t n = wa->bs.nbf;
@@ -867,7 +876,7 @@ __device__ __attribute__((noinline)) void process_block(int b, const WorkArgs* w
           const int tp = j / NAB, e = j - tp * NAB;  // tp = tile * 64 + pair
           const int slot = base + tp;
           if (j < n_out && slot < end) {
-            const int64_t r0 = wa->pr.dst0[slot], c0 = wa->pr.dst1[slot];
+            const int64_t r0 = dst[2 * tp], c0 = dst[2 * tp + 1];
             int i, col;
             if (pass == 0) {
               i = e / NB;
@@ -896,8 +905,8 @@ __device__ __attribute__((noinline)) void process_block(int b, const WorkArgs* w
         const int tp = j / NAB, e = j - tp * NAB;
         const int slot = base + tp;
         if (j < n_out && slot < end) {
-          const int64_t bo = wa->pr.dst0[slot];
-          const bool sw = wa->pr.dst1[slot] != 0;
+          const int64_t bo = dst[2 * tp];
+          const bool sw = dst[2 * tp + 1] != 0;
           int src = e;
           if (sw) {  // output entry e = col NA + i holds V(i, col)
             const int col = e / NA, i = e - col * NA;
