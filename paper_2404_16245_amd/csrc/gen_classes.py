@@ -36,6 +36,14 @@ import numpy as np
 
 LMAX_SHELL = 6
 DEFAULT_CAP = 64          # register budget of one group, in doubles of W
+# Classes whose budget differs, so that their group count Q times the tiles per work item that the
+# LDS allows makes eight tasks for the eight wavefronts of a workgroup: four groups of at most 72
+# (with two tiles per item) instead of five of 64, four of 44 instead of three of 64.
+CLASS_CAP = {(5, 5): 72, (6, 4): 72, (4, 4): 44, (5, 3): 44, (6, 2): 44}
+
+
+def class_cap(LA, LB):
+    return CLASS_CAP.get((LA, LB), DEFAULT_CAP)
 KEEP = 1e-14              # drop real Gaunt coefficients below this magnitude
 
 
@@ -274,9 +282,11 @@ def unit_of(M):
     return (abs(M), 1 if M >= 0 else -1)
 
 
-def class_groups(LA, LB, cap=DEFAULT_CAP):
+def class_groups(LA, LB, cap=None):
     """Partition the half-families into groups of at most max(cap, largest half-family) entries
     (largest first, each into the least loaded group it fits)."""
+    if cap is None:
+        cap = class_cap(LA, LB)
     units = class_units(LA, LB)
     size = {u: len(unit_entries(LA, LB, u)) for u in units}
     c = max(cap, max(size.values()))
@@ -369,7 +379,7 @@ def zrot(l, c, s):
     return Zm
 
 
-def emulate_block(LA, LB, A, B, ea, wa, eb, wb, nuc_pos, nuc_Z, cap=DEFAULT_CAP, boys=boys_np):
+def emulate_block(LA, LB, A, B, ea, wa, eb, wb, nuc_pos, nuc_Z, cap=None, boys=boys_np):
     """The V block (2LA+1) x (2LB+1) of shells (LA at A) x (LB at B), computed by the emitted
     algorithm in numpy. ``wa``/``wb`` are the final primitive weights (contraction x norm)."""
     A, B = np.asarray(A, float), np.asarray(B, float)
@@ -828,10 +838,10 @@ def emit_grad_header(lmax=LMAX_SHELL):
     return "\n".join(out) + "\n"
 
 
-def emit_header(cap=DEFAULT_CAP, lmax=LMAX_SHELL):
+def emit_header(cap=None, lmax=LMAX_SHELL):
     out = ["// Generated by gen_classes.py -- do not edit. Class-specific code of the nuclear-attraction",
            "// kernel: nucleus step, coupling (product rule + shift along the A->B axis) and rotations.",
-           f"// Group register budget: {cap} doubles.",
+           f"// Group register budget: {cap if cap is not None else 'per class (class_cap)'} doubles.",
            "#pragma once",
            "",
            "template <int L> struct Rot;"]
@@ -858,7 +868,7 @@ def emit_header(cap=DEFAULT_CAP, lmax=LMAX_SHELL):
 def main(argv):
     out = argv[1] if len(argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)), "generated",
                                                      "shgo_classes.inc")
-    cap = DEFAULT_CAP
+    cap = None
     if "--cap" in argv:
         cap = int(argv[argv.index("--cap") + 1])
     os.makedirs(os.path.dirname(out), exist_ok=True)

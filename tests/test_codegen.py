@@ -111,7 +111,7 @@ def test_groups_partition_families():
             groups = gc.class_groups(LA, LB)
             units = sorted(u for g in groups for u in g)
             assert units == sorted(gc.class_units(LA, LB))
-            cap = max(gc.DEFAULT_CAP, max(len(gc.unit_entries(LA, LB, u)) for u in units))
+            cap = max(gc.class_cap(LA, LB), max(len(gc.unit_entries(LA, LB, u)) for u in units))
             assert all(sum(len(gc.unit_entries(LA, LB, u)) for u in g) <= cap for g in groups)
             # the half-families together hold every W entry of every |M| family exactly once
             ent = sorted(e for g in groups for u in g for e in gc.unit_entries(LA, LB, u))
