@@ -137,6 +137,17 @@ def gradient_molecule(seed=5):
     return molecule(seed=seed, n_atoms=500, box=30.0, ls=(0, 1, 2, 3), kmax=6)
 
 
+def long_contractions(seed=71):
+    """Three atoms with s..g shells of 1 to 20 primitives: shell pairs of up to 400 primitive
+    pairs, more than an 8-bit count holds, next to short ones; returns (basis, nuclei)."""
+    rng = np.random.default_rng(seed)
+    atoms = rng.uniform(0.0, 3.0, (3, 3))
+    ls = np.array([0, 3, 1, 2, 4, 2], np.int32)
+    ks = np.array([16, 20, 4, 20, 16, 1], np.int32)
+    basis = _basis_from_lists(atoms[[0, 0, 1, 1, 2, 2]], ls, ks, rng, 0.05, 500.0, 0.1, 1.0)
+    return basis, Nuclei(atoms.copy(), np.array([3.0, 6.0, 8.0]))
+
+
 def density(nbf, seed=5, sigma=0.1):
     """Symmetric matrix with iid N(0, sigma^2) upper triangle (diagonal included)."""
     rng = np.random.default_rng(seed + 1000)

@@ -73,6 +73,14 @@ def test_many_nuclei_span_several_lane_rounds(shgo):
     assert_grad(gpu_grad(shgo, b, n, D), oracle.grad(b, n, D), "150 nuclei")
 
 
+def test_long_contractions(shgo):
+    # shell pairs of 256 to 400 primitive pairs (the pair key saturates), screened and not
+    b, n = synth.long_contractions(seed=71)
+    D = synth.density(b.nbf(), seed=8)
+    for screen in (0.0, 1e-6):
+        assert_grad(gpu_grad(shgo, b, n, D, screen), oracle.grad(b, n, D, screen=screen), f"K up to 20, screen {screen}")
+
+
 def test_central_differences_of_gpu_energies(shgo):
     import torch
     b, n = synth.molecule(seed=55, n_atoms=6, box=6.0, ls=(0, 1, 2, 3), kmax=4)

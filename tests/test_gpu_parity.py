@@ -105,6 +105,16 @@ def test_edge_cases(shgo):
     assert shgo.nuclear_attraction_pairs(b, n, [], []).numel() == 0
 
 
+def test_long_contractions_saturate_the_pair_key(shgo):
+    # The key of a pair with 255 or more surviving primitive pairs saturates; the kernel then
+    # visits every candidate primitive pair of the shells and skips the screened ones.
+    b, n = synth.long_contractions(seed=71)
+    assert (b.nprim[:, None] * b.nprim[None, :] >= 255).any()
+    for screen in (0.0, 1e-12, 1e-6):
+        V = shgo.nuclear_attraction(b, n, screen=screen).cpu().numpy()
+        assert_parity(V, oracle.nuc_matrix(b, n, screen=screen), what=f"K up to 20, screen {screen}")
+
+
 def test_full_sweep_sampled(shgo):
     # the full high-l sweep (49 classes x 2041 pairs, 64 nuclei), checked on sampled blocks
     hb, hn, pa, pb = synth.high_l_sweep(seed=2)
