@@ -145,7 +145,9 @@ shgo_status shgo_execute_graph(shgo_plan* plan, double* out, void* stream);
  *              default comes from an operation-count model, largest 1024)
  *   tiles[28]  tiles per work item of each class, 1 <= tiles[c] <= shgo_max_tiles(c) (the LDS of
  *              a work item holds per tile (2la+1)(2lb+1) x 65 accumulator doubles and 256 frame
- *              doubles, at most 20448 doubles in all)
+ *              doubles, at most 20448 doubles in all). A new plan's default is the fewest tiles
+ *              that give the eight wavefronts eight tasks, from the class's groups and its mean
+ *              slices per pair, ceil(K_a K_b / 8) capped at 8, over its candidate pairs.
  * get copies the plan's schedule out; set validates (SHGO_ERR_INVALID_ARG) and installs one, e.g. a
  * schedule saved from an earlier autotune of the same workload. Results do not depend on the
  * schedule beyond rounding. */
@@ -158,11 +160,15 @@ shgo_status shgo_plan_set_schedule(shgo_plan* plan, const float* weight, const i
  * and per-item timing, which measures each class's time per unit of the item estimate; builds
  * SHGO_TUNE_CANDIDATES schedules -- 0: the model weights with the default tiles; 1: the measured
  * weights with the default tiles; 2: the measured weights with twice the default tiles where the
- * LDS allows; 3: the measured weights with one tile per item -- times `rounds` executions of each on
- * `stream` (the call synchronizes the stream), and keeps the fastest. ms[SHGO_TUNE_CANDIDATES] (or
- * NULL) receives each candidate's milliseconds per execution, *chosen (or NULL) the index kept.
- * `out` is written as by shgo_execute. */
-#define SHGO_TUNE_CANDIDATES 4
+ * LDS allows; 3: the measured weights with one tile per item; 4: the measured weights with half the
+ * default tiles (at least one) -- times `rounds` executions of each on `stream` (the call
+ * synchronizes the stream), and keeps the fastest. It then refines that schedule class by class
+ * (half and twice a class's tiles; a change is kept when it is more than 1% faster, confirmed by a
+ * second timing beside the incumbent's; at most two passes) and installs the result.
+ * ms[SHGO_TUNE_CANDIDATES] (or NULL) receives each candidate's milliseconds per execution, *chosen
+ * (or NULL) the index of the candidate the refinement started from. `out` is written as by
+ * shgo_execute. */
+#define SHGO_TUNE_CANDIDATES 5
 shgo_status shgo_plan_autotune(shgo_plan* plan, double* out, int32_t rounds, void* stream, double* ms,
                                int32_t* chosen);
 

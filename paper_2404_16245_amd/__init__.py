@@ -32,7 +32,7 @@ EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_erro
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
             "shgo_plan_autotune", "shgo_max_tiles"]
 SHGO_NUM_CLASSES = 28
-SHGO_TUNE_CANDIDATES = 4
+SHGO_TUNE_CANDIDATES = 5
 SHGO_NUM_PHASES = 2
 
 
@@ -281,7 +281,8 @@ def shgo_plan_set_schedule(plan, weight, tiles):
 
 
 def shgo_plan_autotune(plan, out, rounds=5, stream=None):
-    """Tune the plan's schedule; returns (ms per candidate [4], index kept). Synchronizes."""
+    """Tune the plan's schedule; returns (ms per candidate [5], index of the candidate refined and
+    kept). Synchronizes."""
     lib = load_library()
     ms = np.zeros(SHGO_TUNE_CANDIDATES)
     chosen = np.zeros(1, dtype=np.int32)

@@ -1274,6 +1274,7 @@ struct shgo_plan {
   int64_t nbf = 0, n_cand = 0, out_size = 0, integrals = 0;
   double screen = 0.0;
   int class_cand[kNumClasses] = {0};  // candidate pairs per class (bounds the sorted counts)
+  int32_t def_tiles[kNumClasses] = {0};  // default tiles per work item of each class
   std::vector<void*> allocs;
   DevBasis bs{};
   DevPairs pr{};
@@ -1298,7 +1299,7 @@ struct shgo_plan {
 
 namespace {
 
-constexpr int kTuneCandidates = 4;
+constexpr int kTuneCandidates = 5;
 
 void drop_graph(shgo_plan* p) {
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
@@ -1378,8 +1379,53 @@ size_t acc_bytes(const shgo_plan* p) {
   return m;
 }
 
-// Default tiles per work item: enough (tile, group) tasks for the eight wavefronts, within LDS.
-int default_tiles(int c) { return std::max(1, std::min(class_max_tiles(c), (8 + kClassGroups[c] - 1) / kClassGroups[c])); }
+// Default tiles per work item of class c: enough (tile, slice, group) tasks for the eight
+// wavefronts, within LDS. `slices` is the class's mean over its candidate pairs of
+// ceil(K_a K_b / kSliceIters), capped at 8 (screening only lowers it).
+int default_tiles(int c, double slices) {
+  const double tasks_per_tile = kClassGroups[c] * std::max(1.0, slices);
+  const int t = (int)std::ceil(8.0 / tasks_per_tile - 1e-9);
+  return std::max(1, std::min(class_max_tiles(c), t));
+}
+
+// Mean primitive-pair slices per candidate pair of each class, before screening (the matrix
+// plan's pairs a <= b counted from a histogram of shells by l and primitive count).
+void mean_slices(const shgo_basis* b, int full, int64_t n_pairs, const int32_t* pa, const int32_t* pb,
+                 double* mean) {
+  double sum[kNumClasses] = {0}, cnt[kNumClasses] = {0};
+  auto sl = [](int64_t ka, int64_t kb) { return (double)std::min<int64_t>(8, (ka * kb + kSliceIters - 1) / kSliceIters); };
+  auto cls = [](int la, int lb) { return class_id(std::max(la, lb), std::min(la, lb)); };
+  if (full) {
+    constexpr int kK = 64;  // primitive counts above this have the capped slice count too
+    std::vector<double> h((size_t)(SHGO_LMAX + 1) * (kK + 1), 0.0);
+    for (int s = 0; s < b->n_shells; ++s) h[(size_t)b->l[s] * (kK + 1) + std::min(b->n_prim[s], kK)] += 1.0;
+    for (int la = 0; la <= SHGO_LMAX; ++la)
+      for (int lb = 0; lb <= la; ++lb)
+        for (int ka = 1; ka <= kK; ++ka)
+          for (int kb = 1; kb <= kK; ++kb) {
+            const double na = h[(size_t)la * (kK + 1) + ka], nb = h[(size_t)lb * (kK + 1) + kb];
+            if (na == 0.0 || nb == 0.0) continue;
+            double n;
+            if (la != lb)
+              n = na * nb;
+            else if (ka < kb)
+              n = na * nb;
+            else if (ka == kb)
+              n = na * (na + 1.0) / 2.0;
+            else
+              continue;
+            sum[cls(la, lb)] += n * sl(ka, kb);
+            cnt[cls(la, lb)] += n;
+          }
+  } else {
+    for (int64_t i = 0; i < n_pairs; ++i) {
+      const int c = cls(b->l[pa[i]], b->l[pb[i]]);
+      sum[c] += sl(b->n_prim[pa[i]], b->n_prim[pb[i]]);
+      cnt[c] += 1.0;
+    }
+  }
+  for (int c = 0; c < kNumClasses; ++c) mean[c] = cnt[c] > 0.0 ? sum[c] / cnt[c] : 1.0;
+}
 
 // The launches of one evaluation on `st`: pair build (a1), then the persistent integral kernel.
 // With `timed`, HIP events bracket the two phases (never inside a graph capture).
@@ -1498,9 +1544,14 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
   e = e != hipSuccess ? e : dalloc(p, &pr.dst1, (size_t)p->n_cand);
   // persistent-kernel schedule: tiles per work item and the model weight of each class
   model_weights(n->n_nuclei, p->meta.weight);
-  for (int c = 0; c < kNumClasses; ++c) {
-    p->meta.tiles[c] = default_tiles(c);
-    p->meta.groups[c] = kClassGroups[c];
+  {
+    double slices[kNumClasses];
+    mean_slices(b, full, n_pairs, pa, pb, slices);
+    for (int c = 0; c < kNumClasses; ++c) {
+      p->def_tiles[c] = default_tiles(c, slices[c]);
+      p->meta.tiles[c] = p->def_tiles[c];
+      p->meta.groups[c] = kClassGroups[c];
+    }
   }
   e = e != hipSuccess ? e : dalloc(p, &p->queue, 1);
   e = e != hipSuccess ? e : dalloc(p, &p->item_off, (size_t)kNumClasses + 1);
@@ -1749,7 +1800,7 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
   //    unit of the items' estimate (iterations of the longest tile x tiles / busy wavefronts)
   ClassMeta base = p->meta;
   model_weights(p->n_nuc, p->meta.weight);
-  for (int c = 0; c < kNumClasses; ++c) p->meta.tiles[c] = default_tiles(c);
+  for (int c = 0; c < kNumClasses; ++c) p->meta.tiles[c] = p->def_tiles[c];
   const ClassMeta model = p->meta;
   const int64_t nmax = max_items(p);
   unsigned long long* ticks = nullptr;
@@ -1800,7 +1851,8 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
   for (int c = 0; c < kNumClasses; ++c)
     measured[c] = units[c] > 0.0 && mx > 0.0 ? (float)std::max(1.0, 1024.0 * sum_ns[c] / units[c] / mx) : model.weight[c];
   // 2. candidates: the model weights; the measured weights; the measured weights with twice the
-  //    default tiles where the LDS allows; the measured weights with one tile per item
+  //    default tiles where the LDS allows; the measured weights with one tile per item; the
+  //    measured weights with half the default tiles
   ClassMeta cand[kTuneCandidates];
   for (int v = 0; v < kTuneCandidates; ++v) {
     cand[v] = model;
@@ -1810,8 +1862,9 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
   for (int c = 0; c < kNumClasses; ++c) {
     if (2 * model.tiles[c] <= class_max_tiles(c)) cand[2].tiles[c] = 2 * model.tiles[c];
     cand[3].tiles[c] = 1;
+    cand[4].tiles[c] = std::max(1, model.tiles[c] / 2);
   }
-  // 3. time each candidate, keep the fastest
+  // 3. time each candidate and keep the fastest
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1819,29 +1872,67 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
     (void)upload_args(p, nullptr);
     return fail(ctx, SHGO_ERR_DEVICE, "hipEventCreate failed");
   }
+  auto time_schedule = [&](const ClassMeta& m, double& per) {
+    p->meta = m;
+    hipError_t r = upload_args(p, nullptr);
+    if (r != hipSuccess) return r;
+    enqueue(p, out, st, false);  // warm
+    (void)hipEventRecord(e0, st);
+    for (int k = 0; k < rounds; ++k) enqueue(p, out, st, false);
+    (void)hipEventRecord(e1, st);
+    r = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&t, e0, e1);
+    per = (double)t / rounds;
+    return r;
+  };
   int best = 0;
   double best_ms = 0.0;
   for (int v = 0; v < kTuneCandidates && e == hipSuccess; ++v) {
-    p->meta = cand[v];
-    e = upload_args(p, nullptr);
+    double per = 0.0;
+    e = time_schedule(cand[v], per);
     if (e != hipSuccess) break;
-    enqueue(p, out, st, false);  // warm
-    (void)hipEventRecord(e0, st);
-    for (int r = 0; r < rounds; ++r) enqueue(p, out, st, false);
-    (void)hipEventRecord(e1, st);
-    e = hipEventSynchronize(e1);
-    float t = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-    const double per = (double)t / rounds;
     if (ms) ms[v] = per;
     if (v == 0 || per < best_ms) {
       best = v;
       best_ms = per;
     }
   }
+  // 4. refine the kept candidate class by class: half and twice its tiles, each change kept only
+  //    if it is more than 1% faster in a second timing beside a fresh timing of the incumbent;
+  //    at most two passes over the classes
+  ClassMeta cur = cand[best];
+  double cur_ms = best_ms;
+  for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+    bool changed = false;
+    for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
+      if (p->class_cand[c] == 0) continue;
+      const int T = cur.tiles[c];
+      const int opt[2] = {std::max(1, T / 2), std::min(class_max_tiles(c), 2 * T)};
+      for (int o = 0; o < 2 && e == hipSuccess; ++o) {
+        if (opt[o] == T) continue;
+        ClassMeta trial = cur;
+        trial.tiles[c] = opt[o];
+        double t1 = 0.0, t0 = 0.0, t2 = 0.0;
+        e = time_schedule(trial, t1);
+        if (e != hipSuccess || !(t1 < 0.99 * cur_ms)) continue;
+        e = time_schedule(cur, t0);
+        if (e == hipSuccess) e = time_schedule(trial, t2);
+        if (e != hipSuccess) break;
+        if (t2 < 0.99 * t0) {
+          cur = trial;
+          cur_ms = t2;
+          changed = true;
+          break;
+        }
+        cur_ms = t0;
+      }
+    }
+    if (!changed) break;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  p->meta = e == hipSuccess ? cand[best] : base;
+  p->meta = e == hipSuccess ? cur : base;
   const hipError_t e2 = upload_args(p, nullptr);
   if (e != hipSuccess || e2 != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "tuning runs failed");
   if (chosen) *chosen = best;
