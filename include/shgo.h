@@ -91,13 +91,15 @@ shgo_status shgo_validate(const shgo_basis* basis, const shgo_nuclei* nuclei, do
 /* Plan for the full symmetric matrix V (nbf x nbf, row-major) over every shell pair a <= b.
  * screen > 0 drops primitive pairs with exp(-ab/(a+b) |A-B|^2) <= screen (0 keeps all; a pair
  * whose primitive pairs are all dropped gives a zero block).  Validates the inputs, copies them
- * to the device and allocates the plan's workspace. */
+ * to the device and allocates the plan's workspace. Size limits (SHGO_ERR_INVALID_ARG): at most
+ * 2^31 - 1 candidate shell pairs in all and 2^30 in one (l_a, l_b) class. */
 shgo_status shgo_plan_matrix(shgo_context* ctx, const shgo_basis* basis, const shgo_nuclei* nuclei,
                              double screen, shgo_plan** plan);
 
 /* Plan for an explicit list of shell pairs (pair_a[i], pair_b[i]), host arrays of n_pairs
  * shell indices. The output holds the blocks back to back in list order, block i being
- * (2 l_a + 1) x (2 l_b + 1) row-major (rows follow shell pair_a[i]). */
+ * (2 l_a + 1) x (2 l_b + 1) row-major (rows follow shell pair_a[i]). The same size limits as
+ * for shgo_plan_matrix apply to the list. */
 shgo_status shgo_plan_pairs(shgo_context* ctx, const shgo_basis* basis, const shgo_nuclei* nuclei,
                             int64_t n_pairs, const int32_t* pair_a, const int32_t* pair_b, double screen,
                             shgo_plan** plan);

@@ -1516,6 +1516,12 @@ shgo_status make_plan(shgo_context* ctx, const shgo_basis* b, const shgo_nuclei*
     p->out_size = o;
     p->integrals = o;
   }
+  // a work item holds its tile block in 24 bits (class << 24 | block)
+  for (int c = 0; c < kNumClasses; ++c)
+    if (((int64_t)p->class_cand[c] + kTile - 1) / kTile >= ((int64_t)1 << 24)) {
+      shgo_plan_destroy(p);
+      return fail(ctx, SHGO_ERR_INVALID_ARG, "more than 2^30 shell pairs in one (la, lb) class");
+    }
   // device copies and workspace
   hipError_t e = hipSuccess;
   double *center, *expo, *coef, *w;
