@@ -142,7 +142,8 @@ shgo_status shgo_execute_graph(shgo_plan* plan, double* out, void* stream);
  * A work item is a block of tiles[c] tiles of 64 class-sorted shell pairs, run by one workgroup:
  * its eight wavefronts take (tile, slice of at most 8 primitive-pair iterations, group) tasks and
  * add into one LDS accumulator. Items are dispatched longest first, by the estimate
- * weight[c] x (primitive-pair iterations of the item's longest tile) x (its tiles).
+ * weight[c] x (primitive-pair iterations of the item's longest tile) x (its tiles) / (the
+ * wavefronts its tasks keep busy, at most 8).
  *   weight[28] relative time of one primitive-pair iteration of a tile of the class, 1..1e6 (the
  *              default comes from an operation-count model, largest 1024)
  *   tiles[28]  tiles per work item of each class, 1 <= tiles[c] <= shgo_max_tiles(c) (the LDS of
