@@ -175,10 +175,11 @@ shgo_status shgo_plan_set_schedule(shgo_plan* plan, const float* weight, const i
 shgo_status shgo_plan_autotune(shgo_plan* plan, double* out, int32_t rounds, void* stream, double* ms,
                                int32_t* chosen);
 
-/* Phase timing. With n_slots > 0, every later shgo_execute records HIP event pairs around
+/* Phase timing. With n_slots > 0, every later shgo_execute records HIP events at the bounds of
  * its two phases -- 0: pair build (normalisation, enumeration, screening, class sort, work
- * queue), 1: the integral kernel (one persistent launch over every class) -- cycling through
- * n_slots sets of events; n_slots = 0 turns recording off. */
+ * queue), 1: the integral kernel (one persistent launch over every class); three events per
+ * execution, the end of phase 0 being the start of phase 1 -- cycling through n_slots sets of
+ * events; n_slots = 0 turns recording off. */
 #define SHGO_NUM_PHASES 2
 shgo_status shgo_plan_set_timing(shgo_plan* plan, int32_t n_slots);
 

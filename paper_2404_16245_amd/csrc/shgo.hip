@@ -368,7 +368,6 @@ __global__ void __launch_bounds__(kClassifyThreads) k_classify(DevBasis bs, DevP
   }
 }
 
-// Exclusive scan of key_count into key_off (one workgroup of 1024 threads).
 // Cost bucket of work item i (class c = the one whose items start at or below i): the class's
 // weight times the primitive-pair iterations of the item's longest tile (the surviving-pair count
 // of its last slot, keys being sorted within the class) times its tiles, over the wavefronts its
@@ -405,13 +404,40 @@ __device__ int item_bucket(int i, const int* ioff, const int* koff, const ClassM
   return min(kCostBuckets - 1, (int)(4.0f * log2f(cost)));
 }
 
+// Inclusive prefix sum of v over the 1024 threads of the workgroup: each wavefront scans its 64
+// values with shuffles, the first wavefront scans the 16 wavefront totals (wsum, LDS), two
+// barriers in all. Every thread of the workgroup must call it.
+__device__ __forceinline__ int scan_1024(int v, int* wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(v, off);
+    if (lane >= off) v += u;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    int x = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int u = __shfl_up(x, off);
+      if (lane >= off) x += u;
+    }
+    if (lane < 16) wsum[lane] = x;
+  }
+  __syncthreads();
+  return w > 0 ? v + wsum[w - 1] : v;
+}
+
 // Exclusive scan of key_count into key_off (one workgroup of 1024 threads), then the work-item
 // list of the integral kernel: every class's blocks of tiles[c] tiles, sorted by decreasing cost
 // bucket (a counting sort in LDS), so that the persistent kernel takes the longest items first.
 // Also clears key_count for the next evaluation and resets the queue head.
 __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta, int32_t* item_off, int32_t* items,
                                                     int32_t* queue) {
-  __shared__ int part[1024];
+  static_assert(kCostBuckets == 128, "the bucket scan gives each lane of one wavefront two buckets");
+  __shared__ int wsum[16];
+  __shared__ int citems[kNumClasses];
   __shared__ int koff[kNumKeys + 1];
   __shared__ int ioff[kNumClasses + 1];  // first item of each class, in class-id order
   __shared__ int bcount[kCostBuckets];
@@ -425,16 +451,9 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta,
     if (k < kNumKeys) pr.key_count[k] = 0;  // cleared for the next evaluation's k_classify
     s += loc[j];
   }
-  part[t] = s;
   if (t < kCostBuckets) bcount[t] = 0;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int run = part[t] - s;
+  const int incl = scan_1024(s, wsum);
+  int run = incl - s;
   for (int j = 0; j < per; ++j) {
     const int k = t * per + j;
     if (k < kNumKeys) {
@@ -444,18 +463,18 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta,
     run += loc[j];
   }
   if (t == 1023) {
-    pr.key_off[kNumKeys] = part[1023];
-    koff[kNumKeys] = part[1023];
+    pr.key_off[kNumKeys] = incl;
+    koff[kNumKeys] = incl;
   }
   __syncthreads();
   if (t < kNumClasses) {  // items of class t
     const int tiles = (koff[(t + 1) * kKeysPerClass] - koff[t * kKeysPerClass] + kTile - 1) / kTile;
-    part[t] = (tiles + meta.tiles[t] - 1) / meta.tiles[t];
+    citems[t] = (tiles + meta.tiles[t] - 1) / meta.tiles[t];
   }
   __syncthreads();
   if (t <= kNumClasses) {  // first item of class t (t = kNumClasses: the total)
     int off = 0;
-    for (int c = 0; c < t; ++c) off += part[c];
+    for (int c = 0; c < t; ++c) off += citems[c];
     ioff[t] = off;
     if (t == kNumClasses) {
       item_off[0] = off;
@@ -467,17 +486,21 @@ __global__ void __launch_bounds__(1024) k_scan_keys(DevPairs pr, ClassMeta meta,
   int c, blk;
   for (int i = t; i < total; i += 1024) atomicAdd(&bcount[item_bucket(i, ioff, koff, meta, c, blk)], 1);
   __syncthreads();
-  // bucket starts, most expensive bucket first: inclusive scan of the counts in descending bucket
-  // order (part[r] for rank r = kCostBuckets - 1 - bucket), then shifted to exclusive starts
-  if (t < kCostBuckets) part[t] = bcount[kCostBuckets - 1 - t];
-  __syncthreads();
-  for (int off = 1; off < kCostBuckets; off <<= 1) {
-    const int v = t < kCostBuckets && t >= off ? part[t - off] : 0;
-    __syncthreads();
-    if (t < kCostBuckets) part[t] += v;
-    __syncthreads();
+  // bucket starts, most expensive bucket first: rank r = kCostBuckets - 1 - bucket; lane t of the
+  // first wavefront holds ranks 2t and 2t + 1 and scans their sums with shuffles
+  if (t < 64) {
+    const int b0 = kCostBuckets - 1 - 2 * t, b1 = b0 - 1;
+    const int a0 = bcount[b0], a1 = bcount[b1];
+    int x = a0 + a1;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(x, off);
+      if (t >= off) x += u;
+    }
+    const int start = x - a0 - a1;
+    bcount[b0] = start;
+    bcount[b1] = start + a0;
   }
-  if (t < kCostBuckets) bcount[kCostBuckets - 1 - t] = part[t] - bcount[kCostBuckets - 1 - t];
   __syncthreads();
   for (int i = t; i < total; i += 1024) {
     const int b = item_bucket(i, ioff, koff, meta, c, blk);
@@ -1463,8 +1486,7 @@ void enqueue(shgo_plan* p, double* out, hipStream_t st, bool timed) {
   hipLaunchKernelGGL(k_classify, dim3(cb + wb), dim3(kClassifyThreads), 0, st, p->bs, p->pr, cb);
   hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->items, p->queue);
   hipLaunchKernelGGL(k_scatter, dim3(blocks(p->n_cand)), dim3(tb), 0, st, p->bs, p->pr);
-  mark(0, 1);
-  mark(1, 0);
+  mark(0, 1);  // also the start of phase 1: three event records per timed execution
   hipLaunchKernelGGL(k_integrals, dim3(p->ctx->grid), dim3(kIntegralThreads), acc_bytes(p), st,
                      (const WorkArgs*)p->d_wa, out);
   mark(1, 1);
@@ -2059,8 +2081,10 @@ shgo_status shgo_plan_phase_ms(shgo_plan* p, double* ms, int32_t* count) {
     ms[ph] = 0.0;
     for (int64_t sl = 0; sl < n; ++sl) {
       float t = 0.f;
-      const size_t e0 = ((size_t)sl * SHGO_NUM_PHASES + ph) * 2;
-      if (hipEventElapsedTime(&t, p->events[e0], p->events[e0 + 1]) != hipSuccess)
+      // a phase starts where the previous one ended (phase 0 at its own start event)
+      const size_t e1 = ((size_t)sl * SHGO_NUM_PHASES + ph) * 2 + 1;
+      const size_t e0 = ph == 0 ? e1 - 1 : e1 - 2;
+      if (hipEventElapsedTime(&t, p->events[e0], p->events[e1]) != hipSuccess)
         return fail(p->ctx, SHGO_ERR_DEVICE, "hipEventElapsedTime failed (stream not synchronised?)");
       ms[ph] += t;
     }
