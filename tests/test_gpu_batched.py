@@ -106,6 +106,10 @@ def test_autotune_keeps_results(shgo, molecule):
     ms, chosen = shgo.shgo_plan_autotune(plan, out, rounds=2)
     assert 0 <= chosen < shgo.SHGO_TUNE_CANDIDATES and np.all(ms > 0)
     assert ms[chosen] == ms.min()
+    # the installed schedule (the kept candidate after the per-class refinement) is a valid one
+    w, t = shgo.shgo_plan_get_schedule(plan)
+    tmax = np.array([shgo.shgo_max_tiles(c) for c in range(28)])
+    assert np.all((t >= 1) & (t <= tmax)) and np.all((w >= 1.0) & (w <= 1e6))
     out.fill_(float("nan"))
     shgo.shgo_execute_graph(plan, out)
     torch.cuda.synchronize()
