@@ -1065,7 +1065,9 @@ k_grad(GradArgs ga) {
   const int64_t nbf = ga.bs.nbf;
   double e_lane = 0.0;
   for (int j = blockIdx.x * (kGradThreads / 64) + wave; j < count; j += nwaves) {
-    const int slot = start + j;
+    // the class's pairs are sorted by surviving primitive pairs, ascending: take them from the
+    // long end so that the last round of the grid-stride loop holds the shortest pairs
+    const int slot = start + (count - 1 - j);
     const int s1 = ga.pr.s1[slot], s2 = ga.pr.s2[slot];
     PairState ps;
     ps.active = true;
