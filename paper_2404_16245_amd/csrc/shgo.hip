@@ -1320,6 +1320,7 @@ struct shgo_plan {
   double screen = 0.0;
   int class_cand[kNumClasses] = {0};  // candidate pairs per class (bounds the sorted counts)
   int32_t def_tiles[kNumClasses] = {0};  // default tiles per work item of each class
+  int32_t grad_occ[kNumClasses] = {0};    // resident workgroups per CU of each class's gradient kernel
   std::vector<void*> allocs;
   DevBasis bs{};
   DevPairs pr{};
@@ -1667,12 +1668,20 @@ shgo_status grad_class(shgo_plan* p, const GradArgs& ga, hipStream_t st, bool la
     if (lds > 65536 && hipFuncSetAttribute((const void*)k_grad<LA, LB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds) != hipSuccess)
       return fail(p->ctx, SHGO_ERR_DEVICE, "hipFuncSetAttribute failed for the gradient kernel");
+    if (p->grad_occ[c] == 0) {  // workgroups that fit on a CU at once (registers, LDS), at least 1
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_grad<LA, LB>, kGradThreads, lds) !=
+          hipSuccess)
+        nb = 2;
+      p->grad_occ[c] = std::max(1, std::min(nb, 8));
+    }
     return SHGO_OK;
   }
   const int64_t waves_needed = p->class_cand[c];
   const int per_block = kGradThreads / 64;
+  // one round of resident workgroups; the kernel strides over the class's pairs
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + per_block - 1) / per_block,
-                                                                 2 * (int64_t)p->ctx->n_cu));
+                                                                 (int64_t)p->grad_occ[c] * p->ctx->n_cu));
   hipLaunchKernelGGL((k_grad<LA, LB>), dim3(blocks), dim3(kGradThreads), lds, st, ga);
   return SHGO_OK;
 }
