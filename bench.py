@@ -241,8 +241,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        log("bench.py: multi-GPU runs are not part of this build (one GPU per process, --gpus 1)")
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1"}))
+        log("bench.py: the path runs on one GPU per process; multi-GPU runs are not implemented (--gpus 1)")
         sys.exit(2)
 
     import torch

@@ -1,0 +1,67 @@
+"""bench.py's host logic on the CPU: the one-GPU guard, the algorithmic flop model that the
+roofline divides by, and the traffic figure's tie to the kernel sources."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+from paper_2404_16245_amd import synth  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_model_flops_per_nucleus_step():
+    nnz = bench._gaunt_nnz()
+    # the per-(primitive pair, nucleus) model: 52 flops for (0,0), 1818 for (6,6)
+    assert bench.model_flops(0, 0, nnz)[0] == 52
+    assert bench.model_flops(6, 6, nnz)[0] == 1818
+    # more work for every larger class
+    steps = [bench.model_flops(la, lb, nnz)[0] for la in range(7) for lb in range(la + 1)]
+    assert all(x > 0 for x in steps)
+    assert bench.model_flops(6, 5, nnz)[0] < bench.model_flops(6, 6, nnz)[0]
+
+
+def test_sweep_model_flops_per_launch():
+    # the roofline's algorithmic flops for the high-l sweep (49 classes x 2041 pairs, 64 nuclei)
+    basis, nuclei, pa, pb = synth.high_l_sweep(seed=2)
+    _, total = bench.workload_flops(basis, nuclei, pa, pb, 0.0)
+    assert total == 4600891594
+
+
+def test_surviving_prim_pairs_screening():
+    b, _ = synth.long_contractions(seed=71)
+    pa, pb = synth.all_pairs(b.n_shells)
+    full = bench.surviving_prim_pairs(b, pa, pb, 0.0)
+    assert np.array_equal(full, b.nprim[pa].astype(np.int64) * b.nprim[pb])
+    kept = bench.surviving_prim_pairs(b, pa, pb, 1e-6)
+    assert np.all(kept <= full) and kept.sum() < full.sum()
+    # a shell with itself (R = 0) keeps every primitive pair
+    same = pa == pb
+    assert np.array_equal(kept[same], full[same])
+
+
+def test_traffic_figure_follows_the_kernel_sources(tmp_path, monkeypatch):
+    tag = "k_integrals_high_l_sweep"
+    v = bench.traffic_from_profile(tag)
+    assert v is None or v > 0
+    current = bench.kernel_source_hash()
+    # a summary is read only while its source hash is the current one
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: current)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (prof / f"traffic_{tag}.txt").write_text("source_hash: 0000000000000000\nhbm_bytes_per_launch: 123\n")
+    assert bench.traffic_from_profile(tag) is None
+    (prof / f"traffic_{tag}.txt").write_text(f"# a comment: 1\nsource_hash: {current}\nhbm_bytes_per_launch: 123\n")
+    assert bench.traffic_from_profile(tag) == 123.0
