@@ -80,6 +80,23 @@ def test_contracted_screened_matrix(shgo):
                            shgo.nuclear_attraction(b, n).cpu().numpy(), rtol=0, atol=1e-12)
 
 
+def test_screened_pair_list_in_any_order(shgo):
+    # a pair-list plan with screening: contracted shells, the list shuffled, some pairs given as
+    # (b, a), some repeated; each block comes back in list order and orientation
+    b, n = synth.molecule(seed=17, n_atoms=5, box=8.0, ls=(0, 1, 2, 3), kmax=5)
+    pa, pb = synth.all_pairs(b.n_shells)
+    rng = np.random.default_rng(17)
+    order = rng.permutation(len(pa))
+    pa, pb = pa[order].copy(), pb[order].copy()
+    flip = rng.random(len(pa)) < 0.5
+    pa[flip], pb[flip] = pb[flip].copy(), pa[flip].copy()
+    rep = rng.choice(len(pa), 25, replace=False)
+    pa, pb = np.concatenate([pa, pa[rep]]), np.concatenate([pb, pb[rep]])
+    for screen in (1e-10, 1e-4):
+        got = shgo.nuclear_attraction_pairs(b, n, pa, pb, screen=screen).cpu().numpy()
+        assert_parity(got, oracle.nuc_blocks(b, n, pa, pb, screen=screen), what=f"screened pair list, {screen}")
+
+
 def test_edge_cases(shgo):
     b, n = synth.small_molecule(seed=1)
     # no nuclei: V = 0 exactly
