@@ -1059,7 +1059,9 @@ k_grad(GradArgs ga) {
   for (int i = threadIdx.x; i < 3 * n_nuc; i += blockDim.x) ngrad[i] = 0.0;
   __syncthreads();
   constexpr int cls = class_id(LA, LB);
-  const int start = ga.pr.key_off[cls * kKeysPerClass];
+  // pairs whose primitive pairs are all screened out (key 0 of the class, sorted first) add
+  // nothing to E or its gradient: the loop starts after them
+  const int start = ga.pr.key_off[cls * kKeysPerClass + 1];
   const int count = ga.pr.key_off[(cls + 1) * kKeysPerClass] - start;
   const int nwaves = gridDim.x * (kGradThreads / 64);
   const int64_t nbf = ga.bs.nbf;
