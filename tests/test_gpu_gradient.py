@@ -64,6 +64,23 @@ def test_screened_contracted_molecule(shgo):
     assert_grad(gpu_grad(shgo, b, n, D, screen), oracle.grad(b, n, D, screen), "screened")
 
 
+def test_sparse_molecule_with_fully_screened_pairs(shgo):
+    # a sparse molecule where many shell pairs keep no primitive pair: those pairs add nothing
+    b, n = synth.molecule(seed=54, n_atoms=10, box=14.0, ls=(0, 1, 2, 3), kmax=5)
+    D = synth.density(b.nbf(), seed=11)
+    pa, pb = synth.all_pairs(b.n_shells)
+    R2 = np.sum((b.center[pa] - b.center[pb]) ** 2, axis=1)
+    for screen in (1e-12, 1e-8):
+        empty = 0
+        for i in range(len(pa)):
+            ea = b.expo[b.prim_off[pa[i]]:b.prim_off[pa[i]] + b.nprim[pa[i]]]
+            eb = b.expo[b.prim_off[pb[i]]:b.prim_off[pb[i]] + b.nprim[pb[i]]]
+            mu = ea[:, None] * eb[None, :] / (ea[:, None] + eb[None, :])
+            empty += not np.any(np.exp(-mu * R2[i]) > screen)
+        assert empty > len(pa) // 5
+        assert_grad(gpu_grad(shgo, b, n, D, screen), oracle.grad(b, n, D, screen), f"sparse, screen {screen}")
+
+
 def test_many_nuclei_span_several_lane_rounds(shgo):
     # 150 nuclei: three rounds of the 64-lane nucleus loop, the last one ragged
     b, _ = synth.molecule(seed=54, n_atoms=2, box=3.0, ls=(1, 2), kmax=2)
