@@ -136,6 +136,45 @@ def test_translation_sum_rule(shgo):
     assert np.abs(total).max() <= 1e-10 * np.abs(np.concatenate([dn, dc])).max()
 
 
+def test_full_size_gradient_properties(shgo):
+    """The 500-atom gradient workload at full size (nbf 8000, screened 1e-12), where the oracle is
+    too slow: E against sum D V of the GPU forward, the translation sum rule, and central
+    differences of the GPU's own energies for sampled nuclear and shell-center coordinates."""
+    import torch
+    b, n = synth.gradient_molecule(seed=5)
+    D = synth.density(b.nbf(), seed=5)
+    screen = 1e-12
+    dn, dc, E = gpu_grad(shgo, b, n, D, screen)
+    total = dn.sum(axis=0) + dc.sum(axis=0)
+    assert np.abs(total).max() <= 1e-10 * np.abs(np.concatenate([dn, dc])).max()
+    Dt = torch.as_tensor(D, device="cuda")
+
+    def energy(bb, nn):
+        V = shgo.nuclear_attraction(bb, nn, screen=screen)
+        e = float((V.view(-1) * Dt.view(-1)).sum().item())
+        del V
+        return e
+
+    assert energy(b, n) == pytest.approx(E, rel=1e-12)
+    h = 1e-4
+    rng = np.random.default_rng(12)
+    for _ in range(2):
+        c, x = int(rng.integers(n.n)), int(rng.integers(3))
+        pp, pm = n.pos.copy(), n.pos.copy()
+        pp[c, x] += h
+        pm[c, x] -= h
+        fd = (energy(b, synth.Nuclei(pp, n.Z)) - energy(b, synth.Nuclei(pm, n.Z))) / (2 * h)
+        assert fd == pytest.approx(dn[c, x], rel=1e-6, abs=1e-7)
+        s = int(rng.integers(b.n_shells))
+        cp, cm = b.center.copy(), b.center.copy()
+        cp[s, x] += h
+        cm[s, x] -= h
+        bp = synth.Basis(cp, b.l, b.nprim, b.prim_off, b.expo, b.coef)
+        bm = synth.Basis(cm, b.l, b.nprim, b.prim_off, b.expo, b.coef)
+        fd = (energy(bp, n) - energy(bm, n)) / (2 * h)
+        assert fd == pytest.approx(dc[s, x], rel=1e-6, abs=1e-7)
+
+
 def test_autograd_function(shgo):
     import torch
     b, n = synth.small_molecule(seed=2)
