@@ -166,8 +166,9 @@ shgo_status shgo_plan_set_schedule(shgo_plan* plan, const float* weight, const i
  * LDS allows; 3: the measured weights with one tile per item; 4: the measured weights with half the
  * default tiles (at least one) -- times `rounds` executions of each on `stream` (the call
  * synchronizes the stream), and keeps the fastest. It then refines that schedule class by class
- * (half and twice a class's tiles; a change is kept when it is more than 1% faster, confirmed by a
- * second timing beside the incumbent's; at most two passes) and installs the result.
+ * (one tile more or less, twice or half a class's tiles; a change is kept when it is more than
+ * 0.5% faster, confirmed by a second timing beside the incumbent's; at most three passes) and installs
+ * the result.
  * ms[SHGO_TUNE_CANDIDATES] (or NULL) receives each candidate's milliseconds per execution, *chosen
  * (or NULL) the index of the candidate the refinement started from. `out` is written as by
  * shgo_execute. */

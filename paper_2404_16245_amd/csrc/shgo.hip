@@ -1959,28 +1959,28 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
       best_ms = per;
     }
   }
-  // 4. refine the kept candidate class by class: half and twice its tiles, each change kept only
-  //    if it is more than 1% faster in a second timing beside a fresh timing of the incumbent;
-  //    at most two passes over the classes
+  // 4. refine the kept candidate class by class: one tile more or less, twice or half the tiles,
+  //    each change kept only if it is more than 0.5% faster in a second timing beside a fresh
+  //    timing of the incumbent; at most three passes over the classes
   ClassMeta cur = cand[best];
   double cur_ms = best_ms;
-  for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+  for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
     bool changed = false;
     for (int c = 0; c < kNumClasses && e == hipSuccess; ++c) {
       if (p->class_cand[c] == 0) continue;
-      const int T = cur.tiles[c];
-      const int opt[2] = {std::max(1, T / 2), std::min(class_max_tiles(c), 2 * T)};
-      for (int o = 0; o < 2 && e == hipSuccess; ++o) {
-        if (opt[o] == T) continue;
+      const int T = cur.tiles[c], mx = class_max_tiles(c);
+      const int opt[4] = {std::min(mx, T + 1), std::max(1, T - 1), std::min(mx, 2 * T), std::max(1, T / 2)};
+      for (int o = 0; o < 4 && e == hipSuccess; ++o) {
+        if (opt[o] == T || (o >= 2 && opt[o] == opt[o - 2])) continue;
         ClassMeta trial = cur;
         trial.tiles[c] = opt[o];
         double t1 = 0.0, t0 = 0.0, t2 = 0.0;
         e = time_schedule(trial, t1);
-        if (e != hipSuccess || !(t1 < 0.99 * cur_ms)) continue;
+        if (e != hipSuccess || !(t1 < 0.995 * cur_ms)) continue;
         e = time_schedule(cur, t0);
         if (e == hipSuccess) e = time_schedule(trial, t2);
         if (e != hipSuccess) break;
-        if (t2 < 0.99 * t0) {
+        if (t2 < 0.995 * t0) {
           cur = trial;
           cur_ms = t2;
           changed = true;
