@@ -190,7 +190,7 @@ def measure_batched(shgo, synth, torch, steps):
     plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, screen)
     out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
     ms_eager = _time_ms(torch, lambda: shgo.shgo_execute(plan, out), steps, 2)
-    tune_ms, chosen = shgo.shgo_plan_autotune(plan, out, rounds=3)
+    tune_ms, chosen = shgo.shgo_plan_autotune(plan, out, rounds=5)
     ms = _time_ms(torch, lambda: shgo.shgo_execute_graph(plan, out), steps, 2)
     pa, pb = synth.all_pairs(basis.n_shells)
     _, flops = workload_flops(basis, nuclei, pa, pb, screen)
