@@ -92,3 +92,15 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(shgo.ShgoError) as e:
         shgo.shgo_create(0)
     assert e.value.status == shgo.SHGO_ERR_DEVICE
+
+
+def test_binding_constants_match_the_header():
+    # every #define and status code of include/shgo.h that the binding mirrors has the same value
+    import re
+    import paper_2404_16245_amd as shgo
+    text = open(os.path.join(ROOT, "include", "shgo.h")).read()
+    defines = dict(re.findall(r"^#define (SHGO_[A-Z_]+) (\d+)", text, re.M))
+    for name in ("SHGO_LMAX", "SHGO_NUM_CLASSES", "SHGO_TUNE_CANDIDATES", "SHGO_NUM_PHASES"):
+        assert getattr(shgo, name) == int(defines[name]), name
+    codes = dict(re.findall(r"(SHGO_(?:OK|ERR_[A-Z_]+))\s*=\s*(\d+)", text))
+    assert codes and all(getattr(shgo, k) == int(v) for k, v in codes.items())
