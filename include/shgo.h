@@ -117,6 +117,14 @@ int64_t shgo_plan_integrals(const shgo_plan* plan);
  * (shgo_plan_output_size doubles; every element is written). Allocates nothing. */
 shgo_status shgo_execute(shgo_plan* plan, double* out, void* stream);
 
+/* The overlap matrix S of the plan's shells (Eqs. 4-10: the Gaussian product, the shift of both
+ * harmonics to P, and the single-center overlap, which the orthogonality of the harmonics
+ * reduces to one term per (lambda, m)), over every primitive pair (the plan's screening threshold
+ * does not apply), written into the device buffer `out` in the layout shgo_execute gives V:
+ * nbf x nbf row-major for a matrix plan, the listed blocks for a pair plan. The nuclei play no
+ * part. Runs on `stream`, allocates nothing; SHGO_ERR_INVALID_ARG for a null plan or output. */
+shgo_status shgo_execute_overlap(shgo_plan* plan, double* out, void* stream);
+
 /* Gradient of E = sum_ij D_ij V_ij (the nuclear-attraction matrix of Eq. 11, differentiated
  * through Eq. 5, the shift of Eqs. 7-8, the product rule and the Boys function; an adjoint
  * kernel, not finite differences) with respect to the nuclear positions and the shell centers.

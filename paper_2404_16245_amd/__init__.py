@@ -29,6 +29,7 @@ SHGO_LMAX = 6
 EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
             "shgo_plan_integrals", "shgo_execute", "shgo_execute_graph", "shgo_execute_grad", "shgo_boys",
+            "shgo_execute_overlap",
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
             "shgo_plan_autotune", "shgo_max_tiles"]
 SHGO_NUM_CLASSES = 28
@@ -92,6 +93,8 @@ def load_library(path=LIB_PATH):
     lib.shgo_execute.restype = ctypes.c_int
     lib.shgo_execute_graph.argtypes = [vp, vp, vp]
     lib.shgo_execute_graph.restype = ctypes.c_int
+    lib.shgo_execute_overlap.argtypes = [vp, vp, vp]
+    lib.shgo_execute_overlap.restype = ctypes.c_int
     lib.shgo_plan_get_schedule.argtypes = [vp, vp, vp]
     lib.shgo_plan_get_schedule.restype = ctypes.c_int
     lib.shgo_plan_set_schedule.argtypes = [vp, vp, vp]
@@ -257,6 +260,14 @@ def shgo_execute_graph(plan, out, stream=None):
     return out
 
 
+def shgo_execute_overlap(plan, out, stream=None):
+    """Enqueue the overlap matrix S of the plan's shells into ``out`` (the layout V has)."""
+    lib = load_library()
+    _check(lib, plan.ctx, lib.shgo_execute_overlap(plan.handle, _f64_device(out, "out", plan.output_size),
+                                                   _stream_handle(stream)))
+    return out
+
+
 def shgo_max_tiles(class_id):
     """Largest tiles-per-item the LDS accumulator allows for a class (-1 if invalid)."""
     return int(load_library().shgo_max_tiles(int(class_id)))
@@ -388,6 +399,35 @@ def nuclear_attraction_grad(basis, nuclei, D, screen=0.0, device=0):
     shgo_execute_grad(plan, Dt, dn, dc, e)
     torch.cuda.current_stream().synchronize()
     return dn, dc, e
+
+
+def _no_nuclei():
+    class _N:
+        pos = np.zeros((0, 3))
+        Z = np.zeros(0)
+        n = 0
+    return _N()
+
+
+def overlap(basis, device=0):
+    """Full nbf x nbf overlap matrix S of the basis as a float64 CUDA tensor."""
+    import torch
+    plan = shgo_plan_matrix(context(device), basis, _no_nuclei(), 0.0)
+    nbf = shgo_nbf(basis)
+    out = torch.empty((nbf, nbf), dtype=torch.float64, device=f"cuda:{device}")
+    shgo_execute_overlap(plan, out)
+    torch.cuda.current_stream().synchronize()
+    return out
+
+
+def overlap_pairs(basis, pair_a, pair_b, device=0):
+    """Overlap blocks of the listed shell pairs, back to back, as a flat float64 CUDA tensor."""
+    import torch
+    plan = shgo_plan_pairs(context(device), basis, _no_nuclei(), pair_a, pair_b, 0.0)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device=f"cuda:{device}")
+    shgo_execute_overlap(plan, out)
+    torch.cuda.current_stream().synchronize()
+    return out
 
 
 def _autograd_function():

@@ -980,6 +980,156 @@ k_integrals(const WorkArgs* __restrict__ wa_ptr, double* __restrict__ out) {
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Overlap matrix S (Eqs. 4-10): the shell pairs, pair frame, rotation back and output layout of V
+// ---------------------------------------------------------------------------------------------
+// In the pair frame (z along A -> B) the shifts of both harmonics to P run along z and keep m
+// (Eqs. 7-8), and the one-center overlap of S^lam_m(u) with S^lam'_m'(u) under e^{-p u^2} vanishes
+// unless lam = lam' and m = m' (Eq. 9: orthogonality of the harmonics; the coupling of Eq. 10 keeps
+// only L = 0). With the scaled regular solid harmonics R_l^m = Y_l^m / sqrt((l+m)!(l-m)!), whose
+// z-shift is R_l^m(u + t z) = sum_lam R_lam^m(u) t^(l-lam) / (l-lam)!, the frame block is diagonal:
+//   S'(m, m) = sum over primitive pairs of w_a w_b e^{-mu R^2} sum_{lam=|m|}^{lb} A(la,lam,m) A(lb,lam,m)
+//              t_a^(la-lam) t_b^(lb-lam) (4 pi / (2 lam + 1)) Gamma(lam + 3/2) / (2 p^(lam + 3/2)),
+//   A(l, lam, m) = sqrt((l+m)! (l-m)! / ((lam+m)! (lam-m)!)) / (l-lam)!,  t_a = beta R / p,  t_b = -alpha R / p.
+// Every primitive pair counts (no screening). One lane per class-sorted shell pair.
+__host__ __device__ constexpr double fact_d(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= (double)i;
+  return f;
+}
+
+template <int LA, int LB>
+__device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs& pr, int slot, double* __restrict__ out) {
+  constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1;
+  PairState ps;
+  const int s1 = pr.s1[slot], s2 = pr.s2[slot];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    ps.A[x] = bs.center[3 * s1 + x];
+    ps.B[x] = bs.center[3 * s2 + x];
+  }
+  frame_of(ps);
+  const double R = ps.R;
+  // A(la, lam, m) A(lb, lam, m) (4 pi / (2 lam + 1)) Gamma(lam + 3/2) / 2, for m <= lam <= lb
+  double cf[LB + 1][LB + 1];
+#pragma unroll
+  for (int m = 0; m <= LB; ++m)
+#pragma unroll
+    for (int lam = 0; lam <= LB; ++lam) {
+      if (lam < m) {
+        cf[m][lam] = 0.0;
+        continue;
+      }
+      const double den = fact_d(lam + m) * fact_d(lam - m);
+      const double aa = sqrt(fact_d(LA + m) * fact_d(LA - m) / den) / fact_d(LA - lam);
+      const double ab = sqrt(fact_d(LB + m) * fact_d(LB - m) / den) / fact_d(LB - lam);
+      double dfac = 1.0;  // (2 lam + 1)!!
+      for (int i = 2 * lam + 1; i > 1; i -= 2) dfac *= (double)i;
+      const double gam = dfac * 1.7724538509055160273 / ldexp(1.0, lam + 1);  // Gamma(lam + 3/2)
+      cf[m][lam] = aa * ab * (12.566370614359172954 / (2 * lam + 1)) * 0.5 * gam;
+    }
+  double sm[LB + 1];
+#pragma unroll
+  for (int m = 0; m <= LB; ++m) sm[m] = 0.0;
+  const int64_t o1 = bs.prim_off[s1], o2 = bs.prim_off[s2];
+  const int K1 = bs.nprim[s1], K2 = bs.nprim[s2];
+  for (int i = 0; i < K1; ++i)
+    for (int j = 0; j < K2; ++j) {
+      const double a = bs.expo[o1 + i], b = bs.expo[o2 + j];
+      const double p = a + b, ip = 1.0 / p, mu = a * b * ip;
+      const double pre = bs.w[o1 + i] * bs.w[o2 + j] * exp_neg(mu * R * R) * ip * sqrt(ip);
+      const double ta = b * R * ip, tb = -a * R * ip;
+      double pa[LA + 1], pb[LB + 1], pl[LB + 1];
+      pa[0] = 1.0;
+      pb[0] = 1.0;
+      pl[0] = 1.0;
+#pragma unroll
+      for (int k = 1; k <= LA; ++k) pa[k] = pa[k - 1] * ta;
+#pragma unroll
+      for (int k = 1; k <= LB; ++k) {
+        pb[k] = pb[k - 1] * tb;
+        pl[k] = pl[k - 1] * ip;
+      }
+#pragma unroll
+      for (int m = 0; m <= LB; ++m) {
+        double t = 0.0;
+#pragma unroll
+        for (int lam = m; lam <= LB; ++lam) t = fma(cf[m][lam] * pa[LA - lam], pb[LB - lam] * pl[lam], t);
+        sm[m] = fma(pre, t, sm[m]);
+      }
+    }
+  // the frame block (entry (ma + la, mb + lb)), then back to the laboratory frame as for V
+  double V[NA * NB];
+#pragma unroll
+  for (int e = 0; e < NA * NB; ++e) V[e] = 0.0;
+#pragma unroll
+  for (int m = -LB; m <= LB; ++m) V[(m + LA) * NB + (m + LB)] = sm[m < 0 ? -m : m];
+  double cth[LA + 1], sth[LA + 1], cph[LA + 1], sph[LA + 1];
+  angles<LA>(ps.ct, ps.st, cth, sth);
+  angles<LA>(ps.cp, ps.sp, cph, sph);
+#pragma unroll
+  for (int r = 0; r < NA; ++r) {
+    double v[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) v[j] = V[r * NB + j];
+    Rot<LB>::apply(v, cth, sth, cph, sph);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) V[r * NB + j] = v[j];
+  }
+#pragma unroll
+  for (int col = 0; col < NB; ++col) {
+    double v[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) v[i] = V[i * NB + col];
+    Rot<LA>::apply(v, cth, sth, cph, sph);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) V[i * NB + col] = v[i];
+  }
+  const int64_t d0 = pr.dst0[slot], d1 = pr.dst1[slot];
+  if (pr.full) {
+    // the (s1, s2) block and its mirror; a shell with itself writes each entry once per orientation
+    const int64_t n = bs.nbf;
+    for (int i = 0; i < NA; ++i)
+      for (int col = 0; col < NB; ++col)
+        if (d0 != d1 || i <= col) {
+          out[(d0 + i) * n + d1 + col] = V[i * NB + col];
+          out[(d1 + col) * n + d0 + i] = V[i * NB + col];
+        }
+  } else {
+    // the listed orientation: (s1, s2) row-major, or transposed where the listed pair is (s2, s1)
+    for (int i = 0; i < NA; ++i)
+      for (int col = 0; col < NB; ++col) {
+        if (d1 == 0)
+          out[d0 + i * NB + col] = V[i * NB + col];
+        else
+          out[d0 + col * NA + i] = V[i * NB + col];
+      }
+  }
+}
+
+template <int LA, int LB>
+__device__ __forceinline__ void overlap_dispatch(int c, const DevBasis& bs, const DevPairs& pr, int slot,
+                                                 double* __restrict__ out) {
+  if constexpr (LA <= SHGO_LMAX) {
+    if (c == class_id(LA, LB)) {
+      overlap_pair<LA, LB>(bs, pr, slot, out);
+      return;
+    }
+    if constexpr (LB < LA)
+      overlap_dispatch<LA, LB + 1>(c, bs, pr, slot, out);
+    else
+      overlap_dispatch<LA + 1, 0>(c, bs, pr, slot, out);
+  }
+}
+
+// One thread per class-sorted shell pair of the plan (slots from k_scatter; s1 has the higher l).
+__global__ void __launch_bounds__(256) k_overlap(DevBasis bs, DevPairs pr, double* __restrict__ out) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= pr.n_cand) return;
+  const int c = class_id(bs.l[pr.s1[slot]], bs.l[pr.s2[slot]]);
+  overlap_dispatch<0, 0>(c, bs, pr, (int)slot, out);
+}
+
 __global__ void k_fill_f64(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -1843,6 +1993,27 @@ shgo_status shgo_execute_graph(shgo_plan* p, double* out, void* stream) {
   }
   if (hipGraphLaunch(p->gexec, (hipStream_t)stream) != hipSuccess)
     return fail(ctx, SHGO_ERR_DEVICE, "hipGraphLaunch failed");
+  return SHGO_OK;
+}
+
+shgo_status shgo_execute_overlap(shgo_plan* p, double* out, void* stream) {
+  if (!p) return SHGO_ERR_INVALID_ARG;
+  shgo_context* ctx = p->ctx;
+  if (!out && p->out_size > 0) return fail(ctx, SHGO_ERR_INVALID_ARG, "null output");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+  if (p->n_cand == 0) return SHGO_OK;
+  hipStream_t st = (hipStream_t)stream;
+  // the plan's pair build (primitive weights, class-sorted pairs, output destinations), as for V
+  const int tb = 256;
+  const int cb = (int)((p->n_cand + kClassifyThreads - 1) / kClassifyThreads);
+  const int wb = (int)((p->n_shells + kClassifyThreads - 1) / kClassifyThreads);
+  hipLaunchKernelGGL(k_classify, dim3(cb + wb), dim3(kClassifyThreads), 0, st, p->bs, p->pr, cb);
+  hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->items, p->queue);
+  const int nb = (int)((p->n_cand + tb - 1) / tb);
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(tb), 0, st, p->bs, p->pr);
+  hipLaunchKernelGGL(k_overlap, dim3(nb), dim3(tb), 0, st, p->bs, p->pr, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return SHGO_OK;
 }
 

@@ -1,0 +1,81 @@
+"""The overlap matrix S through the C ABI (shgo_execute_overlap) against the oracle's overlap
+blocks, element by element, and the invariants a normalized basis fixes (unit diagonal blocks of a
+shell with itself, exact symmetry)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_16245_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-11, 1e-13
+
+
+@pytest.fixture(scope="module")
+def shgo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_16245_amd as m
+    m.load_library()
+    return m
+
+
+def assert_parity(got, ref, what):
+    got, ref = np.asarray(got), np.asarray(ref)
+    assert got.shape == ref.shape
+    err = np.abs(got - ref)
+    bad = err > ATOL + RTOL * np.abs(ref)
+    assert not bad.any(), f"{what}: {int(bad.sum())} of {bad.size} off, max abs err {err.max():.3e}"
+
+
+def matrix_from_blocks(b, pa, pb, flat):
+    nbf = b.nbf()
+    off = b.shell_offsets()
+    S = np.full((nbf, nbf), np.nan)
+    blocks = oracle.split_blocks(flat, b, pa, pb)
+    for k, (a, c) in enumerate(zip(pa, pb)):
+        na, nc = 2 * b.l[a] + 1, 2 * b.l[c] + 1
+        S[off[a]:off[a] + na, off[c]:off[c] + nc] = blocks[k]
+        S[off[c]:off[c] + nc, off[a]:off[a] + na] = blocks[k].T
+    return S
+
+
+def test_every_class_and_orientation(shgo):
+    # 49 (la, lb) classes x 3 uncontracted pairs; (la < lb) pairs come back in the listed orientation
+    b, _, pa, pb = synth.high_l_sweep(seed=7, pairs_per_class=3)
+    got = shgo.overlap_pairs(b, pa, pb).cpu().numpy()
+    assert_parity(got, oracle.overlap_blocks(b, pa, pb), "49 classes x 3 pairs")
+
+
+def test_contracted_molecule_matrix(shgo):
+    b, _ = synth.molecule(seed=11, n_atoms=8, box=6.0, ls=(0, 1, 2, 3, 4), kmax=6)
+    S = shgo.overlap(b).cpu().numpy()
+    pa, pb = synth.all_pairs(b.n_shells)
+    assert_parity(S, matrix_from_blocks(b, pa, pb, oracle.overlap_blocks(b, pa, pb)), "contracted S")
+    assert np.array_equal(S, S.T)
+    # normalized contracted shells: a shell's block with itself is the identity
+    off = b.shell_offsets()
+    for s in range(b.n_shells):
+        n = 2 * b.l[s] + 1
+        assert np.allclose(S[off[s]:off[s] + n, off[s]:off[s] + n], np.eye(n), rtol=0, atol=1e-12)
+
+
+def test_long_contractions_and_shared_centers(shgo):
+    # up to 400 primitive pairs per shell pair; shells of one atom share a center (R = 0)
+    b, _ = synth.long_contractions(seed=71)
+    pa, pb = synth.all_pairs(b.n_shells)
+    assert_parity(shgo.overlap(b).cpu().numpy(), matrix_from_blocks(b, pa, pb, oracle.overlap_blocks(b, pa, pb)),
+                  "long contractions")
+
+
+def test_pair_list_in_any_order(shgo):
+    b, _ = synth.molecule(seed=19, n_atoms=4, box=5.0, ls=(0, 1, 2, 3, 5, 6), kmax=3)
+    pa, pb = synth.all_pairs(b.n_shells)
+    rng = np.random.default_rng(19)
+    order = rng.permutation(len(pa))
+    pa, pb = pa[order].copy(), pb[order].copy()
+    flip = rng.random(len(pa)) < 0.5
+    pa[flip], pb[flip] = pb[flip].copy(), pa[flip].copy()
+    assert_parity(shgo.overlap_pairs(b, pa, pb).cpu().numpy(), oracle.overlap_blocks(b, pa, pb), "pair list")
