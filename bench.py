@@ -203,6 +203,21 @@ def measure_batched(shgo, synth, torch, steps):
             "fp64_vector_peak_frac": flops / (ms * 1e-3) / FP64_VECTOR_PEAK}
 
 
+def measure_overlap(shgo, synth, torch, steps):
+    """Overlap matrix S of the batched molecule's basis (nbf 5000, K 1..8), full matrix: the plan's
+    pair build and the overlap kernel per step. Bound by writing S (8 nbf^2 bytes)."""
+    basis, nuclei = synth.batched_molecule(seed=3)
+    ctx = shgo.context(0)
+    plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, 0.0)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
+    ms = _time_ms(torch, lambda: shgo.shgo_execute_overlap(plan, out), steps, 2)
+    nbytes = 8.0 * plan.output_size
+    return {"workload": "overlap S of the 200-atom batched molecule's basis (l=0..4, K 1..8), full matrix, seed 3",
+            "nbf": basis.nbf(), "integrals_per_step": plan.integrals, "ms_per_step": ms,
+            "integrals_per_s": plan.integrals / (ms * 1e-3), "output_bytes": nbytes,
+            "output_GB_per_s": nbytes / (ms * 1e-3) / 1e9, "hbm_peak_frac": nbytes / (ms * 1e-3) / 8e12}
+
+
 def measure_gradient(shgo, synth, torch, steps):
     """500-atom molecule (l <= 3, K 1..6, screened 1e-12): dE/dR_nuclei and dE/dR_centers of
     E = sum D V with a random symmetric D, by the adjoint kernel; the forward V beside it."""
@@ -336,6 +351,8 @@ def main():
         res["batched"] = measure_batched(shgo, synth, torch, max(3, args.steps // 2))
         log("bench: gradient form")
         res["gradient"] = measure_gradient(shgo, synth, torch, 3)
+        log("bench: overlap form")
+        res["overlap"] = measure_overlap(shgo, synth, torch, 5)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(basis, nuclei, pa, pb, args.cpu_seconds)
