@@ -1123,7 +1123,8 @@ __device__ __forceinline__ void overlap_dispatch(int c, const DevBasis& bs, cons
 }
 
 // One thread per class-sorted shell pair of the plan (slots from k_scatter; s1 has the higher l).
-__global__ void __launch_bounds__(256) k_overlap(DevBasis bs, DevPairs pr, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_overlap(DevBasis bs, DevPairs pr, double* __restrict__ out) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= pr.n_cand) return;
   const int c = class_id(bs.l[pr.s1[slot]], bs.l[pr.s2[slot]]);
