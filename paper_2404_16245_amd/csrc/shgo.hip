@@ -998,15 +998,31 @@ __host__ __device__ constexpr double fact_d(int n) {
   return f;
 }
 
-template <int LA, int LB>
-__device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs& pr, int slot, double* __restrict__ out) {
+// Staged stores: the wavefront's 64 blocks (all of one class) leave through LDS a row at a time,
+// consecutive lanes on consecutive entries, then a column at a time for the mirror.
+constexpr int kOvlStage = 64 * (2 * SHGO_LMAX + 1);  // doubles per wavefront
+__shared__ double s_ovl_stage[4][kOvlStage];
+__shared__ int64_t s_ovl_d0[4][64], s_ovl_d1[4][64];
+
+__device__ __forceinline__ void ovl_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// kStaged: every lane of the wavefront runs this class (inactive lanes, past the last pair, with
+// active = false: no loads, no stores of their own) and the stores go through LDS; otherwise each
+// active lane stores its own block.
+template <int LA, int LB, bool kStaged>
+__device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs& pr, int slot, bool active,
+                                             double* __restrict__ out) {
   constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1;
   PairState ps;
-  const int s1 = pr.s1[slot], s2 = pr.s2[slot];
+  const int s1 = active ? pr.s1[slot] : 0, s2 = active ? pr.s2[slot] : 0;
 #pragma unroll
   for (int x = 0; x < 3; ++x) {
-    ps.A[x] = bs.center[3 * s1 + x];
-    ps.B[x] = bs.center[3 * s2 + x];
+    ps.A[x] = active ? bs.center[3 * s1 + x] : 0.0;
+    ps.B[x] = active ? bs.center[3 * s2 + x] : 0.0;
   }
   frame_of(ps);
   const double R = ps.R;
@@ -1031,8 +1047,8 @@ __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs&
   double sm[LB + 1];
 #pragma unroll
   for (int m = 0; m <= LB; ++m) sm[m] = 0.0;
-  const int64_t o1 = bs.prim_off[s1], o2 = bs.prim_off[s2];
-  const int K1 = bs.nprim[s1], K2 = bs.nprim[s2];
+  const int64_t o1 = active ? bs.prim_off[s1] : 0, o2 = active ? bs.prim_off[s2] : 0;
+  const int K1 = active ? bs.nprim[s1] : 0, K2 = active ? bs.nprim[s2] : 0;
   for (int i = 0; i < K1; ++i)
     for (int j = 0; j < K2; ++j) {
       const double a = bs.expo[o1 + i], b = bs.expo[o2 + j];
@@ -1085,7 +1101,51 @@ __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs&
 #pragma unroll
     for (int i = 0; i < NA; ++i) V[i * NB + col] = v[i];
   }
-  const int64_t d0 = pr.dst0[slot], d1 = pr.dst1[slot];
+  const int64_t d0 = active ? pr.dst0[slot] : -1, d1 = active ? pr.dst1[slot] : 0;
+  if constexpr (kStaged) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* const stg = s_ovl_stage[w];
+    s_ovl_d0[w][lane] = d0;
+    s_ovl_d1[w][lane] = d1;
+    const int64_t n = bs.nbf;
+    // rows i of every block: entry k = p NB + j is block p's (i, j)
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) stg[lane * NB + j] = V[i * NB + j];
+      ovl_wave_sync();
+      for (int k = lane; k < 64 * NB; k += 64) {
+        const int q = k / NB, j = k - q * NB;
+        const int64_t e0 = s_ovl_d0[w][q], e1 = s_ovl_d1[w][q];
+        if (e0 < 0) continue;
+        if (pr.full) {
+          if (e0 != e1 || i <= j) out[(e0 + i) * n + e1 + j] = stg[k];
+        } else if (e1 == 0) {
+          out[e0 + i * NB + j] = stg[k];
+        } else {
+          out[e0 + j * NA + i] = stg[k];
+        }
+      }
+      ovl_wave_sync();
+    }
+    if (pr.full) {
+      // the mirror, column col of every block: entry k = p NA + i is block p's (i, col)
+#pragma unroll
+      for (int col = 0; col < NB; ++col) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) stg[lane * NA + i] = V[i * NB + col];
+        ovl_wave_sync();
+        for (int k = lane; k < 64 * NA; k += 64) {
+          const int q = k / NA, i = k - q * NA;
+          const int64_t e0 = s_ovl_d0[w][q], e1 = s_ovl_d1[w][q];
+          if (e0 < 0) continue;
+          if (e0 != e1 || i <= col) out[(e1 + col) * n + e0 + i] = stg[k];
+        }
+        ovl_wave_sync();
+      }
+    }
+    return;
+  }
   if (pr.full) {
     // the (s1, s2) block and its mirror; a shell with itself writes each entry once per orientation
     const int64_t n = bs.nbf;
@@ -1107,28 +1167,36 @@ __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs&
   }
 }
 
-template <int LA, int LB>
-__device__ __forceinline__ void overlap_dispatch(int c, const DevBasis& bs, const DevPairs& pr, int slot,
+template <int LA, int LB, bool kStaged>
+__device__ __forceinline__ void overlap_dispatch(int c, const DevBasis& bs, const DevPairs& pr, int slot, bool active,
                                                  double* __restrict__ out) {
   if constexpr (LA <= SHGO_LMAX) {
     if (c == class_id(LA, LB)) {
-      overlap_pair<LA, LB>(bs, pr, slot, out);
+      overlap_pair<LA, LB, kStaged>(bs, pr, slot, active, out);
       return;
     }
     if constexpr (LB < LA)
-      overlap_dispatch<LA, LB + 1>(c, bs, pr, slot, out);
+      overlap_dispatch<LA, LB + 1, kStaged>(c, bs, pr, slot, active, out);
     else
-      overlap_dispatch<LA + 1, 0>(c, bs, pr, slot, out);
+      overlap_dispatch<LA + 1, 0, kStaged>(c, bs, pr, slot, active, out);
   }
 }
 
 // One thread per class-sorted shell pair of the plan (slots from k_scatter; s1 has the higher l).
+// A wavefront whose active lanes all hold one class (all but those at class boundaries) stores
+// through LDS; the others store lane by lane.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_overlap(DevBasis bs, DevPairs pr, double* __restrict__ out) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= pr.n_cand) return;
-  const int c = class_id(bs.l[pr.s1[slot]], bs.l[pr.s2[slot]]);
-  overlap_dispatch<0, 0>(c, bs, pr, (int)slot, out);
+  const bool active = slot < pr.n_cand;
+  const int c = active ? class_id(bs.l[pr.s1[slot]], bs.l[pr.s2[slot]]) : -1;
+  const int c0 = __shfl(c, 0);  // lanes past the last pair come after the active ones
+  if (c0 < 0) return;           // no active lane in this wavefront
+  if (__all(!active || c == c0)) {
+    overlap_dispatch<0, 0, true>(c0, bs, pr, (int)(active ? slot : 0), active, out);
+  } else if (active) {
+    overlap_dispatch<0, 0, false>(c, bs, pr, (int)slot, true, out);
+  }
 }
 
 __global__ void k_fill_f64(double* p, int64_t n) {
