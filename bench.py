@@ -1,20 +1,25 @@
 #!/usr/bin/env python
 """Benchmark: contracted SHGO nuclear-attraction integrals/s on one MI355X (gfx950).
 
-Workload (default): the high-l sweep -- 49 classes (l_a, l_b) in {0..6}^2 x 2041 uncontracted
-shell pairs (100,009 pairs), exponents log-uniform [0.05, 100], centers uniform in a 10-bohr
-cube, 64 point nuclei with Z in {1..10} (seed 2, ``synth.high_l_sweep``).
+Workload (default): the batched molecule -- 200 atoms in a 20-bohr box, one shell per l = 0..4 per
+atom, K uniform 1..8 primitives, exponents log-uniform [0.1, 50], Z in 1..8, primitive pairs
+screened by exp(-mu R^2) > 1e-12, the full V matrix (nbf 5000), seed 3 (``synth.batched_molecule``).
 
 A step is one ``shgo_execute`` of a plan whose inputs already sit in HBM: primitive
-normalisation, pair classification/screening/class sort, and every class kernel (Gaussian
-product, shift, product rule, Boys, nucleus sum, contraction, scatter) -- all on the device.
+normalisation, pair classification/screening/class sort, and the persistent integral kernel
+(Gaussian product, shift, product rule, Boys, nucleus sum, contraction, scatter over every class)
+-- all on the device. The plan is autotuned once before the timed steps.
 
-Output: one JSON line on stdout. ``value`` = integrals/s over the K timed steps (HIP events on
-the stream the library launches on, bracketed by device synchronisation). ``roofline`` refers
-to the dominant class kernel, timed live with per-kernel HIP events recorded by the library
-during the same timed steps; its algorithmic FLOPs come from the per-(primitive pair, nucleus)
-and per-primitive-pair operation counts of the vector-coupling route (``model_flops``).
-``cpu_baseline`` times the CPU oracle (all host threads) on a bounded, class-stratified sample.
+Output: one JSON line on stdout. ``value`` = integrals/s over the K timed steps (HIP events on the
+stream the library launches on, bracketed by device synchronisation); integrals count the shell
+pairs that keep a primitive pair, (2la+1)(2lb+1) each. ``roofline`` refers to the integral kernel,
+timed live with HIP events the library records around its launch on the same stream during the
+same timed steps; its algorithmic FLOPs come from the per-(primitive pair, nucleus) and
+per-primitive-pair operation counts of the vector-coupling route (``model_flops``) over the
+surviving primitive pairs. ``cpu_baseline`` times the CPU oracle on a class-stratified random
+sample of the same workload's kept shell pairs, with every host thread (and, beside it, one
+thread). Extra blocks: the high-l sweep (49 (l_a, l_b) classes x 2041 uncontracted pairs, each
+class also timed alone), the gradient, and the overlap matrix.
 """
 import argparse
 import hashlib
@@ -108,9 +113,14 @@ def workload_flops(basis, nuclei, pa, pb, screen=0.0):
 # ----------------------------------------------------------------------------------------------
 # HBM traffic from the committed rocprofv3 counter summary (null when the kernel has changed)
 # ----------------------------------------------------------------------------------------------
+KERNEL_SOURCES = ("paper_2404_16245_amd/csrc/shgo_integrals.hip", "paper_2404_16245_amd/csrc/shgo_internal.h",
+                  "paper_2404_16245_amd/csrc/schedule.h", "paper_2404_16245_amd/csrc/gen_classes.py")
+
+
 def kernel_source_hash():
+    """Hash of the sources the integral kernel is compiled from."""
     h = hashlib.sha256()
-    for rel in ("paper_2404_16245_amd/csrc/shgo.hip", "paper_2404_16245_amd/csrc/gen_classes.py"):
+    for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -136,33 +146,44 @@ def traffic_from_profile(kernel_tag):
 # ----------------------------------------------------------------------------------------------
 # CPU baseline: the oracle on a class-stratified sample
 # ----------------------------------------------------------------------------------------------
-def cpu_baseline(basis, nuclei, pa, pb, target_s):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(basis, nuclei, pa, pb, screen, target_s, threads):
+    """The oracle on a class-stratified random sample of the kept shell pairs: the same fraction of
+    every (la, lb) class, sized by a pilot run to about target_s seconds. Returns (integrals/s,
+    sample description, seconds)."""
     import oracle
+    keep = surviving_prim_pairs(basis, pa, pb, screen) > 0
     la, lb = basis.l[pa], basis.l[pb]
-    order = {}
-    for c in sorted(set(zip(la.tolist(), lb.tolist()))):
-        order[c] = np.nonzero((la == c[0]) & (lb == c[1]))[0]
-    threads = os.cpu_count() or 1
+    cls = np.maximum(la, lb) * 16 + np.minimum(la, lb)
+    rng = np.random.default_rng(2024)
+    groups = [rng.permutation(np.nonzero(keep & (cls == c))[0]) for c in np.unique(cls[keep])]
 
-    def sample(k):
-        return np.concatenate([v[:k] for v in order.values()])
+    def sample(frac):
+        return np.concatenate([g[:max(1, int(round(frac * len(g))))] for g in groups])
 
-    pilot_k = 4
-    s = sample(pilot_k)
-    t0 = time.perf_counter()
-    oracle.nuc_blocks(basis, nuclei, pa[s], pb[s], nthreads=threads)
-    pilot = time.perf_counter() - t0
-    per_pair_class = max(pilot / pilot_k, 1e-6)
-    kmax = max(len(v) for v in order.values())
-    k = int(min(kmax, max(pilot_k, target_s / per_pair_class)))
-    s = sample(k)
-    t0 = time.perf_counter()
-    oracle.nuc_blocks(basis, nuclei, pa[s], pb[s], nthreads=threads)
-    dt = time.perf_counter() - t0
-    n_int = int(oracle.block_sizes(basis, pa[s], pb[s]).sum())
-    return {"value": n_int / dt, "unit": "integrals/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {k} pairs of each of the {len(order)} classes ({len(s)} pairs, {n_int} integrals, "
-                      f"{dt:.1f} s wall, OpenMP over pairs)"}
+    def run(sel):
+        t0 = time.perf_counter()
+        oracle.nuc_blocks(basis, nuclei, pa[sel], pb[sel], screen=screen, nthreads=threads)
+        return time.perf_counter() - t0
+
+    pilot = 0.002
+    dt = run(sample(pilot))
+    frac = float(min(1.0, max(pilot, pilot * target_s / max(dt, 1e-3))))
+    sel = sample(frac)
+    dt = run(sel)
+    n_int = int(oracle.block_sizes(basis, pa[sel], pb[sel]).sum())
+    desc = (f"{100 * frac:.2f}% of the kept shell pairs of each of the {len(groups)} (la,lb) classes, drawn at "
+            f"random ({len(sel)} pairs, {n_int} integrals, {dt:.1f} s wall, {threads} OpenMP thread(s) over pairs)")
+    return n_int / dt, desc, dt
 
 
 # ----------------------------------------------------------------------------------------------
@@ -181,26 +202,58 @@ def _time_ms(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def measure_batched(shgo, synth, torch, steps):
-    """200-atom molecule (l <= 4, K 1..8, screened 1e-12), full V: autotuned schedule, one
-    hipGraph-captured evaluation per step."""
-    basis, nuclei = synth.batched_molecule(seed=3)
-    screen = 1e-12
+def timed_steps(shgo, torch, plan, out, steps, warmup):
+    """K timed executions of a plan (after W warm ones) with the library's phase timers on: (ms per
+    step from events around the loop, mean ms of phase 0 (pair build) and phase 1 (integral
+    kernel) from the events the library records around its launches on the same stream)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        shgo.shgo_execute(plan, out)
+    torch.cuda.synchronize()
+    shgo.shgo_plan_set_timing(plan, steps)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        shgo.shgo_execute(plan, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    phase_ms, nrec = shgo.shgo_plan_phase_ms(plan)
+    shgo.shgo_plan_set_timing(plan, 0)
+    return total_ms / steps, phase_ms / max(nrec, 1)
+
+
+def measure_sweep(shgo, synth, torch, steps):
+    """The high-l sweep (49 (la, lb) classes x 2041 uncontracted pairs, 64 nuclei, seed 2): all
+    classes in one autotuned plan, then each (la, lb) class alone in a plan of its own pairs."""
+    basis, nuclei, pa, pb = synth.high_l_sweep(seed=2)
     ctx = shgo.context(0)
-    plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, screen)
+    plan = shgo.shgo_plan_pairs(ctx, basis, nuclei, pa, pb, 0.0)
     out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
-    ms_eager = _time_ms(torch, lambda: shgo.shgo_execute(plan, out), steps, 2)
-    tune_ms, chosen = shgo.shgo_plan_autotune(plan, out, rounds=5)
-    ms = _time_ms(torch, lambda: shgo.shgo_execute_graph(plan, out), steps, 2)
-    pa, pb = synth.all_pairs(basis.n_shells)
-    _, flops = workload_flops(basis, nuclei, pa, pb, screen)
-    return {"workload": "200 atoms, 20-bohr box, l=0..4, K uniform 1..8, screened exp(-mu R^2) > 1e-12, full V, "
-                        "seed 3; autotuned schedule, hipGraph replay",
-            "nbf": basis.nbf(), "integrals_per_step": plan.integrals, "ms_per_step": ms,
-            "integrals_per_s": plan.integrals / (ms * 1e-3), "ms_per_step_eager_untuned": ms_eager,
-            "tune_candidates_ms": [float(x) for x in tune_ms], "tune_chosen": chosen,
-            "model_flops_per_step": flops, "fp64_model_tflops": flops / (ms * 1e-3) / 1e12,
-            "fp64_vector_peak_frac": flops / (ms * 1e-3) / FP64_VECTOR_PEAK}
+    shgo.shgo_plan_autotune(plan, out, rounds=5)
+    ms, ph = timed_steps(shgo, torch, plan, out, steps, 3)
+    per_class_flops, flops = workload_flops(basis, nuclei, pa, pb, 0.0)
+    res = {"workload": "high-l sweep: 49 (l_a,l_b) classes x 2041 uncontracted shell pairs, l<=6, exponents "
+                       "log-uniform [0.05,100], 10-bohr cube, 64 nuclei Z in 1..10, seed 2; autotuned",
+           "integrals_per_step": plan.integrals, "ms_per_step": ms, "integrals_per_s": plan.integrals / (ms * 1e-3),
+           "kernel_ms": ph[1], "pair_build_ms": ph[0], "model_flops_per_launch": flops,
+           "kernel_fp64_peak_frac": flops / (ph[1] * 1e-3) / FP64_VECTOR_PEAK, "per_class": []}
+    gn = _gaunt_nnz()
+    for la in range(7):
+        for lb in range(7):
+            sel = np.nonzero((basis.l[pa] == la) & (basis.l[pb] == lb))[0]
+            p1 = shgo.shgo_plan_pairs(ctx, basis, nuclei, pa[sel], pb[sel], 0.0)
+            o1 = torch.empty(p1.output_size, dtype=torch.float64, device="cuda")
+            ms1, ph1 = timed_steps(shgo, torch, p1, o1, 20, 3)
+            nucl, pair = model_flops(max(la, lb), min(la, lb), gn)
+            f1 = len(sel) * (nuclei.n * nucl + pair)
+            res["per_class"].append({"la": la, "lb": lb, "pairs": int(len(sel)), "integrals": p1.integrals,
+                                     "ms_per_step": ms1, "kernel_ms": ph1[1],
+                                     "integrals_per_s": p1.integrals / (ms1 * 1e-3),
+                                     "kernel_fp64_peak_frac": f1 / (ph1[1] * 1e-3) / FP64_VECTOR_PEAK})
+            del p1, o1
+    return res
 
 
 def measure_overlap(shgo, synth, torch, steps):
@@ -246,10 +299,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="high_l_sweep", choices=["high_l_sweep", "small_molecule", "batched"])
+    ap.add_argument("--workload", default="batched_molecule",
+                    choices=["batched_molecule", "high_l_sweep", "small_molecule"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the batched and gradient forms")
+    ap.add_argument("--no-forms", action="store_true", help="skip the sweep, gradient and overlap blocks")
     ap.add_argument("--no-tune", action="store_true", help="time the model schedule, without autotuning")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run a plain device copy of this many bytes (calibrates HBM counters)")
@@ -271,36 +325,38 @@ def main():
     ctx = shgo.context(0)
 
     screen = 0.0
-    if args.workload == "high_l_sweep":
+    if args.workload == "batched_molecule":
+        basis, nuclei = synth.batched_molecule(seed=3)
+        pa, pb = synth.all_pairs(basis.n_shells)
+        screen = 1e-12
+        plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, screen)
+        info = shgo.shgo_plan_get_info(plan)
+        desc = ("batched molecule: 200 atoms in a 20-bohr box, shells l=0..4 per atom, K uniform 1..8, exponents "
+                "log-uniform [0.1,50], Z in 1..8, screened exp(-mu R^2) > 1e-12, full V matrix, seed 3")
+        cfg = {"workload": desc, "nbf": basis.nbf(), "atoms": nuclei.n, "shell_pairs": info["candidate_pairs"],
+               "shell_pairs_kept": info["kept_pairs"], "prim_pairs_kept": info["kept_prim_pairs"], "screen": screen,
+               "seed": 3}
+    elif args.workload == "high_l_sweep":
         basis, nuclei, pa, pb = synth.high_l_sweep(seed=2)
         plan = shgo.shgo_plan_pairs(ctx, basis, nuclei, pa, pb, screen)
         desc = ("high-l sweep: 49 (l_a,l_b) classes x 2041 uncontracted shell pairs, l<=6, exponents "
                 "log-uniform [0.05,100], 10-bohr cube, 64 nuclei Z in 1..10, seed 2")
         cfg = {"workload": desc, "shell_pairs": int(len(pa)), "nuclei": nuclei.n, "classes": 49, "seed": 2}
-    elif args.workload == "small_molecule":
+    else:
         basis, nuclei = synth.small_molecule(seed=1)
         pa, pb = synth.all_pairs(basis.n_shells)
         plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, screen)
         desc = "4 atoms in a 6-bohr cube, s/p/d shells with 3 primitives, full V matrix, seed 1"
         cfg = {"workload": desc, "nbf": basis.nbf(), "nuclei": nuclei.n, "seed": 1}
-    else:
-        basis, nuclei = synth.batched_molecule(seed=3)
-        pa, pb = synth.all_pairs(basis.n_shells)
-        screen = 1e-12
-        plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, screen)
-        desc = ("200 atoms in a 20-bohr box, shells l=0..4, K uniform 1..8, screened exp(-mu R^2) > 1e-12, "
-                "full V matrix, seed 3")
-        cfg = {"workload": desc, "nbf": basis.nbf(), "nuclei": nuclei.n, "seed": 3}
 
     out = torch.empty(plan.output_size, dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
     tune = None
     if not args.no_tune:
         # one-time schedule tuning of the plan (not part of the timed steps)
         ms_c, chosen = shgo.shgo_plan_autotune(plan, out, rounds=5)
-        weights, slices = shgo.shgo_plan_get_schedule(plan)
+        _, tiles = shgo.shgo_plan_get_schedule(plan)
         tune = {"candidates_ms": [float(x) for x in ms_c], "chosen": chosen,
-                "tiles_per_item": {int(c): int(v) for c, v in enumerate(slices)}}
+                "tiles_per_item": {int(c): int(v) for c, v in enumerate(tiles)}}
     if args.copy_bytes > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters calibrate the kernel's
         src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
@@ -310,52 +366,41 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     log(f"bench: {args.workload}, {plan.integrals} integrals per step, warmup {args.warmup}, steps {args.steps}")
-    for _ in range(args.warmup):
-        shgo.shgo_execute(plan, out)
-    torch.cuda.synchronize()
-
-    shgo.shgo_plan_set_timing(plan, args.steps)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        shgo.shgo_execute(plan, out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    phase_ms, nrec = shgo.shgo_plan_phase_ms(plan)
-    shgo.shgo_plan_set_timing(plan, 0)
-    ms_per_step = total_ms / args.steps
-    value = plan.integrals * args.steps / (total_ms * 1e-3)
+    ms_per_step, phase = timed_steps(shgo, torch, plan, out, args.steps, args.warmup)
+    value = plan.integrals / (ms_per_step * 1e-3)
     log(f"bench: {ms_per_step:.4f} ms/step, {value:.4e} integrals/s")
 
-    per_class_flops, total_flops = workload_flops(basis, nuclei, pa, pb, screen)
-    avg_phase_ms = phase_ms / max(nrec, 1)
-    kern_s = avg_phase_ms[1] * 1e-3
+    _, total_flops = workload_flops(basis, nuclei, pa, pb, screen)
+    kern_s = phase[1] * 1e-3
     achieved = total_flops / kern_s / 1e12
     tag = f"k_integrals_{args.workload}"
-    traffic = traffic_from_profile(tag)
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": traffic,
-                "kernel": "k_integrals (persistent, every class)", "kernel_ms": avg_phase_ms[1],
+                "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": traffic_from_profile(tag),
+                "kernel": "k_integrals (persistent, every class)", "kernel_ms": phase[1],
                 "model_flops_per_launch": total_flops}
     step_tflops = total_flops / (ms_per_step * 1e-3) / 1e12
     res = {"metric": METRIC, "value": value, "unit": "integrals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
-           "integrals_per_step": plan.integrals,
-           "fp64_model_tflops": step_tflops, "fp64_vector_peak_frac": step_tflops / (FP64_VECTOR_PEAK / 1e12),
-           "pair_build_ms": avg_phase_ms[0], "roofline": roofline, "schedule_tuning": tune}
-    if not args.no_forms and args.workload == "high_l_sweep":
-        log("bench: batched form")
-        res["batched"] = measure_batched(shgo, synth, torch, max(3, args.steps // 2))
+           "integrals_per_step": plan.integrals, "fp64_model_tflops": step_tflops,
+           "fp64_vector_peak_frac": step_tflops / (FP64_VECTOR_PEAK / 1e12), "pair_build_ms": phase[0],
+           "roofline": roofline, "schedule_tuning": tune}
+    if not args.no_forms:
+        del out
+        log("bench: high-l sweep, all classes and each class alone")
+        res["high_l_sweep"] = measure_sweep(shgo, synth, torch, args.steps)
         log("bench: gradient form")
         res["gradient"] = measure_gradient(shgo, synth, torch, 3)
         log("bench: overlap form")
         res["overlap"] = measure_overlap(shgo, synth, torch, 5)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
-        res["cpu_baseline"] = cpu_baseline(basis, nuclei, pa, pb, args.cpu_seconds)
+        threads = os.cpu_count() or 1
+        v, desc_s, _ = cpu_baseline(basis, nuclei, pa, pb, screen, args.cpu_seconds, threads)
+        v1, desc_1, _ = cpu_baseline(basis, nuclei, pa, pb, screen, args.cpu_seconds / 2, 1)
+        res["cpu_baseline"] = {"value": v, "unit": "integrals/s", "cores": threads, "kind": "oracle",
+                               "sample": desc_s, "cpu_model": cpu_model(), "value_1_thread": v1,
+                               "sample_1_thread": desc_1}
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

@@ -71,6 +71,30 @@ typedef struct {
   const double* charge;    /* [n_nuclei] (Z) */
 } shgo_nuclei;
 
+/* Arithmetic of the integral evaluation.
+ *   SHGO_PREC_FP64   binary64 throughout.
+ *   SHGO_PREC_MIXED  the product-rule / shift coupling of each primitive pair and the primitive
+ *                    accumulation in binary32 with error-free transformations (see
+ *                    shgo_plan_set_precision); Boys function, exp(-mu R^2) prefactors and the
+ *                    final contraction stay binary64. */
+typedef enum { SHGO_PREC_FP64 = 0, SHGO_PREC_MIXED = 1 } shgo_precision;
+
+/* Options of the single-call entry points (shgo_nuclear_attraction, shgo_nuclear_attraction_grad).
+ * shgo_options_default fills: FP64, no screening, no graph, no autotune cache, no scratch limit. */
+typedef struct {
+  int32_t precision;          /* shgo_precision */
+  double screen_threshold;    /* drop primitive pairs with exp(-ab/(a+b)|A-B|^2) <= it; 0 keeps all */
+  int32_t use_graph;          /* nonzero: replay the evaluation as a captured HIP graph (V only) */
+  const char* autotune_cache; /* NULL, or the path of a schedule file: read if it exists (a file
+                                 that is not a schedule: SHGO_ERR_INVALID_ARG before any device
+                                 work), else a new plan is autotuned once and the file written
+                                 (V only) */
+  size_t scratch_limit_bytes; /* 0: no limit; else SHGO_ERR_OUT_OF_MEMORY, before any device work,
+                                 when the call's device workspace would exceed it */
+} shgo_options;
+
+void shgo_options_default(shgo_options* options);
+
 /* Create a context on HIP device `device` (tables are built on the host and uploaded).
  * Returns SHGO_ERR_DEVICE if the device cannot be used. */
 shgo_status shgo_create(int device, shgo_context** ctx);
@@ -87,6 +111,31 @@ int64_t shgo_nbf(const shgo_basis* basis);
  * copies a NUL-terminated message of at most msg_len bytes into it. */
 shgo_status shgo_validate(const shgo_basis* basis, const shgo_nuclei* nuclei, double screen, char* msg,
                           size_t msg_len);
+
+
+/* V = -sum_c Z_c int chi_a chi_b / |r - c| (Eq. 11 with the Boys function of Eq. 12), the full
+ * symmetric nbf x nbf matrix in one call: validates, copies the inputs to the device, builds the
+ * shell pairs, and evaluates on `stream` into the device buffer V (nbf * nbf doubles, row-major,
+ * every element written). The context keeps the plan of its last call: a call with byte-identical
+ * inputs and options reuses it (no copies; its tuned schedule and captured graph); a call with
+ * others first waits for the device, then replaces it.
+ *   options  NULL: shgo_options_default.
+ * Errors before any device work, with V untouched: SHGO_ERR_INVALID_ARG / _UNSUPPORTED_L /
+ * _NOT_FINITE as for shgo_validate; SHGO_ERR_OUT_OF_MEMORY when the workspace would exceed
+ * options->scratch_limit_bytes or the device allocation fails. */
+shgo_status shgo_nuclear_attraction(shgo_context* ctx, const shgo_basis* basis, const shgo_nuclei* nuclei,
+                                    const shgo_options* options, double* V, void* stream);
+
+/* dE/d(nuclear positions) and dE/d(shell centers) of E = sum_ij D_ij V_ij in one call (the adjoint
+ * of Eq. 11 through Eq. 5, the shift of Eqs. 7-8, the product rule and the Boys function):
+ *   D            device, nbf x nbf row-major
+ *   dE_dnuclei   device [n_nuclei][3], overwritten
+ *   dE_dcenters  device [n_shells][3], overwritten
+ * Plan reuse, options and errors as for shgo_nuclear_attraction (use_graph and autotune_cache do
+ * not apply; precision must be SHGO_PREC_FP64). */
+shgo_status shgo_nuclear_attraction_grad(shgo_context* ctx, const shgo_basis* basis, const shgo_nuclei* nuclei,
+                                         const shgo_options* options, const double* D, double* dE_dnuclei,
+                                         double* dE_dcenters, void* stream);
 
 /* Plan for the full symmetric matrix V (nbf x nbf, row-major) over every shell pair a <= b.
  * screen > 0 drops primitive pairs with exp(-ab/(a+b) |A-B|^2) <= screen (0 keeps all; a pair
@@ -109,13 +158,40 @@ void shgo_plan_destroy(shgo_plan* plan);
 /* Number of doubles the plan writes (nbf*nbf for a matrix plan, sum of block sizes otherwise). */
 int64_t shgo_plan_output_size(const shgo_plan* plan);
 
-/* Number of integrals one execution computes: sum over the plan's shell pairs of
- * (2 l_a + 1)(2 l_b + 1) (unique pairs a <= b for a matrix plan). */
+/* Number of integrals one execution computes: sum of (2 l_a + 1)(2 l_b + 1) over the plan's shell
+ * pairs that keep at least one primitive pair (all of them without screening; unique pairs a <= b
+ * for a matrix plan). The other shell pairs' blocks are written as zeros. */
 int64_t shgo_plan_integrals(const shgo_plan* plan);
+
+/* Sizes of a plan. kept_*: after screening (the same rule as the kernels, evaluated on the host). */
+typedef struct {
+  int64_t candidate_pairs;  /* shell pairs of the plan (a <= b, or the list) */
+  int64_t kept_pairs;       /* shell pairs with at least one surviving primitive pair */
+  int64_t kept_prim_pairs;  /* surviving primitive pairs */
+  int64_t integrals;        /* as shgo_plan_integrals */
+  int64_t output_size;      /* as shgo_plan_output_size */
+  int64_t nbf;
+  size_t workspace_bytes;   /* the plan's device workspace */
+} shgo_plan_info;
+shgo_status shgo_plan_get_info(const shgo_plan* plan, shgo_plan_info* info);
+
+/* The host-side checks of a single call (shgo_nuclear_attraction / _grad with these inputs and
+ * options), without touching a device: input validation, the options, and the scratch limit
+ * against the device workspace the call needs. When `info` is not NULL and the inputs are valid,
+ * it receives the sizes of the matrix plan the call would make. Returns the status the call would
+ * return before any device work; `msg` (or NULL) receives a NUL-terminated message of at most
+ * msg_len bytes. */
+shgo_status shgo_check_call(const shgo_basis* basis, const shgo_nuclei* nuclei, const shgo_options* options,
+                            shgo_plan_info* info, char* msg, size_t msg_len);
 
 /* Run the whole evaluation on `stream`, writing the plan's output into the device buffer `out`
  * (shgo_plan_output_size doubles; every element is written). Allocates nothing. */
 shgo_status shgo_execute(shgo_plan* plan, double* out, void* stream);
+
+/* Arithmetic of the plan's integral evaluation (shgo_execute, shgo_execute_graph):
+ * SHGO_PREC_FP64 (the default) or SHGO_PREC_MIXED. SHGO_ERR_INVALID_ARG for an unknown value or a
+ * precision this build does not offer. Replaces a captured graph. */
+shgo_status shgo_plan_set_precision(shgo_plan* plan, int32_t precision);
 
 /* The overlap matrix S of the plan's shells (Eqs. 4-10: the Gaussian product, the shift of both
  * harmonics to P, and the single-center overlap, which the orthogonality of the harmonics

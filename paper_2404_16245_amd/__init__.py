@@ -31,10 +31,13 @@ EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_erro
             "shgo_plan_integrals", "shgo_execute", "shgo_execute_graph", "shgo_execute_grad", "shgo_boys",
             "shgo_execute_overlap",
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
-            "shgo_plan_autotune", "shgo_max_tiles"]
+            "shgo_plan_autotune", "shgo_max_tiles", "shgo_options_default", "shgo_check_call",
+            "shgo_nuclear_attraction", "shgo_nuclear_attraction_grad", "shgo_plan_get_info", "shgo_plan_set_precision"]
 SHGO_NUM_CLASSES = 28
 SHGO_TUNE_CANDIDATES = 5
 SHGO_NUM_PHASES = 2
+SHGO_PREC_FP64 = 0
+SHGO_PREC_MIXED = 1
 
 
 class ShgoError(RuntimeError):
@@ -51,6 +54,17 @@ class _Basis(ctypes.Structure):
 
 class _Nuclei(ctypes.Structure):
     _fields_ = [("n_nuclei", ctypes.c_int32), ("position", ctypes.c_void_p), ("charge", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("screen_threshold", ctypes.c_double), ("use_graph", ctypes.c_int32),
+                ("autotune_cache", ctypes.c_char_p), ("scratch_limit_bytes", ctypes.c_size_t)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("candidate_pairs", ctypes.c_int64), ("kept_pairs", ctypes.c_int64),
+                ("kept_prim_pairs", ctypes.c_int64), ("integrals", ctypes.c_int64), ("output_size", ctypes.c_int64),
+                ("nbf", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -111,6 +125,21 @@ def load_library(path=LIB_PATH):
     lib.shgo_plan_set_timing.restype = ctypes.c_int
     lib.shgo_plan_phase_ms.argtypes = [vp, vp, vp]
     lib.shgo_plan_phase_ms.restype = ctypes.c_int
+    lib.shgo_options_default.argtypes = [ctypes.POINTER(_Options)]
+    lib.shgo_options_default.restype = None
+    lib.shgo_check_call.argtypes = [ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei), ctypes.POINTER(_Options),
+                                    ctypes.POINTER(_PlanInfo), ctypes.c_char_p, ctypes.c_size_t]
+    lib.shgo_check_call.restype = ctypes.c_int
+    lib.shgo_nuclear_attraction.argtypes = [vp, ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei),
+                                            ctypes.POINTER(_Options), vp, vp]
+    lib.shgo_nuclear_attraction.restype = ctypes.c_int
+    lib.shgo_nuclear_attraction_grad.argtypes = [vp, ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei),
+                                                 ctypes.POINTER(_Options), vp, vp, vp, vp]
+    lib.shgo_nuclear_attraction_grad.restype = ctypes.c_int
+    lib.shgo_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
+    lib.shgo_plan_get_info.restype = ctypes.c_int
+    lib.shgo_plan_set_precision.argtypes = [vp, i32]
+    lib.shgo_plan_set_precision.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -138,6 +167,36 @@ class _HostNuclei:
         self.pos = np.ascontiguousarray(nuclei.pos, dtype=np.float64).reshape(-1, 3)
         self.Z = np.ascontiguousarray(nuclei.Z, dtype=np.float64)
         self.struct = _Nuclei(int(self.Z.shape[0]), self.pos.ctypes.data, self.Z.ctypes.data)
+
+
+_PRECISIONS = {"fp64": SHGO_PREC_FP64, "mixed": SHGO_PREC_MIXED}
+
+
+def shgo_options_default():
+    o = _Options()
+    load_library().shgo_options_default(ctypes.byref(o))
+    return o
+
+
+def options(precision="fp64", screen=0.0, use_graph=False, autotune_cache=None, scratch_limit_bytes=0):
+    """A shgo_options struct for the single-call entry points."""
+    o = shgo_options_default()
+    o.precision = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.screen_threshold = float(screen)
+    o.use_graph = 1 if use_graph else 0
+    o.autotune_cache = None if autotune_cache is None else os.fsencode(autotune_cache)
+    o.scratch_limit_bytes = int(scratch_limit_bytes)
+    return o
+
+
+def shgo_check_call(basis, nuclei, opts=None):
+    """(status, message, plan sizes as a dict) of the host-side checks of a single call."""
+    hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
+    buf = ctypes.create_string_buffer(256)
+    info = _PlanInfo()
+    st = load_library().shgo_check_call(ctypes.byref(hb.struct), ctypes.byref(hn.struct),
+                                        None if opts is None else ctypes.byref(opts), ctypes.byref(info), buf, 256)
+    return int(st), buf.value.decode(), {k: int(getattr(info, k)) for k, _ in _PlanInfo._fields_}
 
 
 def _stream_handle(stream=None):
@@ -225,6 +284,43 @@ def shgo_plan_pairs(ctx, basis, nuclei, pair_a, pair_b, screen=0.0):
     _check(lib, ctx, lib.shgo_plan_pairs(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct), int(pa.shape[0]),
                                          pa.ctypes.data, pb.ctypes.data, float(screen), ctypes.byref(h)))
     return Plan(ctx, h)
+
+
+def shgo_nuclear_attraction(ctx, basis, nuclei, opts, V, stream=None):
+    """The single call: V (float64 device tensor, nbf x nbf) from the host basis and nuclei."""
+    lib = load_library()
+    hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
+    nbf = int(np.sum(2 * hb.l + 1))
+    _check(lib, ctx, lib.shgo_nuclear_attraction(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct),
+                                                 None if opts is None else ctypes.byref(opts),
+                                                 _f64_device(V, "V", nbf * nbf), _stream_handle(stream)))
+    return V
+
+
+def shgo_nuclear_attraction_grad(ctx, basis, nuclei, opts, D, dE_dnuclei, dE_dcenters, stream=None):
+    """The single call of the gradient of E = sum D V (float64 device tensors)."""
+    lib = load_library()
+    hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
+    nbf = int(np.sum(2 * hb.l + 1))
+    _check(lib, ctx, lib.shgo_nuclear_attraction_grad(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct),
+                                                      None if opts is None else ctypes.byref(opts),
+                                                      _f64_device(D, "D", nbf * nbf),
+                                                      _f64_device(dE_dnuclei, "dE_dnuclei", 3 * int(hn.Z.shape[0])),
+                                                      _f64_device(dE_dcenters, "dE_dcenters", 3 * int(hb.l.shape[0])),
+                                                      _stream_handle(stream)))
+
+
+def shgo_plan_get_info(plan):
+    info = _PlanInfo()
+    lib = load_library()
+    _check(lib, plan.ctx, lib.shgo_plan_get_info(plan.handle, ctypes.byref(info)))
+    return {k: int(getattr(info, k)) for k, _ in _PlanInfo._fields_}
+
+
+def shgo_plan_set_precision(plan, precision):
+    lib = load_library()
+    p = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib, plan.ctx, lib.shgo_plan_set_precision(plan.handle, p))
 
 
 def shgo_plan_destroy(plan):
@@ -362,14 +458,15 @@ def context(device=0):
     return _ctx[device]
 
 
-def nuclear_attraction(basis, nuclei, screen=0.0, device=0):
-    """Full nbf x nbf nuclear-attraction matrix as a float64 CUDA tensor."""
+def nuclear_attraction(basis, nuclei, screen=0.0, device=0, precision="fp64", use_graph=False, autotune_cache=None,
+                       scratch_limit_bytes=0):
+    """Full nbf x nbf nuclear-attraction matrix as a float64 CUDA tensor (shgo_nuclear_attraction)."""
     import torch
     ctx = context(device)
-    plan = shgo_plan_matrix(ctx, basis, nuclei, screen)
     nbf = shgo_nbf(basis)
     out = torch.empty((nbf, nbf), dtype=torch.float64, device=f"cuda:{device}")
-    shgo_execute(plan, out)
+    opts = options(precision, screen, use_graph, autotune_cache, scratch_limit_bytes)
+    shgo_nuclear_attraction(ctx, basis, nuclei, opts, out)
     torch.cuda.current_stream().synchronize()
     return out
 

@@ -838,20 +838,35 @@ def emit_grad_header(lmax=LMAX_SHELL):
     return "\n".join(out) + "\n"
 
 
-def emit_header(cap=None, lmax=LMAX_SHELL):
-    out = ["// Generated by gen_classes.py -- do not edit. Class-specific code of the nuclear-attraction",
-           "// kernel: nucleus step, coupling (product rule + shift along the A->B axis) and rotations.",
-           f"// Group register budget: {cap if cap is not None else 'per class (class_cap)'} doubles.",
+def emit_rotations(lmax=LMAX_SHELL):
+    out = ["// Generated by gen_classes.py -- do not edit. Rotation of a real solid-harmonic vector from the",
+           "// pair frame (z along A->B) back to the laboratory frame, D^l(Q)^T = Z(phi) J^T Z(theta) J.",
            "#pragma once",
            "",
            "template <int L> struct Rot;"]
     for l in range(lmax + 1):
         out.append(emit_rotation(l))
-    out.append("template <int LA, int LB> struct ClassInfo;")
-    out.append("template <int LA, int LB, int G> struct GroupOf;")
+    return "\n".join(out) + "\n"
+
+
+def emit_meta(cap=None, lmax=LMAX_SHELL):
+    """Host- and device-visible class constants: the wavefront groups of every class."""
     qs = [len(class_groups(LA, LB, cap)) for LA in range(lmax + 1) for LB in range(LA + 1)]
-    out.append("// groups per class, indexed by la(la+1)/2 + lb")
-    out.append(f"constexpr int kClassGroups[{len(qs)}] = {{{', '.join(map(str, qs))}}};")
+    out = ["// Generated by gen_classes.py -- do not edit. Wavefront groups of each (la, lb) class of the",
+           "// integral kernel, indexed by la(la+1)/2 + lb.",
+           "#pragma once",
+           f"constexpr int kClassGroups[{len(qs)}] = {{{', '.join(map(str, qs))}}};"]
+    return "\n".join(out) + "\n"
+
+
+def emit_header(cap=None, lmax=LMAX_SHELL):
+    out = ["// Generated by gen_classes.py -- do not edit. Class-specific code of the nuclear-attraction",
+           "// kernel: nucleus step and coupling (product rule + shift along the A->B axis) per group.",
+           f"// Group register budget: {cap if cap is not None else 'per class (class_cap)'} doubles.",
+           "#pragma once",
+           "",
+           "template <int LA, int LB> struct ClassInfo;",
+           "template <int LA, int LB, int G> struct GroupOf;"]
     for LA in range(lmax + 1):
         for LB in range(LA + 1):
             groups = class_groups(LA, LB, cap)
@@ -865,22 +880,27 @@ def emit_header(cap=None, lmax=LMAX_SHELL):
     return "\n".join(out) + "\n"
 
 
+def _write(path, text):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        f.write(text)
+    os.replace(tmp, path)
+
+
 def main(argv):
+    """Writes shgo_classes.inc (the path given, default generated/shgo_classes.inc) and, beside it,
+    shgo_rot.inc, shgo_meta.inc and shgo_grad.inc."""
     out = argv[1] if len(argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)), "generated",
                                                      "shgo_classes.inc")
     cap = None
     if "--cap" in argv:
         cap = int(argv[argv.index("--cap") + 1])
-    os.makedirs(os.path.dirname(out), exist_ok=True)
-    text = emit_header(cap)
-    tmp = out + ".tmp"
-    with open(tmp, "w") as f:
-        f.write(text)
-    os.replace(tmp, out)
-    gout = os.path.join(os.path.dirname(out), "shgo_grad.inc")
-    with open(gout + ".tmp", "w") as f:
-        f.write(emit_grad_header())
-    os.replace(gout + ".tmp", gout)
+    d = os.path.dirname(out)
+    os.makedirs(d, exist_ok=True)
+    _write(out, emit_header(cap))
+    _write(os.path.join(d, "shgo_rot.inc"), emit_rotations())
+    _write(os.path.join(d, "shgo_meta.inc"), emit_meta(cap))
+    _write(os.path.join(d, "shgo_grad.inc"), emit_grad_header())
     return out
 
 

@@ -1,0 +1,372 @@
+// Internal header of the MI355X (gfx950) nuclear-attraction library: constants, the device
+// data layout, device helpers shared by the kernels (exponential, Boys function, pair frame),
+// the plan and context objects and the launch functions each translation unit provides.
+//
+// Method (arXiv:2404.16245): Gaussian product (Eq. 5), shift of both solid harmonics to the
+// product center P with the vector-coupling coefficients (Eqs. 7-8), product rule of solid
+// harmonics (the supplement's Eq. 4), one-center Coulomb integral by Hobson's theorem and the
+// Boys function (Eqs. 11-12, each r^{2k} Y^L_M term of the product rule giving
+// Y^L_M(c-P) 2 pi k!/p^{k+1} sum_j T^j/j! F_{L+j}(T)), sum over nuclei, contraction.
+//
+// Translation units:
+//   shgo_pairs.hip      a1: normalisation, enumeration, screening, class sort (k_classify,
+//                       k_scan_keys, k_scatter); the Boys test kernels; fill kernel
+//   shgo_integrals.hip  a2-a8: the persistent integral kernel (k_integrals)
+//   shgo_overlap.hip    the overlap matrix S (k_overlap)
+//   shgo_grad.hip       the adjoint kernels of the gradient (k_grad<LA, LB>)
+//   shgo_api.hip        host side: the C ABI, plans, the autotuner
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "shgo.h"
+#include "schedule.h"
+#include "generated/shgo_meta.inc"
+
+static_assert(shgo_sched::kLmax == SHGO_LMAX, "schedule and ABI disagree on the highest l");
+static_assert(shgo_sched::kNumClasses == SHGO_NUM_CLASSES, "schedule and ABI disagree on the class count");
+
+namespace shgo_impl {
+
+using namespace shgo_sched;
+
+// ---------------------------------------------------------------------------------------------
+// Constants and device data layout
+// ---------------------------------------------------------------------------------------------
+constexpr int kBoysOrders = 22;    // F_0..F_21 stored per grid point (mmax <= 14 with 8 Taylor terms)
+constexpr int kBoysPoints = 1153;  // grid t_i = i/16, i = 0..1152
+constexpr double kBoysTcut = 72.0; // below: table; above: asymptotic form (e^{-t} < 6e-32)
+constexpr int kPrefetchMaxW = 32;  // groups up to this many W doubles prefetch the next nucleus
+constexpr int kClassifyThreads = 1024;
+constexpr int kGradThreads = 256;
+
+struct alignas(32) Nuc {
+  double x, y, z, Z;
+};
+// Nuclei are read through the scalar data cache: the index is the same in every lane, and the
+// constant address space lets the compiler use scalar loads.
+typedef const __attribute__((address_space(4))) Nuc* NucPtr;
+
+__device__ __forceinline__ NucPtr uniform_nuclei(const Nuc* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (NucPtr)(((uint64_t)hi << 32) | lo);
+}
+
+struct DevBasis {
+  const double* center;    // [n][3]
+  const int32_t* l;        // [n]
+  const int32_t* nprim;    // [n]
+  const int64_t* prim_off; // [n]
+  const double* expo;      // [nprim total]
+  const double* coef;      // [nprim total]
+  double* w;               // [nprim total] normalised weights (written by k_classify)
+  const int64_t* bf_off;   // [n] first basis function of each shell
+  int32_t n_shells;
+  int64_t nbf;
+};
+
+struct DevPairs {
+  int64_t n_cand;          // candidate shell pairs
+  int32_t full;            // 1: all a <= b of the basis; 0: explicit list
+  const int32_t* pa;       // [n_cand] (explicit list)
+  const int32_t* pb;
+  const int64_t* blk_off;  // [n_cand] output offset of each block (explicit list)
+  int32_t* key;            // [n_cand] sort key
+  int32_t* s1;             // [n_cand] sorted: shell with the higher l
+  int32_t* s2;             // [n_cand] sorted: the other shell
+  int32_t* orig;           // [n_cand] sorted: candidate index
+  int32_t* nsurv;          // [n_cand] sorted: surviving primitive pairs
+  int32_t* key_count;      // [kNumKeys]
+  int32_t* rank;           // [n_cand] position inside the key's bucket
+  int32_t* key_off;        // [kNumKeys + 1]
+  int64_t* dst0;           // [n_cand] sorted: output row offset of s1 (matrix) or block offset (list)
+  int64_t* dst1;           // [n_cand] sorted: output offset of s2 (matrix) or 1 if the listed pair is (s2, s1)
+  double screen;
+};
+
+// Schedule of the persistent integral kernel.
+struct ClassMeta {
+  float weight[kNumClasses];   // relative time of one primitive-pair iteration of a tile of the class
+  int32_t tiles[kNumClasses];  // tiles per work item, 1..8, within the LDS of a workgroup
+  int32_t groups[kNumClasses]; // wavefront groups of the class (fixed by the generated code)
+};
+
+struct WorkArgs {
+  DevBasis bs;
+  DevPairs pr;
+  const Nuc* __restrict__ nuc;
+  int32_t n_nuc;
+  const double* __restrict__ boys_tab;
+  int32_t* __restrict__ queue;     // [0]: next work item
+  int32_t* __restrict__ item_off;  // [0]: number of work items
+  int32_t* __restrict__ items;     // work items, longest first: class << 24 | tile block
+  unsigned long long* __restrict__ item_ns;  // per-item durations (10 ns ticks) when tuning, else null
+  ClassMeta meta;
+};
+// The work arguments live in device memory (one copy per plan) and are read through the scalar
+// data cache: every lane of a wavefront reads the same fields.
+typedef const __attribute__((address_space(4))) WorkArgs* WAP;
+
+__device__ __forceinline__ WAP uniform_args(const WorkArgs* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (WAP)(((uint64_t)hi << 32) | lo);
+}
+
+struct GradArgs {
+  DevBasis bs;
+  DevPairs pr;
+  const Nuc* __restrict__ nuc;
+  int32_t n_nuc;
+  const double* __restrict__ boys_tab;
+  const double* __restrict__ D;  // nbf x nbf
+  double* __restrict__ dnuc;     // [n_nuc][3]
+  double* __restrict__ dcen;     // [n_shells][3]
+  double* __restrict__ energy;   // [1]
+};
+
+// ---------------------------------------------------------------------------------------------
+// Exponential (device)
+// ---------------------------------------------------------------------------------------------
+// The polynomial constants of an exponential inside the integral kernel's loops would otherwise be
+// kept in vector registers across the loop and, under the kernel's register pressure, spilled and
+// reloaded on every iteration. These helpers take the constant as a scalar operand (one per
+// instruction, the constant-bus limit), materialised in scalar registers.
+__device__ __forceinline__ double fma_vvs(double a, double b, double c) {  // a * b + c, c scalar
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+__device__ __forceinline__ double mul_vs(double a, double b) {  // a * b, b scalar
+  double r;
+  asm("v_mul_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+__device__ __forceinline__ double add_vs(double a, double b) {  // a + b, b scalar
+  double r;
+  asm("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+
+// e^{-t} for t >= 0 (0 once it underflows): Cody-Waite reduction t = n ln 2 - r with the two-part
+// ln 2 of fdlibm (n ln2_hi exact), |r| <= ln(2)/2, and the Taylor polynomial of e^r to degree 13
+// (remainder below 5e-18 relative) by Horner's rule, then the exponent n.
+__device__ __forceinline__ double exp_neg(double t) {
+  const double x = -fmin(t, 746.0);
+  const double n = rint(x * 1.4426950408889634074);  // log2(e)
+  double r = fma(n, -6.93147180369123816490e-01, x);
+  r = fma(n, -1.90821492927058770002e-10, r);
+  double q = add_vs(mul_vs(r, 1.6059043836821614599e-10), 2.0876756987868098979e-09);  // 1/13!, 1/12!
+  q = fma_vvs(q, r, 2.5052108385441718775e-08);  // 1/11!
+  q = fma_vvs(q, r, 2.7557319223985890653e-07);  // 1/10!
+  q = fma_vvs(q, r, 2.7557319223985890653e-06);  // 1/9!
+  q = fma_vvs(q, r, 2.4801587301587301587e-05);  // 1/8!
+  q = fma_vvs(q, r, 1.9841269841269841270e-04);  // 1/7!
+  q = fma_vvs(q, r, 1.3888888888888888889e-03);  // 1/6!
+  q = fma_vvs(q, r, 8.3333333333333333333e-03);  // 1/5!
+  q = fma_vvs(q, r, 4.1666666666666666667e-02);  // 1/4!
+  q = fma_vvs(q, r, 1.6666666666666666667e-01);  // 1/3!
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  q = fma(q, r, 1.0);
+  return ldexp(q, (int)n);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Boys function (device)
+// ---------------------------------------------------------------------------------------------
+// x^N by repeated squaring (depth log2 N).
+template <int N>
+__device__ __forceinline__ double pow_n(double x) {
+  if constexpr (N == 0) {
+    return 1.0;
+  } else if constexpr (N == 1) {
+    return x;
+  } else {
+    const double h = pow_n<N / 2>(x);
+    return (N & 1) ? h * h * x : h * h;
+  }
+}
+// Gamma(M + 1/2) / 2 = sqrt(pi) (2M-1)!! / 2^{M+1}
+__host__ __device__ constexpr double half_gamma_half(int M) {
+  double c = 0.88622692545275801365;
+  for (int k = 1; k <= M; ++k) c *= (2.0 * k - 1.0) * 0.5;
+  return c;
+}
+
+// The same evaluation for the integral kernel, with the Taylor row F_{M..M+7}(t_i) of the nearest
+// grid point (clamped to the table) already loaded and e = exp(-t), and no divergent branch: F_M
+// is the table's Taylor series below kBoysTcut and the leading asymptotic term
+// Gamma(M+1/2) / (2 t^{M+1/2}) above it (the neglected part is below e^{-t}/t, 1e-17 relative for
+// M <= 12 at t = 72), selected per lane; then the downward recursion, stable for every t.
+template <int M>
+__device__ __forceinline__ void boys_row(double t, double e, const double (&row)[8], double (&F)[M + 1]) {
+  const int i = (int)(fmin(t, kBoysTcut) * 16.0 + 0.5);
+  const double d = -(t - 0.0625 * (double)i);
+  double f = row[7];
+  f = fma(f, d * (1.0 / 7.0), row[6]);
+  f = fma(f, d * (1.0 / 6.0), row[5]);
+  f = fma(f, d * (1.0 / 5.0), row[4]);
+  f = fma(f, d * (1.0 / 4.0), row[3]);
+  f = fma(f, d * (1.0 / 3.0), row[2]);
+  f = fma(f, d * (1.0 / 2.0), row[1]);
+  f = fma(f, d, row[0]);
+  // 1/sqrt(t) from the hardware estimate and two Newton steps (each doubles the bits)
+  double rs = __builtin_amdgcn_rsq(t);
+  rs = rs * fma(-0.5 * t * rs, rs, 1.5);
+  rs = rs * fma(-0.5 * t * rs, rs, 1.5);
+  const double fa = half_gamma_half(M) * rs * pow_n<M>(rs * rs);
+  F[M] = t < kBoysTcut ? f : fa;
+  const double t2 = 2.0 * t;
+#pragma unroll
+  for (int m = M - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
+}
+
+
+__device__ __forceinline__ bool keep_prim(double a, double b, double R2, double screen) {
+  if (!(screen > 0.0)) return true;
+  return exp_neg(a * b / (a + b) * R2) > screen;
+}
+
+// Per-lane shell-pair state.
+struct PairState {
+  int s1, s2;
+  bool active;
+  double A[3], B[3];
+  double R, ct, st, cp, sp;  // |B-A| and the frame angles
+  int64_t o1, o2;
+  int K1, K2;
+  int nsurv;
+};
+
+__device__ __forceinline__ void frame_of(PairState& ps) {
+  const double rx = ps.B[0] - ps.A[0], ry = ps.B[1] - ps.A[1], rz = ps.B[2] - ps.A[2];
+  const double rho2 = rx * rx + ry * ry;
+  const double R = sqrt(rho2 + rz * rz);
+  const double rho = sqrt(rho2);
+  ps.R = R;
+  if (R > 0.0) {
+    ps.ct = rz / R;
+    ps.st = rho / R;
+  } else {
+    ps.ct = 1.0;
+    ps.st = 0.0;
+  }
+  if (rho > 0.0) {
+    ps.cp = rx / rho;
+    ps.sp = ry / rho;
+  } else {
+    ps.cp = 1.0;
+    ps.sp = 0.0;
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void angles(double c1, double s1, double (&c)[L + 1], double (&s)[L + 1]) {
+  c[0] = 1.0;
+  s[0] = 0.0;
+#pragma unroll
+  for (int m = 1; m <= L; ++m) {
+    c[m] = c[m - 1] * c1 - s[m - 1] * s1;
+    s[m] = s[m - 1] * c1 + c[m - 1] * s1;
+  }
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+}  // namespace shgo_impl
+
+// ---------------------------------------------------------------------------------------------
+// Host objects (the opaque types of the C ABI)
+// ---------------------------------------------------------------------------------------------
+struct shgo_context {
+  int device = 0;
+  int n_cu = 0;
+  int grid = 0;  // workgroups of the persistent kernel resident on the device at once
+  double* boys_tab = nullptr;
+  std::string err;
+  // the plan of the last single call (shgo_nuclear_attraction, _grad) and the inputs it was made
+  // from: a repeated call with the same inputs reuses it (device copies, tuned schedule, graph)
+  shgo_plan* call_plan = nullptr;
+  std::vector<char> call_key;
+};
+
+struct shgo_plan {
+  shgo_context* ctx = nullptr;
+  int full = 0;
+  int32_t n_shells = 0, n_nuc = 0;
+  int64_t nbf = 0, n_cand = 0, out_size = 0;
+  int64_t integrals = 0;        // sum of (2la+1)(2lb+1) over the kept shell pairs
+  int64_t kept_pairs = 0;       // shell pairs that keep at least one primitive pair
+  int64_t kept_prim_pairs = 0;  // primitive pairs that survive screening
+  double screen = 0.0;
+  int32_t precision = SHGO_PREC_FP64;
+  int class_cand[shgo_sched::kNumClasses] = {0};  // candidate pairs per class (bounds the sorted counts)
+  int32_t def_tiles[shgo_sched::kNumClasses] = {0};  // default tiles per work item of each class
+  int32_t grad_occ[shgo_sched::kNumClasses] = {0};    // resident workgroups per CU of each class's gradient kernel
+  // the one device workspace every array below is carved from (plan_host.h: plan_layout); owned
+  // by the plan unless it lives in the library's static scratch array
+  void* block = nullptr;
+  size_t block_bytes = 0;
+  bool owns_block = true;
+  shgo_impl::DevBasis bs{};
+  shgo_impl::DevPairs pr{};
+  shgo_impl::Nuc* nuc = nullptr;
+  // persistent-kernel workspace
+  shgo_impl::ClassMeta meta{};
+  int32_t* queue = nullptr;     // head of the persistent kernel's work queue
+  int32_t* item_off = nullptr;  // [0]: number of work items
+  int32_t* items = nullptr;     // work items, longest first (capacity: one tile per item)
+  shgo_impl::WorkArgs* d_wa = nullptr;  // the integral kernel's arguments, in device memory
+  double* d_energy = nullptr;  // gradient: E when the caller does not ask for it
+  // captured graph of one evaluation (shgo_execute_graph) and its output buffer
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double* graph_out = nullptr;
+  hipStream_t cap_stream = nullptr;
+  // phase timing (off when slots == 0): events [slot][phase][start, end]
+  int32_t slots = 0;
+  int64_t exec_count = 0;
+  std::vector<hipEvent_t> events;
+};
+
+namespace shgo_impl {
+
+// ---------------------------------------------------------------------------------------------
+// Launch functions (each defined in the translation unit of its kernels)
+// ---------------------------------------------------------------------------------------------
+// shgo_pairs.hip
+void launch_pair_build(const shgo_plan* p, hipStream_t st);
+void launch_fill(double* ptr, int64_t n, hipStream_t st);
+hipError_t launch_boys(int mmax, int64_t n, const double* T, double* F, const double* tab, hipStream_t st);
+// shgo_integrals.hip
+void launch_integrals(const shgo_plan* p, double* out, hipStream_t st);
+hipError_t integrals_setup(int device, int* per_cu, std::string* why);
+// shgo_overlap.hip
+void launch_overlap(const shgo_plan* p, double* out, hipStream_t st);
+// shgo_grad.hip: validate (launch = false: LDS limits, occupancy) or launch every class present
+shgo_status grad_classes(shgo_plan* p, const GradArgs& ga, hipStream_t st, bool launch);
+
+// host helpers of shgo_api.hip
+shgo_status fail(shgo_context* ctx, shgo_status s, const std::string& msg);
+
+}  // namespace shgo_impl

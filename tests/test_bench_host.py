@@ -65,3 +65,25 @@ def test_traffic_figure_follows_the_kernel_sources(tmp_path, monkeypatch):
     assert bench.traffic_from_profile(tag) is None
     (prof / f"traffic_{tag}.txt").write_text(f"# a comment: 1\nsource_hash: {current}\nhbm_bytes_per_launch: 123\n")
     assert bench.traffic_from_profile(tag) == 123.0
+
+
+def test_batched_flop_model_counts_the_kept_primitive_pairs():
+    # the headline's algorithmic flops use the primitive pairs that survive screening; their number
+    # is the library's own host count
+    import paper_2404_16245_amd as shgo
+    b, n = synth.batched_molecule(seed=3)
+    pa, pb = synth.all_pairs(b.n_shells)
+    kept = bench.surviving_prim_pairs(b, pa, pb, 1e-12)
+    st, _, info = shgo.shgo_check_call(b, n, shgo.options(screen=1e-12))
+    assert st == 0 and int(kept.sum()) == info["kept_prim_pairs"] and int((kept > 0).sum()) == info["kept_pairs"]
+    per_class, total = bench.workload_flops(b, n, pa, pb, 1e-12)
+    assert total == per_class.sum() > 0 and np.count_nonzero(per_class) == 15
+
+
+def test_cpu_baseline_sample_is_stratified():
+    # a small molecule: the sample takes the same fraction of every class's kept pairs
+    b, n = synth.molecule(seed=11, n_atoms=8, box=12.0, ls=(0, 1, 2), kmax=3)
+    pa, pb = synth.all_pairs(b.n_shells)
+    v, desc, dt = bench.cpu_baseline(b, n, pa, pb, 1e-12, 0.05, 1)
+    assert v > 0 and dt > 0 and "6 (la,lb) classes" in desc and "1 OpenMP thread" in desc
+    assert bench.cpu_model()

@@ -3,6 +3,7 @@ contracted molecules, against the oracle."""
 import numpy as np
 import pytest
 
+import helpers
 import oracle
 from paper_2404_16245_amd import synth
 
@@ -116,27 +117,40 @@ def test_autotune_keeps_results(shgo, molecule):
     assert_parity(out.cpu().numpy(), ref, "after tuning, graph")
 
 
-def test_batched_workload_sampled(shgo):
-    """The batched workload at full size (200 atoms, l <= 4, K <= 8, screened): every element of
-    a sample of shell pairs against the oracle, and exact symmetry."""
+def test_batched_workload_stratified(shgo):
+    """The batched workload at full size (200 atoms, l <= 4, K <= 8, screened 1e-12) in the bench's
+    launch configuration (autotuned schedule, graph replay): every pair that keeps 48 or more
+    primitive pairs (the longest work items), 40 kept pairs of each (la, lb) class and 40 fully
+    screened ones against the oracle, element by element; exact symmetry; zero blocks where
+    nothing survives."""
     import torch
     b, n = synth.batched_molecule(seed=3)
-    plan, out = _plan(shgo, b, n, 1e-12)
+    screen = 1e-12
+    plan, out = _plan(shgo, b, n, screen)
     shgo.shgo_plan_autotune(plan, out, rounds=1)
+    out.fill_(float("nan"))
     shgo.shgo_execute_graph(plan, out)
     torch.cuda.synchronize()
     nbf = b.nbf()
     V = out.cpu().numpy().reshape(nbf, nbf)
+    assert not np.isnan(V).any()
     assert np.array_equal(V, V.T)
-    rng = np.random.default_rng(3)
     pa, pb = synth.all_pairs(b.n_shells)
-    # half the sample from pairs on nearby atoms (large blocks), half uniform
-    d = np.linalg.norm(b.center[pa] - b.center[pb], axis=1)
-    near = np.nonzero(d < 3.0)[0]
-    sel = np.concatenate([rng.choice(near, 40, replace=False), rng.choice(len(pa), 40, replace=False)])
-    ref = oracle.split_blocks(oracle.nuc_blocks(b, n, pa[sel], pb[sel], screen=1e-12), b, pa[sel], pb[sel])
+    ns = helpers.surviving_prim_pairs(b, pa, pb, screen)
+    rng = np.random.default_rng(3)
+    hi, lo = np.maximum(b.l[pa], b.l[pb]), np.minimum(b.l[pa], b.l[pb])
+    sel = [np.nonzero(ns >= 48)[0]]
+    for la in range(5):
+        for lb in range(la + 1):
+            cls = np.nonzero((hi == la) & (lo == lb) & (ns > 0))[0]
+            sel.append(rng.choice(cls, min(40, len(cls)), replace=False))
+    zero = rng.choice(np.nonzero(ns == 0)[0], 40, replace=False)
+    sel = np.unique(np.concatenate(sel))
+    assert len(sel) > 1400
+    ref = oracle.split_blocks(oracle.nuc_blocks(b, n, pa[sel], pb[sel], screen=screen), b, pa[sel], pb[sel])
     off = b.shell_offsets()
-    for i, k in enumerate(sel):
-        a, c = pa[k], pb[k]
-        blk = V[off[a]:off[a] + 2 * b.l[a] + 1, off[c]:off[c] + 2 * b.l[c] + 1]
-        assert_parity(blk, ref[i], f"pair ({a}, {c})")
+    blk = lambda a, c: V[off[a]:off[a] + 2 * b.l[a] + 1, off[c]:off[c] + 2 * b.l[c] + 1]  # noqa: E731
+    got = np.concatenate([blk(pa[k], pb[k]).ravel() for k in sel])
+    assert_parity(got, np.concatenate([r.ravel() for r in ref]), f"{len(sel)} stratified pairs")
+    for k in zero:
+        assert np.all(blk(pa[k], pb[k]) == 0.0)

@@ -79,3 +79,33 @@ def test_pair_list_in_any_order(shgo):
     flip = rng.random(len(pa)) < 0.5
     pa[flip], pb[flip] = pb[flip].copy(), pa[flip].copy()
     assert_parity(shgo.overlap_pairs(b, pa, pb).cpu().numpy(), oracle.overlap_blocks(b, pa, pb), "pair list")
+
+
+# Wavefronts whose 64 lanes (or, in the last one, all active lanes) hold pairs of a single class
+# store through LDS; the tests below make most wavefronts single-class.
+@pytest.mark.parametrize("ls,n_atoms", [((1,), 15), ((2,), 20), ((0, 3), 16)])
+def test_single_class_wavefronts_matrix(shgo, ls, n_atoms):
+    # (1,): 120 pairs of class (1,1): one full wavefront and one with 56 active lanes;
+    # (2,): 210 pairs of (2,2); (0, 3): classes of 136, 256 and 136 pairs, some wavefronts
+    # straddling a class boundary (lane-by-lane stores) beside single-class ones
+    b, _ = synth.molecule(seed=29 + n_atoms, n_atoms=n_atoms, box=6.0, ls=ls, kmax=3)
+    S = shgo.overlap(b).cpu().numpy()
+    pa, pb = synth.all_pairs(b.n_shells)
+    assert_parity(S, matrix_from_blocks(b, pa, pb, oracle.overlap_blocks(b, pa, pb)), f"ls {ls}")
+    assert np.array_equal(S, S.T)
+
+
+def test_single_class_wavefronts_pair_list(shgo):
+    # 140 pairs of class (3,2), about half listed as (d, f): two full single-class wavefronts and a
+    # last one with 12 active lanes, each storing both orientations of the listed blocks
+    b, _ = synth.molecule(seed=37, n_atoms=12, box=6.0, ls=(3, 2), kmax=2)
+    f = np.nonzero(b.l == 3)[0]
+    d = np.nonzero(b.l == 2)[0]
+    rng = np.random.default_rng(37)
+    pa = rng.choice(f, 140)
+    pb = rng.choice(d, 140)
+    flip = rng.random(140) < 0.5
+    pa[flip], pb[flip] = pb[flip].copy(), pa[flip].copy()
+    assert 50 < flip.sum() < 90
+    got = shgo.overlap_pairs(b, pa, pb).cpu().numpy()
+    assert_parity(got, oracle.overlap_blocks(b, pa, pb), "140 (3,2) pairs, half swapped")

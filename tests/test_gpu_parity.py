@@ -36,12 +36,18 @@ def shgo():
 
 
 def test_boys_device_against_oracle(shgo):
+    # shgo_boys runs the evaluation the integral and gradient kernels run (clamped table row,
+    # Taylor series below t = 72, leading asymptotic term above, downward recursion), for every
+    # order those kernels instantiate; the oracle's __float128 Boys function is the reference
     import torch
-    T = np.concatenate([[0.0, 1e-14, 1e-8, 1e-3], np.linspace(0.01, 29.99, 700), [29.999999, 30.0, 30.000001],
-                        np.linspace(30.5, 120.0, 200), [500.0, 1e4, 6.4e4]])
-    F = shgo.shgo_boys(shgo.context(0), torch.tensor(T, device="cuda"), 13).cpu().numpy()
+    T = np.concatenate([[0.0, 1e-14, 1e-8, 1e-3], np.linspace(0.01, 29.99, 300), [29.999999, 30.0, 30.000001],
+                        np.linspace(30.5, 71.8, 120), np.linspace(71.9, 72.1, 41), [72.0 - 1e-12, 72.0 + 1e-12],
+                        np.linspace(72.2, 300.0, 80), [500.0, 1e3, 1e4, 6.4e4]])
     ref = np.array([oracle.boys(13, t, precision=2) for t in T])
-    assert_parity(F, ref, rtol=5e-15 * 4, atol=0.0, what="Boys")
+    Tt = torch.tensor(T, device="cuda")
+    for mmax in range(14):
+        F = shgo.shgo_boys(shgo.context(0), Tt, mmax).cpu().numpy()
+        assert_parity(F, ref[:, :mmax + 1], rtol=2e-14, atol=0.0, what=f"Boys F_0..F_{mmax}")
 
 
 def test_small_molecule_matrix(shgo):
@@ -132,15 +138,16 @@ def test_long_contractions_saturate_the_pair_key(shgo):
         assert_parity(V, oracle.nuc_matrix(b, n, screen=screen), what=f"K up to 20, screen {screen}")
 
 
-def test_full_sweep_sampled(shgo):
-    # the full high-l sweep (49 classes x 2041 pairs, 64 nuclei), checked on sampled blocks
+def test_full_sweep_every_block(shgo):
+    # the full high-l sweep (49 classes x 2041 pairs, 64 nuclei) in the bench's launch
+    # configuration (autotuned schedule, graph replay): every block against the oracle
+    import torch
     hb, hn, pa, pb = synth.high_l_sweep(seed=2)
-    got = shgo.nuclear_attraction_pairs(hb, hn, pa, pb).cpu().numpy()
-    sizes = oracle.block_sizes(hb, pa, pb)
-    offs = np.concatenate([[0], np.cumsum(sizes)])
-    rng = np.random.default_rng(99)
-    sample = np.unique(np.concatenate([rng.choice(len(pa), 120, replace=False), [0, len(pa) - 1]]))
-    ref = oracle.nuc_blocks(hb, hn, pa[sample], pb[sample])
-    got_s = np.concatenate([got[offs[i]:offs[i + 1]] for i in sample])
-    assert_parity(got_s, ref, what="sampled full sweep")
-    assert np.all(np.isfinite(got))
+    plan = shgo.shgo_plan_pairs(shgo.context(0), hb, hn, pa, pb)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
+    shgo.shgo_plan_autotune(plan, out, rounds=1)
+    out.fill_(float("nan"))
+    shgo.shgo_execute_graph(plan, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert_parity(got, oracle.nuc_blocks(hb, hn, pa, pb), what="full sweep, 100009 blocks")

@@ -104,3 +104,75 @@ def test_binding_constants_match_the_header():
         assert getattr(shgo, name) == int(defines[name]), name
     codes = dict(re.findall(r"(SHGO_(?:OK|ERR_[A-Z_]+))\s*=\s*(\d+)", text))
     assert codes and all(getattr(shgo, k) == int(v) for k, v in codes.items())
+
+
+# ----------------------------------------------------------------------------------------------
+# single-call entry points: host-side checks (no GPU)
+# ----------------------------------------------------------------------------------------------
+def _independent_screen_count(b, screen):
+    """Shell pairs a <= b keeping a primitive pair with exp(-ab/(a+b)|A-B|^2) > screen, and their
+    integrals, by a numpy mask written here (independent of the library's host code)."""
+    n = b.n_shells
+    kept_pairs = integrals = 0
+    for a in range(n):
+        c = np.arange(a, n)
+        R2 = np.sum((b.center[c] - b.center[a]) ** 2, axis=1)
+        ea = b.expo[b.prim_off[a]:b.prim_off[a] + b.nprim[a]]
+        keep = np.zeros(len(c), bool)
+        for j, s in enumerate(c):
+            eb = b.expo[b.prim_off[s]:b.prim_off[s] + b.nprim[s]]
+            mu = ea[:, None] * eb[None, :] / (ea[:, None] + eb[None, :])
+            keep[j] = bool(np.any(np.exp(-mu * R2[j]) > screen))
+        kept_pairs += int(keep.sum())
+        integrals += int(np.sum((2 * b.l[a] + 1) * (2 * b.l[c[keep]] + 1)))
+    return kept_pairs, integrals
+
+
+def test_check_call_counts_the_screened_pairs():
+    # the 200-atom molecule (l <= 4, K 1..8) screened at 1e-12: integrals count only the shell pairs
+    # that keep a primitive pair
+    b, n = synth.batched_molecule(seed=3)
+    st, msg, info = shgo.shgo_check_call(b, n, shgo.options(screen=1e-12))
+    assert st == shgo.SHGO_OK and msg == ""
+    assert info["candidate_pairs"] == 1000 * 1001 // 2 and info["nbf"] == 5000
+    assert (info["kept_pairs"], info["integrals"]) == (309418, 7649172)
+    assert (info["kept_pairs"], info["integrals"]) == _independent_screen_count(b, 1e-12)
+    # without screening every pair counts
+    st, _, info0 = shgo.shgo_check_call(b, n, shgo.options(screen=0.0))
+    assert info0["kept_pairs"] == info0["candidate_pairs"]
+    assert info0["integrals"] == (5000 * 5000 + int(np.sum((2 * b.l + 1) ** 2))) // 2
+
+
+def test_check_call_rejects_bad_options_before_device_work():
+    b, n = _basis()
+    assert shgo.shgo_check_call(b, n)[0] == shgo.SHGO_OK
+    assert shgo.shgo_check_call(b, n, shgo.options(precision=7))[0] == shgo.SHGO_ERR_INVALID_ARG
+    assert shgo.shgo_check_call(b, n, shgo.options(screen=-1.0))[0] == shgo.SHGO_ERR_INVALID_ARG
+    assert shgo.shgo_check_call(b, n, shgo.options(screen=float("inf")))[0] == shgo.SHGO_ERR_INVALID_ARG
+    b.l[1] = 9
+    assert shgo.shgo_check_call(b, n)[0] == shgo.SHGO_ERR_UNSUPPORTED_L
+
+
+def test_check_call_forced_out_of_memory():
+    # a scratch limit below the call's device workspace gives SHGO_ERR_OUT_OF_MEMORY with no
+    # device involved; at exactly the workspace the call is accepted
+    b, n = _basis()
+    st, _, info = shgo.shgo_check_call(b, n)
+    ws = info["workspace_bytes"]
+    assert st == shgo.SHGO_OK and ws > 0 and ws % 256 == 0
+    st, msg, _ = shgo.shgo_check_call(b, n, shgo.options(scratch_limit_bytes=ws - 1))
+    assert st == shgo.SHGO_ERR_OUT_OF_MEMORY and "scratch limit" in msg
+    assert shgo.shgo_check_call(b, n, shgo.options(scratch_limit_bytes=ws))[0] == shgo.SHGO_OK
+    assert shgo.shgo_check_call(b, n, shgo.options(scratch_limit_bytes=1))[0] == shgo.SHGO_ERR_OUT_OF_MEMORY
+
+
+def test_single_call_without_gpu_fails_cleanly():
+    # the single call needs a context, and a context needs a device
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = shgo.load_library()
+    hb, hn = shgo._HostBasis(_basis()[0]), shgo._HostNuclei(_basis()[1])
+    import ctypes
+    assert lib.shgo_nuclear_attraction(None, ctypes.byref(hb.struct), ctypes.byref(hn.struct), None, None,
+                                       None) == shgo.SHGO_ERR_INVALID_ARG

@@ -215,3 +215,59 @@ def test_double_oracle_rounding_error():
     Bq = oracle.nuc_blocks(hb, hn, pa, pb, precision=2)
     assert np.all(np.abs(B - Bq) <= 1e-14 + 1e-12 * np.abs(Bq))
     assert np.abs(B - Bq).max() <= 1e-14 * np.abs(Bq).max()
+
+
+def _screen_mask(basis, sa, sb, screen):
+    """Primitive pairs of shells sa, sb kept by exp(-mu |A-B|^2) > screen, mu = ab/(a+b): a numpy
+    mask written here, independent of the oracle."""
+    ea = basis.expo[basis.prim_off[sa]:basis.prim_off[sa] + basis.nprim[sa]]
+    eb = basis.expo[basis.prim_off[sb]:basis.prim_off[sb] + basis.nprim[sb]]
+    R2 = float(np.sum((basis.center[sa] - basis.center[sb]) ** 2))
+    mu = ea[:, None] * eb[None, :] / (ea[:, None] + eb[None, :])
+    return np.exp(-mu * R2) > screen
+
+
+@pytest.mark.parametrize("screen", [1e-8, 1e-4])
+def test_screening_rule_against_masked_mcmurchie_davidson(screen):
+    # thresholds that drop some but not all primitive pairs of many shell pairs: the oracle's
+    # screened blocks equal the Cartesian McMurchie-Davidson route summed over exactly the primitive
+    # pairs an independent mask keeps (mu = ab/(a+b), strict >); the unscreened blocks differ
+    bs, nuc = synth.molecule(seed=23, n_atoms=4, box=8.0, ls=(0, 1, 2), kmax=4)
+    pa, pb = synth.all_pairs(bs.n_shells)
+    got = oracle.split_blocks(oracle.nuc_blocks(bs, nuc, pa, pb, screen=screen), bs, pa, pb)
+    full = oracle.split_blocks(oracle.nuc_blocks(bs, nuc, pa, pb), bs, pa, pb)
+    partial = dropped = decisive = 0
+    for k, (a, b) in enumerate(zip(pa, pb)):
+        keep = _screen_mask(bs, a, b, screen)
+        if keep.all():
+            assert np.array_equal(got[k], full[k])
+            continue
+        if not keep.any():
+            dropped += 1
+            assert np.all(got[k] == 0.0)
+            continue
+        partial += 1
+        ref = xcheck.contracted_block(xcheck.md_nuclear_prim, bs, nuc, a, b, keep=keep)
+        assert np.allclose(got[k], ref, rtol=1e-10, atol=1e-12), (a, b)
+        # blocks where the dropped primitive pairs weigh far above the tolerance decide the rule
+        decisive += not np.allclose(got[k], full[k], rtol=1e-8, atol=1e-10)
+    assert partial >= 5 and dropped >= 1 and decisive >= 3, (partial, dropped, decisive)
+
+
+def test_screening_threshold_is_strict():
+    # a primitive pair exactly at the threshold (exp(-mu R^2) == screen) is dropped, one just below
+    # it is kept: two s shells with one primitive each
+    A, B = np.array([0.0, 0.0, 0.0]), np.array([0.0, 0.3, 1.1])
+    a, b = 0.7, 1.9
+    bs = synth.Basis(np.array([A, B]), np.array([0, 0], np.int32), np.array([1, 1], np.int32),
+                     np.array([0, 1], np.int64), np.array([a, b]), np.array([1.0, 1.0]))
+    nuc = synth.Nuclei(np.array([[0.2, 0.1, 0.4]]), np.array([2.0]))
+    at = float(np.exp(-(a * b / (a + b)) * float(np.sum((A - B) ** 2))))
+    on = oracle.nuc_blocks(bs, nuc, [0], [1], screen=at)
+    below = oracle.nuc_blocks(bs, nuc, [0], [1], screen=np.nextafter(at, 0.0))
+    assert on[0] == 0.0
+    assert below[0] != 0.0 and below[0] == oracle.nuc_blocks(bs, nuc, [0], [1])[0]
+    # the threshold is on mu = ab/(a+b), not on p = a+b: at exp(-p R^2) < screen < exp(-mu R^2) the
+    # pair is kept
+    mid = float(np.sqrt(at * np.exp(-(a + b) * float(np.sum((A - B) ** 2)))))
+    assert oracle.nuc_blocks(bs, nuc, [0], [1], screen=mid)[0] != 0.0

@@ -268,8 +268,9 @@ def md_nuclear_prim(la, A, a, lb, B, b, c):
     return real_solid_poly(la) @ Vc @ real_solid_poly(lb).T
 
 
-def contracted_block(route, basis, nuclei, sa, sb):
-    """Real V block for shells sa, sb using route ``md_nuclear_prim`` or ``quad_nuclear_prim``."""
+def contracted_block(route, basis, nuclei, sa, sb, keep=None):
+    """Real V block for shells sa, sb using route ``md_nuclear_prim`` or ``quad_nuclear_prim``;
+    ``keep`` (K_a x K_b booleans, or None for all) selects the primitive pairs that enter."""
     la, lb = int(basis.l[sa]), int(basis.l[sb])
     A, B = basis.center[sa], basis.center[sb]
     ea = basis.expo[basis.prim_off[sa]:basis.prim_off[sa] + basis.nprim[sa]]
@@ -281,6 +282,8 @@ def contracted_block(route, basis, nuclei, sa, sb):
     out = np.zeros((2 * la + 1, 2 * lb + 1))
     for i, a in enumerate(ea):
         for j, b in enumerate(eb):
+            if keep is not None and not keep[i, j]:
+                continue
             for c, Z in zip(nuclei.pos, nuclei.Z):
                 out -= Z * wa[i] * wb[j] * route(la, A, a, lb, B, b, c)
     return out
