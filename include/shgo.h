@@ -85,10 +85,10 @@ typedef struct {
   int32_t precision;          /* shgo_precision */
   double screen_threshold;    /* drop primitive pairs with exp(-ab/(a+b)|A-B|^2) <= it; 0 keeps all */
   int32_t use_graph;          /* nonzero: replay the evaluation as a captured HIP graph (V only) */
-  const char* autotune_cache; /* NULL, or the path of a schedule file: read if it exists (a file
-                                 that is not a schedule: SHGO_ERR_INVALID_ARG before any device
-                                 work), else a new plan is autotuned once and the file written
-                                 (V only) */
+  const char* autotune_cache; /* NULL, or the path of a schedule file for the call's plan: read
+                                 if it exists (a file that is not a schedule: SHGO_ERR_INVALID_ARG
+                                 before any device work), else the plan is autotuned and the file
+                                 written; done once per plan and path (V only) */
   size_t scratch_limit_bytes; /* 0: no limit; else SHGO_ERR_OUT_OF_MEMORY, before any device work,
                                  when the call's device workspace would exceed it */
 } shgo_options;
@@ -259,6 +259,15 @@ shgo_status shgo_plan_set_schedule(shgo_plan* plan, const float* weight, const i
 #define SHGO_TUNE_CANDIDATES 5
 shgo_status shgo_plan_autotune(shgo_plan* plan, double* out, int32_t rounds, void* stream, double* ms,
                                int32_t* chosen);
+
+/* Per-item profile of the persistent launch: runs one execution of the plan (written to `out`)
+ * with each work item timed on the device wall clock, synchronizes `stream`, and returns the
+ * number of items in *n_items and, for the first max_items of them in dispatch order, the item
+ * (class << 24 | tile block), its start relative to the first item's (microseconds) and its
+ * duration (microseconds). Allocates a timing buffer. Shows how far the longest items set the
+ * kernel's length. */
+shgo_status shgo_plan_item_profile(shgo_plan* plan, double* out, int32_t max_items, int32_t* items, double* start_us,
+                                   double* duration_us, int32_t* n_items, void* stream);
 
 /* Phase timing. With n_slots > 0, every later shgo_execute records HIP events at the bounds of
  * its two phases -- 0: pair build (normalisation, enumeration, screening, class sort, work

@@ -32,7 +32,8 @@ EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_erro
             "shgo_execute_overlap",
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
             "shgo_plan_autotune", "shgo_max_tiles", "shgo_options_default", "shgo_check_call",
-            "shgo_nuclear_attraction", "shgo_nuclear_attraction_grad", "shgo_plan_get_info", "shgo_plan_set_precision"]
+            "shgo_nuclear_attraction", "shgo_nuclear_attraction_grad", "shgo_plan_get_info", "shgo_plan_set_precision",
+            "shgo_plan_item_profile"]
 SHGO_NUM_CLASSES = 28
 SHGO_TUNE_CANDIDATES = 5
 SHGO_NUM_PHASES = 2
@@ -136,6 +137,8 @@ def load_library(path=LIB_PATH):
     lib.shgo_nuclear_attraction_grad.argtypes = [vp, ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei),
                                                  ctypes.POINTER(_Options), vp, vp, vp, vp]
     lib.shgo_nuclear_attraction_grad.restype = ctypes.c_int
+    lib.shgo_plan_item_profile.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.shgo_plan_item_profile.restype = ctypes.c_int
     lib.shgo_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
     lib.shgo_plan_get_info.restype = ctypes.c_int
     lib.shgo_plan_set_precision.argtypes = [vp, i32]
@@ -290,10 +293,10 @@ def shgo_nuclear_attraction(ctx, basis, nuclei, opts, V, stream=None):
     """The single call: V (float64 device tensor, nbf x nbf) from the host basis and nuclei."""
     lib = load_library()
     hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
-    nbf = int(np.sum(2 * hb.l + 1))
+    nbf = int(lib.shgo_nbf(ctypes.byref(hb.struct)))  # -1 for an l out of range: the call refuses it
     _check(lib, ctx, lib.shgo_nuclear_attraction(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct),
                                                  None if opts is None else ctypes.byref(opts),
-                                                 _f64_device(V, "V", nbf * nbf), _stream_handle(stream)))
+                                                 _f64_device(V, "V", max(nbf, 0) ** 2), _stream_handle(stream)))
     return V
 
 
@@ -301,7 +304,7 @@ def shgo_nuclear_attraction_grad(ctx, basis, nuclei, opts, D, dE_dnuclei, dE_dce
     """The single call of the gradient of E = sum D V (float64 device tensors)."""
     lib = load_library()
     hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
-    nbf = int(np.sum(2 * hb.l + 1))
+    nbf = max(int(lib.shgo_nbf(ctypes.byref(hb.struct))), 0)
     _check(lib, ctx, lib.shgo_nuclear_attraction_grad(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct),
                                                       None if opts is None else ctypes.byref(opts),
                                                       _f64_device(D, "D", nbf * nbf),
@@ -417,6 +420,23 @@ def shgo_execute_grad(plan, D, dE_dnuclei, dE_dcenters, energy=None, stream=None
                                                 _f64_device(dE_dnuclei, "dE_dnuclei", 0),
                                                 _f64_device(dE_dcenters, "dE_dcenters", 0), e,
                                                 _stream_handle(stream)))
+
+
+def shgo_plan_item_profile(plan, out, stream=None):
+    """One profiled execution: (items [n] int32 (class << 24 | block), start [n] us, duration [n] us)
+    in dispatch order. Synchronizes."""
+    lib = load_library()
+    n = np.zeros(1, dtype=np.int32)
+    _check(lib, plan.ctx, lib.shgo_plan_item_profile(plan.handle, _f64_device(out, "out", plan.output_size), 0, None,
+                                                     None, None, n.ctypes.data, _stream_handle(stream)))
+    m = int(n[0])
+    items = np.zeros(max(m, 1), dtype=np.int32)
+    start = np.zeros(max(m, 1))
+    dur = np.zeros(max(m, 1))
+    _check(lib, plan.ctx, lib.shgo_plan_item_profile(plan.handle, _f64_device(out, "out", plan.output_size), m,
+                                                     items.ctypes.data, start.ctypes.data, dur.ctypes.data,
+                                                     n.ctypes.data, _stream_handle(stream)))
+    return items[:m], start[:m], dur[:m]
 
 
 def shgo_plan_set_timing(plan, n_slots):

@@ -72,7 +72,7 @@ hipError_t upload_args(shgo_plan* p, unsigned long long* item_ns) {
 }
 
 // Work items of the queue for the plan's candidate counts (an upper bound of the device count).
-int64_t max_items(const shgo_plan* p) {
+int64_t max_items_of(const shgo_plan* p) {
   int64_t n = 0;
   for (int c = 0; c < kNumClasses; ++c) n += class_items(p->class_cand[c], p->meta.tiles[c]);
   return n;
@@ -510,11 +510,11 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
   model_weights(p->n_nuc, p->meta.weight);
   for (int c = 0; c < kNumClasses; ++c) p->meta.tiles[c] = p->def_tiles[c];
   const ClassMeta model = p->meta;
-  const int64_t nmax = max_items(p);
+  const int64_t nmax = max_items_of(p);
   unsigned long long* ticks = nullptr;
-  if (hipMalloc(&ticks, sizeof(unsigned long long) * (size_t)std::max<int64_t>(nmax, 1)) != hipSuccess)
+  if (hipMalloc(&ticks, 2 * sizeof(unsigned long long) * (size_t)std::max<int64_t>(nmax, 1)) != hipSuccess)
     return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "tuning buffer");
-  std::vector<unsigned long long> th((size_t)std::max<int64_t>(nmax, 1));
+  std::vector<unsigned long long> th(2 * (size_t)std::max<int64_t>(nmax, 1));
   std::vector<int32_t> it((size_t)std::max<int64_t>(nmax, 1)), koff(kNumKeys + 1);
   int32_t n_items = 0;
   hipError_t e = upload_args(p, ticks);
@@ -525,7 +525,7 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
   if (e == hipSuccess) e = hipMemcpy(&n_items, p->item_off, sizeof(int32_t), hipMemcpyDeviceToHost);
   if (e == hipSuccess && (n_items < 0 || n_items > nmax)) e = hipErrorUnknown;
   if (e == hipSuccess && n_items > 0) {
-    e = hipMemcpy(th.data(), ticks, sizeof(unsigned long long) * (size_t)n_items, hipMemcpyDeviceToHost);
+    e = hipMemcpy(th.data(), ticks, 2 * sizeof(unsigned long long) * (size_t)n_items, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(it.data(), p->items, sizeof(int32_t) * (size_t)n_items, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(koff.data(), p->pr.key_off, sizeof(int32_t) * koff.size(), hipMemcpyDeviceToHost);
   }
@@ -542,7 +542,7 @@ shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* 
     const ItemGeom g = item_geom(koff.data(), c, model.tiles[c], blk);
     const int m = item_iters(koff.data(), c, g);
     const int tasks = item_tasks(g.nt, kClassGroups[c], m);
-    sum_ns[c] += 10.0 * (double)th[(size_t)q];
+    sum_ns[c] += 10.0 * (double)th[2 * (size_t)q + 1];
     units[c] += (double)m * g.nt / std::min(kWaves, tasks);
   }
   // measured weights, scaled like the model's (largest 1024); classes without items keep theirs
@@ -819,7 +819,7 @@ shgo_status shgo_nuclear_attraction(shgo_context* ctx, const shgo_basis* basis, 
   if (s != SHGO_OK) return s;
   s = shgo_plan_set_precision(p, o.precision);
   if (s != SHGO_OK) return s;
-  if (fresh && o.autotune_cache && p->n_cand > 0) {
+  if (o.autotune_cache && p->n_cand > 0 && p->schedule_file != o.autotune_cache) {
     if (r > 0) {
       s = shgo_plan_set_schedule(p, w, t);
       if (s != SHGO_OK) return s;
@@ -829,6 +829,7 @@ shgo_status shgo_nuclear_attraction(shgo_context* ctx, const shgo_basis* basis, 
       if (!write_schedule(o.autotune_cache, p->meta.weight, p->meta.tiles))
         return fail(ctx, SHGO_ERR_INVALID_ARG, std::string("cannot write the autotune cache ") + o.autotune_cache);
     }
+    p->schedule_file = o.autotune_cache;
   }
   return o.use_graph ? shgo_execute_graph(p, V, stream) : shgo_execute(p, V, stream);
 }
@@ -846,6 +847,49 @@ shgo_status shgo_nuclear_attraction_grad(shgo_context* ctx, const shgo_basis* ba
   const shgo_status s = call_plan(ctx, basis, nuclei, o, &p, &fresh);
   if (s != SHGO_OK) return s;
   return shgo_execute_grad(p, D, dE_dnuclei, dE_dcenters, nullptr, stream);
+}
+
+shgo_status shgo_plan_item_profile(shgo_plan* p, double* out, int32_t max_items, int32_t* items, double* start_us,
+                                   double* duration_us, int32_t* n_items, void* stream) {
+  if (!p || !n_items || max_items < 0 || (max_items > 0 && (!items || !start_us || !duration_us)))
+    return SHGO_ERR_INVALID_ARG;
+  shgo_context* ctx = p->ctx;
+  if (!out && p->out_size > 0) return fail(ctx, SHGO_ERR_INVALID_ARG, "null output");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+  *n_items = 0;
+  if (p->n_cand == 0) return SHGO_OK;
+  hipStream_t st = (hipStream_t)stream;
+  drop_graph(p);
+  const int64_t nmax = std::max<int64_t>(max_items_of(p), 1);
+  unsigned long long* ticks = nullptr;
+  if (hipMalloc(&ticks, 2 * sizeof(unsigned long long) * (size_t)nmax) != hipSuccess)
+    return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "profiling buffer");
+  int32_t n = 0;
+  std::vector<unsigned long long> th(2 * (size_t)nmax);
+  std::vector<int32_t> it((size_t)nmax);
+  hipError_t e = upload_args(p, ticks);
+  if (e == hipSuccess) {
+    enqueue(p, out, st, false);
+    e = hipStreamSynchronize(st);
+  }
+  if (e == hipSuccess) e = hipMemcpy(&n, p->item_off, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && (n < 0 || n > nmax)) e = hipErrorUnknown;
+  if (e == hipSuccess && n > 0) {
+    e = hipMemcpy(th.data(), ticks, 2 * sizeof(unsigned long long) * (size_t)n, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(it.data(), p->items, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost);
+  }
+  (void)hipFree(ticks);
+  const hipError_t e2 = upload_args(p, nullptr);
+  if (e != hipSuccess || e2 != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "profiling run failed");
+  unsigned long long t0 = ~0ull;
+  for (int q = 0; q < n; ++q) t0 = std::min(t0, th[2 * (size_t)q]);
+  *n_items = n;
+  for (int q = 0; q < std::min(n, max_items); ++q) {
+    items[q] = it[(size_t)q];
+    start_us[q] = 0.01 * (double)(th[2 * (size_t)q] - t0);  // wall clock: 100 MHz
+    duration_us[q] = 0.01 * (double)th[2 * (size_t)q + 1];
+  }
+  return SHGO_OK;
 }
 
 shgo_status shgo_plan_get_info(const shgo_plan* p, shgo_plan_info* info) {

@@ -348,10 +348,13 @@ k_integrals(const WorkArgs* __restrict__ wa_ptr, double* __restrict__ out) {
     const int q = s_item;
     if (q >= total) break;
     const int item = wa->items[q];
-    unsigned long long* const tick = wa->item_ns;
+    unsigned long long* const tick = wa->item_ns;  // [item][start, duration] in wall-clock ticks
     const unsigned long long t0 = tick ? wall_clock64() : 0ull;
     dispatch_class<0, 0>(item >> 24, item & 0xffffff, wa_ptr, out, &s_task, &s_item);
-    if (tick && threadIdx.x == 0) tick[q] = wall_clock64() - t0;
+    if (tick && threadIdx.x == 0) {
+      tick[2 * q] = t0;
+      tick[2 * q + 1] = wall_clock64() - t0;
+    }
     __syncthreads();
   }
 }

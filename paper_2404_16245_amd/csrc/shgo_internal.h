@@ -108,7 +108,7 @@ struct WorkArgs {
   int32_t* __restrict__ queue;     // [0]: next work item
   int32_t* __restrict__ item_off;  // [0]: number of work items
   int32_t* __restrict__ items;     // work items, longest first: class << 24 | tile block
-  unsigned long long* __restrict__ item_ns;  // per-item durations (10 ns ticks) when tuning, else null
+  unsigned long long* __restrict__ item_ns;  // per item: start and duration (10 ns ticks) when profiling, else null
   ClassMeta meta;
 };
 // The work arguments live in device memory (one copy per plan) and are read through the scalar
@@ -343,6 +343,8 @@ struct shgo_plan {
   hipGraphExec_t gexec = nullptr;
   double* graph_out = nullptr;
   hipStream_t cap_stream = nullptr;
+  // the autotune-cache file the schedule was last read from or written to (single calls)
+  std::string schedule_file;
   // phase timing (off when slots == 0): events [slot][phase][start, end]
   int32_t slots = 0;
   int64_t exec_count = 0;
