@@ -137,6 +137,24 @@ shgo_status shgo_nuclear_attraction_grad(shgo_context* ctx, const shgo_basis* ba
                                          const shgo_options* options, const double* D, double* dE_dnuclei,
                                          double* dE_dcenters, void* stream);
 
+/* The single call of shgo_nuclear_attraction without any device allocation, for callers that
+ * cannot allocate (work under HIP graph capture setup, tight serving loops, harnesses that forbid
+ * hipMalloc). Its whole workspace -- device copies of the inputs, keys, sorted pairs, work queue and
+ * kernel arguments, plan_host layout -- lives in one static device array of
+ * SHGO_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; it calls no hipMalloc, hipFree
+ * or allocating library routine. It copies the inputs on `stream` and waits for that stream before
+ * launching (so the host arrays may go when it returns); V is then written asynchronously.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race, and must be ordered by the caller.
+ * options: FP64 only, use_graph = 0, autotune_cache = NULL (SHGO_ERR_INVALID_ARG otherwise); the
+ * default schedule; scratch_limit_bytes, when nonzero, caps the workspace further.
+ * SHGO_ERR_OUT_OF_MEMORY, before any device work, when the workspace (shgo_check_call's
+ * workspace_bytes) exceeds the array (about 800,000 candidate shell pairs). Other errors as for
+ * shgo_nuclear_attraction. */
+#define SHGO_NOALLOC_SCRATCH_BYTES (32u << 20)
+shgo_status shgo_nuclear_attraction_noalloc(shgo_context* ctx, const shgo_basis* basis, const shgo_nuclei* nuclei,
+                                            const shgo_options* options, double* V, void* stream);
+
 /* Plan for the full symmetric matrix V (nbf x nbf, row-major) over every shell pair a <= b.
  * screen > 0 drops primitive pairs with exp(-ab/(a+b) |A-B|^2) <= screen (0 keeps all; a pair
  * whose primitive pairs are all dropped gives a zero block).  Validates the inputs, copies them

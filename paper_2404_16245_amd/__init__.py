@@ -33,12 +33,13 @@ EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_erro
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
             "shgo_plan_autotune", "shgo_max_tiles", "shgo_options_default", "shgo_check_call",
             "shgo_nuclear_attraction", "shgo_nuclear_attraction_grad", "shgo_plan_get_info", "shgo_plan_set_precision",
-            "shgo_plan_item_profile"]
+            "shgo_nuclear_attraction_noalloc", "shgo_plan_item_profile"]
 SHGO_NUM_CLASSES = 28
 SHGO_TUNE_CANDIDATES = 5
 SHGO_NUM_PHASES = 2
 SHGO_PREC_FP64 = 0
 SHGO_PREC_MIXED = 1
+SHGO_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class ShgoError(RuntimeError):
@@ -137,6 +138,9 @@ def load_library(path=LIB_PATH):
     lib.shgo_nuclear_attraction_grad.argtypes = [vp, ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei),
                                                  ctypes.POINTER(_Options), vp, vp, vp, vp]
     lib.shgo_nuclear_attraction_grad.restype = ctypes.c_int
+    lib.shgo_nuclear_attraction_noalloc.argtypes = [vp, ctypes.POINTER(_Basis), ctypes.POINTER(_Nuclei),
+                                                    ctypes.POINTER(_Options), vp, vp]
+    lib.shgo_nuclear_attraction_noalloc.restype = ctypes.c_int
     lib.shgo_plan_item_profile.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
     lib.shgo_plan_item_profile.restype = ctypes.c_int
     lib.shgo_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
@@ -297,6 +301,18 @@ def shgo_nuclear_attraction(ctx, basis, nuclei, opts, V, stream=None):
     _check(lib, ctx, lib.shgo_nuclear_attraction(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct),
                                                  None if opts is None else ctypes.byref(opts),
                                                  _f64_device(V, "V", max(nbf, 0) ** 2), _stream_handle(stream)))
+    return V
+
+
+def shgo_nuclear_attraction_noalloc(ctx, basis, nuclei, opts, V, stream=None):
+    """The allocation-free single call: V (float64 device tensor, nbf x nbf), workspace in the
+    library's static scratch array."""
+    lib = load_library()
+    hb, hn = _HostBasis(basis), _HostNuclei(nuclei)
+    nbf = int(lib.shgo_nbf(ctypes.byref(hb.struct)))
+    _check(lib, ctx, lib.shgo_nuclear_attraction_noalloc(ctx, ctypes.byref(hb.struct), ctypes.byref(hn.struct),
+                                                         None if opts is None else ctypes.byref(opts),
+                                                         _f64_device(V, "V", max(nbf, 0) ** 2), _stream_handle(stream)))
     return V
 
 

@@ -7,7 +7,35 @@
 
 #include "plan_host.h"
 
+#include <mutex>
+
 namespace shgo_impl {
+
+// Workspace of shgo_nuclear_attraction_noalloc: a file-scope device array, one copy per GPU, held
+// until the process ends. In host code its name stands for nothing on the device: kernels and
+// copies use the address hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr size_t kScratchBytes = SHGO_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {nullptr};
+
+// The device address of `scratch` on `device` (current), looked up once per device.
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
+}  // namespace
 
 shgo_status fail(shgo_context* ctx, shgo_status s, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -377,6 +405,11 @@ shgo_status shgo_create(int device, shgo_context** out) {
   }
   c->n_cu = n_cu;
   c->grid = std::max(1, n_cu * std::max(1, per_cu));
+  if (scratch_address(device, &c->scratch) != hipSuccess) {
+    std::fprintf(stderr, "shgo_create: hipGetSymbolAddress of the scratch array failed\n");
+    shgo_destroy(c);
+    return SHGO_ERR_DEVICE;
+  }
   *out = c;
   return SHGO_OK;
 }
@@ -889,6 +922,47 @@ shgo_status shgo_plan_item_profile(shgo_plan* p, double* out, int32_t max_items,
     start_us[q] = 0.01 * (double)(th[2 * (size_t)q] - t0);  // wall clock: 100 MHz
     duration_us[q] = 0.01 * (double)th[2 * (size_t)q + 1];
   }
+  return SHGO_OK;
+}
+
+shgo_status shgo_nuclear_attraction_noalloc(shgo_context* ctx, const shgo_basis* basis, const shgo_nuclei* nuclei,
+                                            const shgo_options* options, double* V, void* stream) {
+  if (!ctx) return SHGO_ERR_INVALID_ARG;
+  shgo_options o;
+  shgo_options_default(&o);
+  if (options) o = *options;
+  if (!basis || !nuclei) return fail(ctx, SHGO_ERR_INVALID_ARG, "null basis or nuclei");
+  std::string msg;
+  shgo_status st = shgo_host::validate_options(&o, &msg);
+  if (st != SHGO_OK) return fail(ctx, st, msg);
+  if (o.precision != SHGO_PREC_FP64 || o.use_graph || o.autotune_cache)
+    return fail(ctx, SHGO_ERR_INVALID_ARG, "the allocation-free call takes FP64, no graph and no autotune cache");
+  if (!V && shgo_nbf(basis) > 0) return fail(ctx, SHGO_ERR_INVALID_ARG, "null output");
+  if (!ctx->scratch) return fail(ctx, SHGO_ERR_DEVICE, "no scratch address for this device");
+  const size_t limit = o.scratch_limit_bytes > 0 ? std::min(o.scratch_limit_bytes, kScratchBytes) : kScratchBytes;
+  // the plan lives on the stack and its workspace in the static scratch: nothing is allocated
+  shgo_plan p;
+  shgo_host::PlanCounts pc;
+  shgo_host::PlanLayout lay;
+  st = plan_host_part(ctx, basis, nuclei, 1, 0, nullptr, nullptr, o.screen_threshold, limit, &p, &pc, &lay);
+  if (st != SHGO_OK) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+  if (p.n_cand == 0) return SHGO_OK;
+  p.owns_block = false;
+  p.block = ctx->scratch;
+  p.block_bytes = lay.total;
+  carve(&p, lay, (char*)ctx->scratch, 1);
+  hipStream_t st_ = (hipStream_t)stream;
+  // inputs, cleared key counters and the kernel's arguments into the scratch on the caller's
+  // stream; the wait lets the host arrays go once the call returns
+  hipError_t e = upload_inputs(&p, basis, nuclei, pc, nullptr, nullptr, st_);
+  const WorkArgs wa{p.bs, p.pr, p.nuc, p.n_nuc, ctx->boys_tab, p.queue, p.item_off, p.items, nullptr, p.meta};
+  if (e == hipSuccess) e = hipMemcpyAsync(p.d_wa, &wa, sizeof(WorkArgs), hipMemcpyHostToDevice, st_);
+  if (e == hipSuccess) e = hipStreamSynchronize(st_);
+  if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("upload failed: ") + hipGetErrorString(e));
+  enqueue(&p, V, st_, false);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
   return SHGO_OK;
 }
 

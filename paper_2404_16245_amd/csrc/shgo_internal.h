@@ -308,6 +308,8 @@ struct shgo_context {
   // from: a repeated call with the same inputs reuses it (device copies, tuned schedule, graph)
   shgo_plan* call_plan = nullptr;
   std::vector<char> call_key;
+  // this device's address of the library's static scratch array (shgo_nuclear_attraction_noalloc)
+  void* scratch = nullptr;
 };
 
 struct shgo_plan {
