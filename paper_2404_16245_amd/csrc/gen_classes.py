@@ -570,9 +570,23 @@ def emit_group(LA, LB, gi, group):
         o.append("    }")
     o.append("  }")
     # ---- scaling by pre * 2 pi k!/p^{k+1} and the harmonic normalisation c_L ----
+    # The constants of scale() and couple() are read from the group's table in memory rather than
+    # written as literals: thousands of 64-bit literals would be materialised in scalar registers,
+    # overflow them and be spilled to vector-register lanes.
+    table = []
+    slot = {}
+
+    def tab(v):
+        v = float(v)
+        if v not in slot:
+            slot[v] = len(table)
+            table.append(v)
+        return slot[v]
+
     o.append(f"  static __device__ __forceinline__ void scale(double (&W)[NW], const double (&fk)[{LB + 1}]) {{")
+    o.append(f"    const CTab C = launder_table(kTab{LA}{LB}_{gi});")
     for (L, M, k), i in idx.items():
-        o.append(f"    W[{i}] *= fk[{k}] * {lit(monic_c(L, abs(M)))};")
+        o.append(f"    W[{i}] *= fk[{k}] * C[{tab(monic_c(L, abs(M)))}];")
     o.append("  }")
     # ---- coupling ----
     # Outputs are visited in blocks of equal (|ma|, |mb|): inside a block the sign variants
@@ -586,6 +600,7 @@ def emit_group(LA, LB, gi, group):
     o.append(f"  static __device__ __forceinline__ void couple(const double (&W)[NW], const double (&ta)[{LA + 1}],")
     o.append(f"                                                 const double (&tb)[{LB + 1}], double* __restrict__ Vp) {{")
     o.append("    // Vp: this lane's entry (0, 0) of the tile accumulator; entries are SHGO_ACC_STRIDE apart")
+    o.append(f"    const CTab C = launder_table(kTab{LA}{LB}_{gi});")
     for (aa, ab), ts in sorted(blocks.items()):
         outs = sorted(set((t[0], t[1]) for t in ts))
         name = {mm: f"v{i}" for i, mm in enumerate(outs)}
@@ -604,11 +619,13 @@ def emit_group(LA, LB, gi, group):
                     mm = (t[0], t[1])
                     e = f"e{name[mm][1:]}"
                     wi = idx[(t[4], t[5], t[6])]
+                    c = t[7]
+                    cref = f"C[{tab(abs(c))}]" if c > 0 else f"-C[{tab(abs(c))}]"
                     if first[mm]:
-                        lines.append(f"double {e} = {lit(t[7])} * W[{wi}];")
+                        lines.append(f"double {e} = {cref} * W[{wi}];")
                         first[mm] = False
                     else:
-                        lines.append(f"{e} = fma({lit(t[7])}, W[{wi}], {e});")
+                        lines.append(f"{e} = fma({cref}, W[{wi}], {e});")
                 o.append("        { " + " ".join(lines))
                 for mm in o2:
                     k = name[mm][1:]
@@ -629,7 +646,9 @@ def emit_group(LA, LB, gi, group):
         o.append("    }")
     o.append("  }")
     o.append("};")
-    return "\n".join(o)
+    head = [f"// constants of the scale and coupling of group {gi} of class ({LA}, {LB})",
+            f"__device__ const double kTab{LA}{LB}_{gi}[{len(table)}] = {{{', '.join(lit(v) for v in table)}}};"]
+    return "\n".join(head + o)
 
 
 def emit_rotation(l):
@@ -865,6 +884,16 @@ def emit_header(cap=None, lmax=LMAX_SHELL):
            f"// Group register budget: {cap if cap is not None else 'per class (class_cap)'} doubles.",
            "#pragma once",
            "",
+           "// A group's constant table, read through the scalar data cache. The address passes through an",
+           "// empty asm statement at every use, so that the loads stay at the use instead of being hoisted",
+           "// out of the primitive-pair loop into scalar registers.",
+           "typedef const __attribute__((address_space(4))) double* CTab;",
+           "static __device__ __forceinline__ CTab launder_table(const double* p) {",
+           "  const uint64_t v = (uint64_t)p;",
+           "  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));",
+           "  asm volatile(\"\" : \"+s\"(lo), \"+s\"(hi));",
+           "  return (CTab)(((uint64_t)hi << 32) | lo);",
+           "}",
            "template <int LA, int LB> struct ClassInfo;",
            "template <int LA, int LB, int G> struct GroupOf;"]
     for LA in range(lmax + 1):

@@ -38,7 +38,7 @@ constexpr int kFrameDoubles = 4 * kTile;                         // cos/sin of t
 constexpr int kLdsBytes = 163840;
 constexpr int kStaticLdsReserve = 256;
 constexpr int kLdsDoubles = (kLdsBytes - kStaticLdsReserve) / 8;
-constexpr int kSliceIters = 8;                                   // primitive-pair iterations per slice
+constexpr int kSliceIters = 2;                                   // primitive-pair iterations per slice
 constexpr int kCostBuckets = 128;                                // 4 per octave of the item estimate
 
 SHGO_HD constexpr int imin(int a, int b) { return a < b ? a : b; }
@@ -141,19 +141,21 @@ SHGO_HD float item_cost(float weight, int m, int nt, int tasks) {
 }
 
 // Decode a task index of an item with nt tiles of per-tile iteration counts iters[t] and Q
-// groups: tasks are tile-major, then slice, then group. Returns false once the index lies past
-// the item's last task; else the tile t, the group g and the iteration range [it0, it1).
+// groups: tasks are tile-major from the item's last tile to its first (a class's pairs ascend in
+// surviving primitive pairs, so the longest tasks are handed out first and the short ones fill the
+// end), then slice, then group (groups are generated heaviest first). Returns false once the index
+// lies past the item's last task; else the tile t, the group g and the iteration range [it0, it1).
 SHGO_HD bool decode_task(int task, int Q, int nt, const int* iters, int& t, int& g, int& it0, int& it1) {
   int u = task / Q;
   g = task - u * Q;
   int m = 0;
-  for (t = 0; t < nt; ++t) {
+  for (t = nt - 1; t >= 0; --t) {
     m = iters[t];
     const int s = slices_of(m);
     if (u < s) break;
     u -= s;
   }
-  if (t >= nt) return false;
+  if (t < 0) return false;
   it0 = u * kSliceIters;
   it1 = imin(m, it0 + kSliceIters);
   return true;
