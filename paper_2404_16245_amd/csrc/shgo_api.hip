@@ -44,20 +44,34 @@ shgo_status fail(shgo_context* ctx, shgo_status s, const std::string& msg) {
 
 namespace {
 
-// Boys table F_m(i/16), m < kBoysOrders, by the convergent series in long double (positive terms).
+// Boys table (rows of kBoysRow doubles, order M major): F_{M+k}(t_i)/k! for k < 8, e^{-t_i} as a
+// high and a low double, with
+// F_m(t) = e^{-t} sum_j (2t)^j / ((2m+1)(2m+3)...(2m+2j+1)) summed in long double (positive terms).
 std::vector<double> boys_table() {
-  std::vector<double> tab((size_t)kBoysPoints * kBoysOrders);
+  constexpr int kOrders = kBoysMaxM + 8;
+  std::vector<double> tab((size_t)(kBoysMaxM + 1) * kBoysPoints * kBoysRow, 0.0);
+  std::vector<long double> F(kOrders);
   for (int i = 0; i < kBoysPoints; ++i) {
     const long double t = (long double)i / 16.0L;
     const long double et = expl(-t);
-    for (int m = 0; m < kBoysOrders; ++m) {
+    for (int m = 0; m < kOrders; ++m) {
       long double term = 1.0L / (2 * m + 1), sum = term;
       for (int k = 1; k < 4000; ++k) {
         term *= 2.0L * t / (2 * m + 2 * k + 1);
         sum += term;
         if (term < 1e-22L * sum) break;
       }
-      tab[(size_t)i * kBoysOrders + m] = (double)(et * sum);
+      F[m] = et * sum;
+    }
+    for (int M = 0; M <= kBoysMaxM; ++M) {
+      double* row = &tab[((size_t)M * kBoysPoints + i) * kBoysRow];
+      long double fact = 1.0L;
+      for (int k = 0; k < 8; ++k) {
+        if (k > 0) fact *= k;
+        row[k] = (double)(F[M + k] / fact);
+      }
+      row[8] = (double)et;
+      row[9] = (double)(et - (long double)row[8]);
     }
   }
   return tab;

@@ -199,19 +199,17 @@ k_grad(GradArgs ga) {
           const double z = qz[0] * cx + qz[1] * cy + qz[2] * cz;
           const double r2 = fma(cx, cx, fma(cy, cy, cz * cz));
           const double T = p * r2;
-          static_assert(LM + 1 + 7 < kBoysOrders, "the Taylor row must lie inside the table");
-          // Boys F_0..F_{LM+1} without a divergent branch, as in the integral kernel: the Taylor
-          // row of the nearest grid point (index clamped to the table), or the asymptote above
-          // kBoysTcut, selected per lane
-          double row[8];
+          // Boys F_0..F_{LM+1} without a divergent branch, as in the integral kernel: the row of the
+          // nearest grid point (index clamped to the table), or the asymptote above kBoysTcut,
+          // selected per lane
+          double row[kBoysRowLoad];
           {
-            const int i = (int)(fmin(T, kBoysTcut) * 16.0 + 0.5);  // 0 .. kBoysPoints - 1
-            const double* __restrict__ r = ga.boys_tab + i * kBoysOrders + LM + 1;
+            const double* __restrict__ r = boys_row_ptr(ga.boys_tab, LM + 1, boys_index(T));
 #pragma unroll
-            for (int k = 0; k < 8; ++k) row[k] = r[k];
+            for (int k = 0; k < kBoysRowLoad; ++k) row[k] = r[k];
           }
           double F[LM + 2];
-          boys_row<LM + 1>(T, exp_neg(T), row, F);
+          boys_row<LM + 1>(T, row, F);
           double tj[LB + 1];
           tj[0] = 1.0;
 #pragma unroll

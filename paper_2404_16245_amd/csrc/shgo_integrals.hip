@@ -58,8 +58,8 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int it_be
       double W[Grp::NW];
 #pragma unroll
       for (int q = 0; q < Grp::NW; ++q) W[q] = 0.0;
-      // nucleus loop: geometry in the pair frame, Boys row from LDS, then the group's step
-      double nx = 0.0, ny = 0.0, nz = 0.0, nr2 = 0.0, nt = 0.0, nZ = 0.0, nrow[8];
+      // nucleus loop: geometry in the pair frame, the Boys row of the nucleus's T, then the group's step
+      double nx = 0.0, ny = 0.0, nz = 0.0, nr2 = 0.0, nt = 0.0, nZ = 0.0, nrow[kBoysRowLoad];
       const NucPtr nucs = uniform_nuclei(wa->nuc);
       const int c_lo = __builtin_amdgcn_readfirstlane(c_begin), n_nuc = __builtin_amdgcn_readfirstlane(c_end);
       auto geometry = [&](int c) {
@@ -71,15 +71,14 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int it_be
         nr2 = fma(cx, cx, fma(cy, cy, cz * cz));
         nt = p * nr2;
         nZ = nucs[c].Z;
-        const int i = (int)(fmin(nt, kBoysTcut) * 16.0 + 0.5);  // 0 .. kBoysPoints - 1
-        const double* __restrict__ r = wa->boys_tab + i * kBoysOrders + LM;
+        const double* __restrict__ r = boys_row_ptr(wa->boys_tab, LM, boys_index(nt));  // index 0 .. kBoysPoints - 1
 #pragma unroll
-        for (int k = 0; k < 8; ++k) nrow[k] = r[k];
+        for (int k = 0; k < kBoysRowLoad; ++k) nrow[k] = r[k];
       };
-      auto nucleus = [&](double x, double y, double z, double r2, double t, double Zc, const double (&row)[8]) {
-        const double e = exp_neg(t);
+      auto nucleus = [&](double x, double y, double z, double r2, double t, double Zc,
+                         const double (&row)[kBoysRowLoad]) {
         double F[LM + 1];
-        boys_row<LM>(t, e, row, F);
+        boys_row<LM>(t, row, F);
         double tj[LB + 1];
         tj[0] = 1.0;
 #pragma unroll
@@ -91,9 +90,9 @@ __device__ __forceinline__ void run_group(const PairState& ps, WAP wa, int it_be
         if (c_lo < n_nuc) geometry(c_lo);
         for (int c = c_lo; c < n_nuc; ++c) {
           const double x = nx, y = ny, z = nz, r2 = nr2, t = nt, Zc = nZ;
-          double row[8];
+          double row[kBoysRowLoad];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) row[k] = nrow[k];
+          for (int k = 0; k < kBoysRowLoad; ++k) row[k] = nrow[k];
           if (c + 1 < n_nuc) geometry(c + 1);
           nucleus(x, y, z, r2, t, Zc, row);
         }

@@ -39,8 +39,12 @@ using namespace shgo_sched;
 // ---------------------------------------------------------------------------------------------
 // Constants and device data layout
 // ---------------------------------------------------------------------------------------------
-constexpr int kBoysOrders = 22;    // F_0..F_21 stored per grid point (mmax <= 14 with 8 Taylor terms)
+// Boys table: one row per (order M, grid point t_i = i/16) holding the Taylor coefficients of F_M
+// about t_i, F_{M+k}(t_i)/k! for k < 8, then e^{-t_i} as the sum of two doubles (high, low part).
+constexpr int kBoysMaxM = 13;      // highest order a kernel evaluates (l_a + l_b + 1 for the gradient)
 constexpr int kBoysPoints = 1153;  // grid t_i = i/16, i = 0..1152
+constexpr int kBoysRow = 10;       // doubles per row
+constexpr int kBoysRowLoad = 10;   // doubles a kernel reads of a row
 constexpr double kBoysTcut = 72.0; // below: table; above: asymptotic form (e^{-t} < 6e-32)
 constexpr int kPrefetchMaxW = 32;  // groups up to this many W doubles prefetch the next nucleus
 constexpr int kClassifyThreads = 1024;
@@ -208,24 +212,43 @@ __host__ __device__ constexpr double half_gamma_half(int M) {
 // is the table's Taylor series below kBoysTcut and the leading asymptotic term
 // Gamma(M+1/2) / (2 t^{M+1/2}) above it (the neglected part is below e^{-t}/t, 1e-17 relative for
 // M <= 12 at t = 72), selected per lane; then the downward recursion, stable for every t.
+// Grid index of t (clamped to the table) and the first double of its row of order M.
+__device__ __forceinline__ int boys_index(double t) { return (int)(fmin(t, kBoysTcut) * 16.0 + 0.5); }
+__device__ __forceinline__ const double* boys_row_ptr(const double* tab, int M, int i) {
+  return tab + ((size_t)M * kBoysPoints + i) * kBoysRow;
+}
+
+// F_0..F_M(t) from the row of order M at the grid point t_i nearest t (the clamped index of
+// boys_index) and no divergent branch. Below kBoysTcut: the Taylor series of F_M about t_i,
+// F_M(t_i + h) = sum_k F_{M+k}(t_i) (-h)^k / k!, |h| <= 1/32 (the row holds the coefficients with
+// their 1/k!), and e^{-t} = e^{-t_i} e^{-h} with e^{-h} by its Taylor polynomial of degree 7 (the
+// remainder is below 3e-17) and e^{-t_i} carried in two parts (about one rounding in all). Above: the leading asymptotic term Gamma(M+1/2) / (2 t^{M+1/2}) (the
+// neglected part is below e^{-t}/t, 1e-17 relative for M <= 13 at t = 72) and e^{-t} taken as 0.
+// The two are selected per lane; then the downward recursion F_m = (2t F_{m+1} + e^{-t})/(2m+1),
+// stable for every t.
 template <int M>
-__device__ __forceinline__ void boys_row(double t, double e, const double (&row)[8], double (&F)[M + 1]) {
-  const int i = (int)(fmin(t, kBoysTcut) * 16.0 + 0.5);
-  const double d = -(t - 0.0625 * (double)i);
+__device__ __forceinline__ void boys_row(double t, const double (&row)[kBoysRowLoad], double (&F)[M + 1]) {
+  static_assert(M <= kBoysMaxM, "order beyond the table");
+  const int i = boys_index(t);
+  const double d = 0.0625 * (double)i - t;  // t_i - t = -h
   double f = row[7];
-  f = fma(f, d * (1.0 / 7.0), row[6]);
-  f = fma(f, d * (1.0 / 6.0), row[5]);
-  f = fma(f, d * (1.0 / 5.0), row[4]);
-  f = fma(f, d * (1.0 / 4.0), row[3]);
-  f = fma(f, d * (1.0 / 3.0), row[2]);
-  f = fma(f, d * (1.0 / 2.0), row[1]);
-  f = fma(f, d, row[0]);
+#pragma unroll
+  for (int k = 6; k >= 0; --k) f = fma(f, d, row[k]);
+  double q = add_vs(mul_vs(d, 1.9841269841269841270e-04), 1.3888888888888888889e-03);  // 1/7!, 1/6!
+  q = fma_vvs(q, d, 8.3333333333333333333e-03);  // 1/5!
+  q = fma_vvs(q, d, 4.1666666666666666667e-02);  // 1/4!
+  q = fma_vvs(q, d, 1.6666666666666666667e-01);  // 1/3!
+  q = fma(q, d, 0.5);
+  q = fma(q, d, 1.0);
+  q = fma(q, d, 1.0);
   // 1/sqrt(t) from the hardware estimate and two Newton steps (each doubles the bits)
   double rs = __builtin_amdgcn_rsq(t);
   rs = rs * fma(-0.5 * t * rs, rs, 1.5);
   rs = rs * fma(-0.5 * t * rs, rs, 1.5);
   const double fa = half_gamma_half(M) * rs * pow_n<M>(rs * rs);
-  F[M] = t < kBoysTcut ? f : fa;
+  const bool tab_ok = t < kBoysTcut;
+  F[M] = tab_ok ? f : fa;
+  const double e = tab_ok ? fma(row[8], q, row[9] * q) : 0.0;
   const double t2 = 2.0 * t;
 #pragma unroll
   for (int m = M - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));

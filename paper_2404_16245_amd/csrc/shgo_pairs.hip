@@ -240,21 +240,20 @@ __global__ void k_scatter(DevBasis bs, DevPairs pr) {
   }
 }
 
-// Boys function F_0..F_M(t) exactly as the integral and gradient kernels evaluate it: the Taylor
-// row of the nearest grid point with the index clamped to the table, e^{-t}, then boys_row.
+// Boys function F_0..F_M(t) exactly as the integral and gradient kernels evaluate it: the row of
+// order M at the nearest grid point, the index clamped to the table, then boys_row.
 template <int M>
 __global__ void k_boys(int64_t n, const double* __restrict__ T, double* __restrict__ F,
                        const double* __restrict__ tab) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double t = T[i];
-  const int g = (int)(fmin(t, kBoysTcut) * 16.0 + 0.5);  // 0 .. kBoysPoints - 1
-  const double* __restrict__ r = tab + g * kBoysOrders + M;
-  double row[8];
+  const double* __restrict__ r = boys_row_ptr(tab, M, boys_index(t));  // index 0 .. kBoysPoints - 1
+  double row[kBoysRowLoad];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) row[k] = r[k];
+  for (int k = 0; k < kBoysRowLoad; ++k) row[k] = r[k];
   double f[M + 1];
-  boys_row<M>(t, exp_neg(t), row, f);
+  boys_row<M>(t, row, f);
 #pragma unroll
   for (int m = 0; m <= M; ++m) F[i * (M + 1) + m] = f[m];
 }
