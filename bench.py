@@ -224,9 +224,13 @@ def timed_steps(shgo, torch, plan, out, steps, warmup):
     return total_ms / steps, phase_ms / max(nrec, 1)
 
 
+SWEEP_CLASS_COPIES = 8
+
+
 def measure_sweep(shgo, synth, torch, steps):
     """The high-l sweep (49 (la, lb) classes x 2041 uncontracted pairs, 64 nuclei, seed 2): all
-    classes in one autotuned plan, then each (la, lb) class alone in a plan of its own pairs."""
+    classes in one autotuned plan, then each (la, lb) class alone, in a plan of its own pairs listed
+    SWEEP_CLASS_COPIES times (2041 pairs are 32 tiles, too few to occupy 256 compute units)."""
     basis, nuclei, pa, pb = synth.high_l_sweep(seed=2)
     ctx = shgo.context(0)
     plan = shgo.shgo_plan_pairs(ctx, basis, nuclei, pa, pb, 0.0)
@@ -242,13 +246,14 @@ def measure_sweep(shgo, synth, torch, steps):
     gn = _gaunt_nnz()
     for la in range(7):
         for lb in range(7):
-            sel = np.nonzero((basis.l[pa] == la) & (basis.l[pb] == lb))[0]
+            sel = np.tile(np.nonzero((basis.l[pa] == la) & (basis.l[pb] == lb))[0], SWEEP_CLASS_COPIES)
             p1 = shgo.shgo_plan_pairs(ctx, basis, nuclei, pa[sel], pb[sel], 0.0)
             o1 = torch.empty(p1.output_size, dtype=torch.float64, device="cuda")
             ms1, ph1 = timed_steps(shgo, torch, p1, o1, 20, 3)
             nucl, pair = model_flops(max(la, lb), min(la, lb), gn)
             f1 = len(sel) * (nuclei.n * nucl + pair)
-            res["per_class"].append({"la": la, "lb": lb, "pairs": int(len(sel)), "integrals": p1.integrals,
+            res["per_class"].append({"la": la, "lb": lb, "pairs": int(len(sel)), "copies": SWEEP_CLASS_COPIES,
+                                     "integrals": p1.integrals,
                                      "ms_per_step": ms1, "kernel_ms": ph1[1],
                                      "integrals_per_s": p1.integrals / (ms1 * 1e-3),
                                      "kernel_fp64_peak_frac": f1 / (ph1[1] * 1e-3) / FP64_VECTOR_PEAK})
@@ -395,7 +400,8 @@ def main():
         res["overlap"] = measure_overlap(shgo, synth, torch, 5)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
-        threads = os.cpu_count() or 1
+        # the host's share of cores (OMP_NUM_THREADS where the launcher sets it, else at most 16)
+        threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or min(16, os.cpu_count() or 1)
         v, desc_s, _ = cpu_baseline(basis, nuclei, pa, pb, screen, args.cpu_seconds, threads)
         v1, desc_1, _ = cpu_baseline(basis, nuclei, pa, pb, screen, args.cpu_seconds / 2, 1)
         res["cpu_baseline"] = {"value": v, "unit": "integrals/s", "cores": threads, "kind": "oracle",
