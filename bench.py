@@ -22,6 +22,7 @@ thread). Extra blocks: the high-l sweep (49 (l_a, l_b) classes x 2041 uncontract
 class also timed alone), the gradient, and the overlap matrix.
 """
 import argparse
+import re
 import hashlib
 import json
 import os
@@ -70,6 +71,58 @@ def model_flops(la, lb, gaunt_nnz):
     return nucleus, pair
 
 
+def _count_ops(code):
+    """FP64 flops of generated straight-line code: fma = 2, any other binary + - * = 1 (index
+    arithmetic and the adjoint-table pointers excluded)."""
+    n = 0
+    for line in code.splitlines():
+        line = re.sub(r"//.*$", "", line)
+        line = re.sub(r"const double\* w = adj \+ \d+;", "", line)
+        line = re.sub(r"\[[^\]]*\]", "", line)
+        n += 2 * line.count("fma(")
+        prev = None
+        for t in re.findall(r"[A-Za-z_][A-Za-z_0-9.]*|\d+\.\d*(?:e-?\d+)?|\d+|[-+*/=(),;{}<>]", line):
+            if t == "*" or (t in "+-" and prev is not None and (re.match(r"[A-Za-z_0-9.]", prev) or prev == ")")):
+                n += 1
+            prev = t
+    return n
+
+
+def grad_model_flops(la, lb):
+    """(flops per (primitive pair, nucleus), flops per primitive pair) of the adjoint gradient:
+    the generated adjoint nucleus step (solid harmonics and their gradients, G and dG/dT per entry,
+    five products per W entry, eight accumulators) counted from its code, plus the nucleus's frame
+    geometry, Boys F_0..F_{la+lb+1} as in the forward model, the gradient assembly and the three
+    nuclear-gradient adds; per primitive pair the adjoint quadruples (2 products and 1 or 3 FMAs
+    per coupling term of classes (la, lb), (la-1, lb), (la, lb-1), 25 per entry) and 60 for P, K
+    and the shift powers."""
+    sys.path.insert(0, os.path.join(ROOT, "paper_2404_16245_amd", "csrc"))
+    import gen_classes
+    t = gen_classes.emit_grad(la, lb)
+    i = t.index("void step(")
+    body = t[t.index("{", t.index("acc)[8]", i)):t.index("\n  }\n", i)]
+    lm, kmin = la + lb, min(la, lb)
+    nucleus = _count_ops(body) + 3 + 13 + 5 + 1 + (20 + 14 + 3 * (lm + 2)) + 2 * kmin + 14 + 6 + 2 + 18
+    terms = gen_classes.grad_tables(la, lb)
+    pair = 60 + 25 * len(gen_classes.grad_entries(la, lb)) + sum(4 if t[0] == 0 else 8 for t in terms)
+    return nucleus, pair
+
+
+def gradient_flops(basis, nuclei, pa, pb, screen):
+    """Model flops of one gradient evaluation over the kept primitive pairs of every class."""
+    la, lb = basis.l[pa].astype(np.int64), basis.l[pb].astype(np.int64)
+    hi, lo = np.maximum(la, lb), np.minimum(la, lb)
+    npp = surviving_prim_pairs(basis, np.asarray(pa), np.asarray(pb), screen)
+    total = 0.0
+    for a in range(int(hi.max()) + 1):
+        for b in range(a + 1):
+            m = (hi == a) & (lo == b)
+            if m.any():
+                nucl, pair = grad_model_flops(a, b)
+                total += float(npp[m].sum()) * (nuclei.n * nucl + pair)
+    return total
+
+
 def class_id(la, lb):
     a, b = max(la, lb), min(la, lb)
     return a * (a + 1) // 2 + b
@@ -113,8 +166,9 @@ def workload_flops(basis, nuclei, pa, pb, screen=0.0):
 # ----------------------------------------------------------------------------------------------
 # HBM traffic from the committed rocprofv3 counter summary (null when the kernel has changed)
 # ----------------------------------------------------------------------------------------------
-KERNEL_SOURCES = ("paper_2404_16245_amd/csrc/shgo_integrals.hip", "paper_2404_16245_amd/csrc/shgo_internal.h",
-                  "paper_2404_16245_amd/csrc/schedule.h", "paper_2404_16245_amd/csrc/gen_classes.py")
+KERNEL_SOURCES = ("paper_2404_16245_amd/csrc/shgo_integrals.hip", "paper_2404_16245_amd/csrc/shgo_integrals_kernel.h",
+                  "paper_2404_16245_amd/csrc/shgo_internal.h", "paper_2404_16245_amd/csrc/schedule.h",
+                  "paper_2404_16245_amd/csrc/gen_classes.py")
 
 
 def kernel_source_hash():
@@ -224,7 +278,7 @@ def timed_steps(shgo, torch, plan, out, steps, warmup):
     return total_ms / steps, phase_ms / max(nrec, 1)
 
 
-SWEEP_CLASS_COPIES = 8
+SWEEP_CLASS_COPIES = 32
 
 
 def measure_sweep(shgo, synth, torch, steps):
@@ -261,6 +315,34 @@ def measure_sweep(shgo, synth, torch, steps):
     return res
 
 
+def measure_mixed(shgo, synth, torch, steps):
+    """The batched molecule in mixed precision (the coupling in binary32 double-float arithmetic),
+    autotuned like the FP64 line: time per V, and the per-element difference from the FP64 path's
+    V (itself within 1e-11 relative of the oracle; the tests compare the mixed V with the oracle)."""
+    basis, nuclei = synth.batched_molecule(seed=3)
+    ctx = shgo.context(0)
+    plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, 1e-12)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
+    shgo.shgo_execute(plan, out)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    shgo.shgo_plan_set_precision(plan, "mixed")
+    shgo.shgo_plan_autotune(plan, out, rounds=5)
+    ms, ph = timed_steps(shgo, torch, plan, out, steps, 3)
+    err = (out - ref).abs()
+    big = ref.abs() > 1e-10
+    rel = err[big] / ref.abs()[big]
+    large = ref.abs() > 1e-6 * ref.abs().max()
+    rel_large = (err[large] / ref.abs()[large]).max().item()
+    return {"workload": "batched molecule (as the headline), coupling in binary32 double-float arithmetic; "
+                        "Boys, exp(-mu R^2), prefactors, nucleus sums and the contraction in binary64",
+            "integrals_per_step": plan.integrals, "ms_per_step": ms, "integrals_per_s": plan.integrals / (ms * 1e-3),
+            "kernel_ms": ph[1], "pair_build_ms": ph[0],
+            "vs_fp64_path": {"max_abs": err.max().item(), "rms_abs": err.pow(2).mean().sqrt().item(),
+                             "max_rel": rel.max().item(), "rms_rel": rel.pow(2).mean().sqrt().item(),
+                             "rel_floor": 1e-10, "max_rel_above_1e-6_of_max": rel_large}}
+
+
 def measure_overlap(shgo, synth, torch, steps):
     """Overlap matrix S of the batched molecule's basis (nbf 5000, K 1..8), full matrix: the plan's
     pair build and the overlap kernel per step. Bound by writing S (8 nbf^2 bytes)."""
@@ -292,10 +374,13 @@ def measure_gradient(shgo, synth, torch, steps):
     ms_fwd = _time_ms(torch, lambda: shgo.shgo_execute(plan, out), steps, 1)
     total = (dn.sum(0) + dc.sum(0)).abs().max().item()
     scale = max(dn.abs().max().item(), dc.abs().max().item())
+    pa, pb = synth.all_pairs(basis.n_shells)
+    flops = gradient_flops(basis, nuclei, pa, pb, screen)
     return {"workload": "500 atoms, 30-bohr box, l=0..3, K uniform 1..6, screened 1e-12, D iid N(0, 0.1^2) "
                         "symmetric, seed 5", "nbf": basis.nbf(), "nuclei": nuclei.n,
-            "ms_per_gradient": ms_grad, "ms_per_forward": ms_fwd, "energy": e.item(),
-            "translation_sum_rule_rel": total / scale}
+            "ms_per_gradient": ms_grad, "ms_per_forward": ms_fwd, "gradient_over_forward": ms_grad / ms_fwd,
+            "model_flops_per_gradient": flops, "fp64_vector_peak_frac": flops / (ms_grad * 1e-3) / FP64_VECTOR_PEAK,
+            "energy": e.item(), "translation_sum_rule_rel": total / scale}
 
 
 # ----------------------------------------------------------------------------------------------
@@ -394,6 +479,8 @@ def main():
         del out
         log("bench: high-l sweep, all classes and each class alone")
         res["high_l_sweep"] = measure_sweep(shgo, synth, torch, args.steps)
+        log("bench: mixed-precision form")
+        res["mixed_precision"] = measure_mixed(shgo, synth, torch, args.steps)
         log("bench: gradient form")
         res["gradient"] = measure_gradient(shgo, synth, torch, 3)
         log("bench: overlap form")

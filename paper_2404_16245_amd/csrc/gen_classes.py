@@ -36,6 +36,10 @@ import numpy as np
 
 LMAX_SHELL = 6
 DEFAULT_CAP = 64          # register budget of one group, in doubles of W
+# Classes up to this la have a binary32 (double-float) coupling for the mixed-precision kernel;
+# above it the mixed kernel keeps the binary64 coupling (the expanded double-float code of the
+# l = 5, 6 classes, up to 12,000 terms per class, took most of ten minutes to compile).
+MIXED_LMAX = 4
 # Classes whose budget differs. Every group recomputes the nucleus geometry and the Boys row, so
 # fewer groups save work while the nucleus loop stays nearly free of spills: (4, 4) runs in three
 # groups of at most 56 (on the 200-atom batched molecule 5.6% faster than four of 44, and 15% and
@@ -520,6 +524,16 @@ def lit(v):
     return repr(float(v))
 
 
+def flit(v):
+    """A float literal that reads back as exactly the binary32 value v."""
+    v = np.float32(v)
+    t = "%.9g" % float(v)
+    assert np.float32(float(t)) == v
+    if "e" not in t and "." not in t:
+        t += ".0"
+    return t + "f"
+
+
 def emit_group(LA, LB, gi, group):
     LM = LA + LB
     idx = group_index(LA, LB, group)
@@ -648,9 +662,91 @@ def emit_group(LA, LB, gi, group):
             o.append(f"      atomicAdd(Vp + {(mm[0] + LA) * NB + (mm[1] + LB)} * SHGO_ACC_STRIDE, {name[mm]});")
         o.append("    }")
     o.append("  }")
+    # ---- coupling in binary32 with error-free transformations (mixed precision) ----
+    # The same sums as couple(), with W, the shift powers and the coefficients as unevaluated
+    # pairs hi + lo of floats (double-float values) and every product and sum done by the
+    # error-free transformations of shgo_internal.h (TwoProd by fma, TwoSum); the block entry
+    # hi + lo is added to the binary64 accumulator.
+    if LA > MIXED_LMAX:
+        o.append("};")
+        head = [f"// constants of the scale and coupling of group {gi} of class ({LA}, {LB})",
+                f"__device__ const double kTab{LA}{LB}_{gi}[{len(table)}] = {{{', '.join(lit(v) for v in table)}}};"]
+        return "\n".join(head + o)
+    ftable = []
+    fslot = {}
+
+    def ftab(v):
+        v = float(v)
+        if v not in fslot:
+            fslot[v] = len(ftable)
+            ftable.append(v)
+        return fslot[v]
+
+    o.append(f"  static __device__ __forceinline__ void couple_mixed(const double (&W)[NW], const double (&ta)[{LA + 1}],")
+    o.append(f"                                                       const double (&tb)[{LB + 1}], double* __restrict__ Vp) {{")
+    o.append(f"    const CTabF C = launder_table_f(kTabF{LA}{LB}_{gi});")
+    o.append("    df w[NW];")
+    o.append("#pragma unroll")
+    o.append("    for (int i = 0; i < NW; ++i) w[i] = df_split(W[i]);")
+    o.append(f"    df a[{LA + 1}], b[{LB + 1}];")
+    o.append("#pragma unroll")
+    o.append(f"    for (int i = 0; i <= {LA}; ++i) a[i] = df_split(ta[i]);")
+    o.append("#pragma unroll")
+    o.append(f"    for (int i = 0; i <= {LB}; ++i) b[i] = df_split(tb[i]);")
+    for (aa, ab), ts in sorted(blocks.items()):
+        outs = sorted(set((t[0], t[1]) for t in ts))
+        name = {mm: f"v{i}" for i, mm in enumerate(outs)}
+        o.append(f"    {{ // |ma| = {aa}, |mb| = {ab}")
+        o.append("      df " + ", ".join(f"{name[mm]} = df_zero()" for mm in outs) + ";")
+        for l1 in sorted(set(t[2] for t in ts)):
+            t1 = [t for t in ts if t[2] == l1]
+            o1 = sorted(set((t[0], t[1]) for t in t1))
+            o.append("      { df " + ", ".join(f"u{name[mm][1:]} = df_zero()" for mm in o1) + ";")
+            for l2 in sorted(set(t[3] for t in t1)):
+                t2 = [t for t in t1 if t[3] == l2]
+                o2 = sorted(set((t[0], t[1]) for t in t2))
+                first = {mm: True for mm in o2}
+                lines = []
+                for t in sorted(t2, key=lambda t: (abs(t[7]), t[7] < 0, t[0], t[1], t[4], t[5])):
+                    mm = (t[0], t[1])
+                    e = f"e{name[mm][1:]}"
+                    wi = idx[(t[4], t[5], t[6])]
+                    c = t[7]
+                    cref = f"df_coef(C, {ftab(abs(c))}, {'false' if c > 0 else 'true'})"
+                    if first[mm]:
+                        lines.append(f"df {e} = df_mul({cref}, w[{wi}]);")
+                        first[mm] = False
+                    else:
+                        lines.append(f"{e} = df_fma({cref}, w[{wi}], {e});")
+                o.append("        { " + " ".join(lines))
+                for mm in o2:
+                    k = name[mm][1:]
+                    if LB - l2 == 0:
+                        o.append(f"          u{k} = df_add(u{k}, e{k});")
+                    else:
+                        o.append(f"          u{k} = df_fma(b[{LB - l2}], e{k}, u{k});")
+                o.append("        }")
+            for mm in o1:
+                k = name[mm][1:]
+                if LA - l1 == 0:
+                    o.append(f"        {name[mm]} = df_add({name[mm]}, u{k});")
+                else:
+                    o.append(f"        {name[mm]} = df_fma(a[{LA - l1}], u{k}, {name[mm]});")
+            o.append("      }")
+        for mm in outs:
+            o.append(f"      atomicAdd(Vp + {(mm[0] + LA) * NB + (mm[1] + LB)} * SHGO_ACC_STRIDE, df_value({name[mm]}));")
+        o.append("    }")
+    o.append("  }")
     o.append("};")
+    fpairs = []
+    for v in ftable:
+        hi = np.float32(v)
+        lo = np.float32(v - float(hi))
+        fpairs += [flit(hi), flit(lo)]
     head = [f"// constants of the scale and coupling of group {gi} of class ({LA}, {LB})",
-            f"__device__ const double kTab{LA}{LB}_{gi}[{len(table)}] = {{{', '.join(lit(v) for v in table)}}};"]
+            f"__device__ const double kTab{LA}{LB}_{gi}[{len(table)}] = {{{', '.join(lit(v) for v in table)}}};",
+            f"// the coupling coefficients of the same group as float pairs hi, lo (hi + lo = c to 2^-48)",
+            f"__device__ const float kTabF{LA}{LB}_{gi}[{len(fpairs)}] = {{{', '.join(fpairs)}}};"]
     return "\n".join(head + o)
 
 
@@ -877,7 +973,9 @@ def emit_meta(cap=None, lmax=LMAX_SHELL):
     out = ["// Generated by gen_classes.py -- do not edit. Wavefront groups of each (la, lb) class of the",
            "// integral kernel, indexed by la(la+1)/2 + lb.",
            "#pragma once",
-           f"constexpr int kClassGroups[{len(qs)}] = {{{', '.join(map(str, qs))}}};"]
+           f"constexpr int kClassGroups[{len(qs)}] = {{{', '.join(map(str, qs))}}};",
+           "// classes with la up to this have the mixed-precision (double-float) coupling",
+           f"constexpr int kMixedLmax = {MIXED_LMAX};"]
     return "\n".join(out) + "\n"
 
 
@@ -891,11 +989,19 @@ def emit_header(cap=None, lmax=LMAX_SHELL):
            "// empty asm statement at every use, so that the loads stay at the use instead of being hoisted",
            "// out of the primitive-pair loop into scalar registers.",
            "typedef const __attribute__((address_space(4))) double* CTab;",
-           "static __device__ __forceinline__ CTab launder_table(const double* p) {",
+           "typedef const __attribute__((address_space(4))) float* CTabF;",
+           "static __device__ __forceinline__ uint64_t launder_address(const void* p) {",
            "  const uint64_t v = (uint64_t)p;",
            "  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));",
            "  asm volatile(\"\" : \"+s\"(lo), \"+s\"(hi));",
-           "  return (CTab)(((uint64_t)hi << 32) | lo);",
+           "  return ((uint64_t)hi << 32) | lo;",
+           "}",
+           "static __device__ __forceinline__ CTab launder_table(const double* p) { return (CTab)launder_address(p); }",
+           "static __device__ __forceinline__ CTabF launder_table_f(const float* p) { return (CTabF)launder_address(p); }",
+           "// coefficient k of a float-pair table, negated when neg",
+           "static __device__ __forceinline__ df df_coef(CTabF C, int k, bool neg) {",
+           "  const float h = C[2 * k], l = C[2 * k + 1];",
+           "  return neg ? df{-h, -l} : df{h, l};",
            "}",
            "template <int LA, int LB> struct ClassInfo;",
            "template <int LA, int LB, int G> struct GroupOf;"]

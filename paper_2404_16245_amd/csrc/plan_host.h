@@ -203,13 +203,27 @@ inline PlanLayout plan_layout(const PlanCounts& pc, int32_t n_shells, int32_t n_
   return L;
 }
 
-// Default tiles per work item of class c: enough (tile, slice, group) tasks for the eight
-// wavefronts, within LDS. `slices` is the class's mean over its candidate pairs of
-// ceil(K_a K_b / kSliceIters), capped at 8 (screening only lowers it).
+// Default tiles per work item of class c, within LDS: the fewest tiles that give the eight
+// wavefronts eight (tile, slice, group) tasks. `slices` is the class's mean over its candidate
+// pairs of ceil(K_a K_b / kSliceIters), capped at 8 (screening only lowers it). Where every pair
+// has one slice the task counts are exact, and a smaller tile count is taken when it keeps the
+// wavefronts busier over the item's task rounds (tasks / (kWaves * ceil(tasks / kWaves))): three
+// groups take two tiles (six tasks in one round) rather than three (nine tasks, two rounds).
 inline int default_tiles(int c, double slices) {
   const double tasks_per_tile = kClassGroups[c] * std::max(1.0, slices);
-  const int t = (int)std::ceil(8.0 / tasks_per_tile - 1e-9);
-  return std::max(1, std::min(class_max_tiles(c), t));
+  const int t0 = std::max(1, std::min(class_max_tiles(c), (int)std::ceil(8.0 / tasks_per_tile - 1e-9)));
+  if (slices > 1.0) return t0;
+  int best = t0;
+  double best_eff = 0.0;
+  for (int t = t0; t >= 1; --t) {
+    const int tasks = t * kClassGroups[c];
+    const double eff = (double)tasks / (kWaves * ((tasks + kWaves - 1) / kWaves));
+    if (eff > best_eff + 1e-12) {
+      best = t;
+      best_eff = eff;
+    }
+  }
+  return best;
 }
 
 // Mean primitive-pair slices per candidate pair of each class, before screening (the matrix

@@ -120,6 +120,14 @@ int64_t max_items_of(const shgo_plan* p) {
   return n;
 }
 
+// The integral kernel of the plan's precision.
+void launch_integrals(const shgo_plan* p, double* out, hipStream_t st) {
+  if (p->precision == SHGO_PREC_MIXED)
+    launch_integrals_mixed(p, out, st);
+  else
+    launch_integrals_fp64(p, out, st);
+}
+
 // The launches of one evaluation on `st`: pair build (a1), then the persistent integral kernel.
 // With `timed`, HIP events bracket the two phases (never inside a graph capture).
 void enqueue(shgo_plan* p, double* out, hipStream_t st, bool timed) {
@@ -411,7 +419,12 @@ shgo_status shgo_create(int device, shgo_context** out) {
   }
   int n_cu = 0, per_cu = 0;
   std::string why;
-  const hipError_t ge = integrals_setup(device, &per_cu, &why);
+  // both forms of the integral kernel: launch guard, dynamic LDS, workgroups per CU (the same
+  // launch bounds; the grid takes the smaller occupancy)
+  int per_cu_mixed = 0;
+  hipError_t ge = integrals_setup_fp64(&per_cu, &why);
+  if (ge == hipSuccess) ge = integrals_setup_mixed(&per_cu_mixed, &why);
+  per_cu = std::min(per_cu, per_cu_mixed);
   if (ge != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
     if (!why.empty()) std::fprintf(stderr, "shgo_create: %s\n", why.c_str());
     shgo_destroy(c);
@@ -854,7 +867,6 @@ shgo_status shgo_nuclear_attraction(shgo_context* ctx, const shgo_basis* basis, 
   if (options) o = *options;
   if (!basis || !nuclei) return fail(ctx, SHGO_ERR_INVALID_ARG, "null basis or nuclei");
   if (!V && shgo_nbf(basis) > 0) return fail(ctx, SHGO_ERR_INVALID_ARG, "null output");
-  if (o.precision == SHGO_PREC_MIXED) return fail(ctx, SHGO_ERR_INVALID_ARG, "mixed precision is not available");
   // a schedule file is read (or found absent or malformed) before any device work
   float w[kNumClasses];
   int32_t t[kNumClasses];
@@ -994,12 +1006,14 @@ shgo_status shgo_plan_get_info(const shgo_plan* p, shgo_plan_info* info) {
 
 shgo_status shgo_plan_set_precision(shgo_plan* p, int32_t precision) {
   if (!p) return SHGO_ERR_INVALID_ARG;
-  if (precision == SHGO_PREC_FP64) {
+  if (precision != SHGO_PREC_FP64 && precision != SHGO_PREC_MIXED)
+    return fail(p->ctx, SHGO_ERR_INVALID_ARG, "unknown precision");
+  if (precision != p->precision) {
+    if (hipSetDevice(p->ctx->device) != hipSuccess) return fail(p->ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+    drop_graph(p);  // a captured graph holds the other form's kernel
     p->precision = precision;
-    return SHGO_OK;
   }
-  if (precision == SHGO_PREC_MIXED) return fail(p->ctx, SHGO_ERR_INVALID_ARG, "mixed precision is not available");
-  return fail(p->ctx, SHGO_ERR_INVALID_ARG, "unknown precision");
+  return SHGO_OK;
 }
 
 }  // extern "C"

@@ -32,6 +32,55 @@
 static_assert(shgo_sched::kLmax == SHGO_LMAX, "schedule and ABI disagree on the highest l");
 static_assert(shgo_sched::kNumClasses == SHGO_NUM_CLASSES, "schedule and ABI disagree on the class count");
 
+// ---------------------------------------------------------------------------------------------
+// Double-float arithmetic (the mixed-precision coupling)
+// ---------------------------------------------------------------------------------------------
+// A double-float is an unevaluated sum h + l of two binary32 numbers with |l| <= ulp(h) / 2, about
+// 48 significant bits. Products and sums use the error-free transformations: TwoProd (the
+// rounding error of a * b is exactly fma(a, b, -a * b)) and Knuth's TwoSum (the rounding error of
+// a + b from six additions), each followed by a renormalisation (Fast2Sum). Contraction of a
+// product into a later sum is switched off in them, since it would change the rounding the
+// transformations rely on. Global, like the generated class code that uses them.
+struct df {
+  float h, l;
+};
+__device__ __forceinline__ df df_zero() { return df{0.0f, 0.0f}; }
+__device__ __forceinline__ df df_split(double x) {
+  const float h = (float)x;
+  return df{h, (float)(x - (double)h)};
+}
+__device__ __forceinline__ double df_value(df a) { return (double)a.h + (double)a.l; }
+__device__ __forceinline__ df df_renorm(float s, float e) {
+#pragma clang fp contract(off)
+  const float h = s + e;
+  return df{h, e - (h - s)};
+}
+// a * b: TwoProd of the high parts and the first-order cross terms
+__device__ __forceinline__ df df_mul(df a, df b) {
+#pragma clang fp contract(off)
+  const float p = a.h * b.h;
+  const float e = __builtin_fmaf(a.h, b.h, -p) + __builtin_fmaf(a.h, b.l, a.l * b.h);
+  return df_renorm(p, e);
+}
+// a + b: TwoSum of the high parts and the sum of the low parts
+__device__ __forceinline__ df df_add(df a, df b) {
+#pragma clang fp contract(off)
+  const float s = a.h + b.h;
+  const float bb = s - a.h;
+  const float e = ((a.h - (s - bb)) + (b.h - bb)) + (a.l + b.l);
+  return df_renorm(s, e);
+}
+// c + a * b: TwoProd, then TwoSum of the product's high part into c
+__device__ __forceinline__ df df_fma(df a, df b, df c) {
+#pragma clang fp contract(off)
+  const float p = a.h * b.h;
+  const float pe = __builtin_fmaf(a.h, b.h, -p) + __builtin_fmaf(a.h, b.l, a.l * b.h);
+  const float s = c.h + p;
+  const float bb = s - c.h;
+  const float e = ((c.h - (s - bb)) + (p - bb)) + (c.l + pe);
+  return df_renorm(s, e);
+}
+
 namespace shgo_impl {
 
 using namespace shgo_sched;
@@ -385,9 +434,14 @@ namespace shgo_impl {
 void launch_pair_build(const shgo_plan* p, hipStream_t st);
 void launch_fill(double* ptr, int64_t n, hipStream_t st);
 hipError_t launch_boys(int mmax, int64_t n, const double* T, double* F, const double* tab, hipStream_t st);
-// shgo_integrals.hip
+// shgo_integrals.hip and shgo_integrals_mixed.hip: the two forms of the integral kernel; the
+// plan's precision picks one (launch_integrals, shgo_api.hip). The setup checks the kernel's LDS
+// and threads against the launch and gives its workgroups per CU.
+void launch_integrals_fp64(const shgo_plan* p, double* out, hipStream_t st);
+void launch_integrals_mixed(const shgo_plan* p, double* out, hipStream_t st);
+hipError_t integrals_setup_fp64(int* per_cu, std::string* why);
+hipError_t integrals_setup_mixed(int* per_cu, std::string* why);
 void launch_integrals(const shgo_plan* p, double* out, hipStream_t st);
-hipError_t integrals_setup(int device, int* per_cu, std::string* why);
 // shgo_overlap.hip
 void launch_overlap(const shgo_plan* p, double* out, hipStream_t st);
 // shgo_grad.hip: validate (launch = false: LDS limits, occupancy) or launch every class present

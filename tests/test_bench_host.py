@@ -87,3 +87,18 @@ def test_cpu_baseline_sample_is_stratified():
     v, desc, dt = bench.cpu_baseline(b, n, pa, pb, 1e-12, 0.05, 1)
     assert v > 0 and dt > 0 and "6 (la,lb) classes" in desc and "1 OpenMP thread" in desc
     assert bench.cpu_model()
+
+
+def test_gradient_model_counts_the_generated_step():
+    # fma = 2 flops, other binary + - * = 1; indices, unary minus and comments are not counted
+    assert bench._count_ops("a = fma(b, c, a); d = -e[3] * f[2 + 1]; g = h + i - j;  // x - y") == 2 + 1 + 2
+    n00, p00 = bench.grad_model_flops(0, 0)
+    # (0,0): one W entry, five FMAs on it, eight accumulator FMAs and the product -t^0 F_1 = 27,
+    # plus the per-nucleus geometry, Boys (orders 0..1), assembly and nuclear-gradient terms
+    assert n00 == 27 + 3 + 13 + 5 + 1 + (20 + 14 + 3 * 2) + 0 + 14 + 6 + 2 + 18
+    assert p00 == 60 + 25 * 1 + 4 * 1
+    per_nucleus = [bench.grad_model_flops(la, lb)[0] for la, lb in [(1, 0), (1, 1), (2, 1), (2, 2), (3, 3)]]
+    assert per_nucleus == sorted(per_nucleus)
+    # the adjoint step does several times the forward step's arithmetic
+    gn = bench._gaunt_nnz()
+    assert bench.grad_model_flops(3, 3)[0] > 4 * bench.model_flops(3, 3, gn)[0]
