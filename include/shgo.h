@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SHGO_LMAX 6 /* highest supported angular momentum of a shell */
+#define SHGO_LMAX 7 /* highest supported angular momentum of a shell */
 
 typedef enum {
   SHGO_OK = 0,
@@ -237,7 +237,8 @@ shgo_status shgo_execute_overlap(shgo_plan* plan, double* out, void* stream);
  *   energy       device [1], overwritten with E, or NULL
  * Runs on `stream` and allocates nothing. The work needs 8 (3 n_nuclei + 4 S) bytes of LDS per
  * workgroup, S a per-class layout of at most ~2.9k doubles; SHGO_ERR_INVALID_ARG if that
- * exceeds the 160 KB of a CU (about 2,800 nuclei for l <= 6), before any device work. */
+ * exceeds the 160 KB of a CU (about 2,800 nuclei for l <= 6, 1,300 with l = 7 shells), before
+ * any device work. */
 shgo_status shgo_execute_grad(shgo_plan* plan, const double* D, double* dE_dnuclei, double* dE_dcenters,
                               double* energy, void* stream);
 
@@ -254,9 +255,9 @@ shgo_status shgo_execute_graph(shgo_plan* plan, double* out, void* stream);
  * add into one LDS accumulator. Items are dispatched longest first, by the estimate
  * weight[c] x (primitive-pair iterations of the item's longest tile) x (its tiles) / (the
  * wavefronts its tasks keep busy, at most 8).
- *   weight[28] relative time of one primitive-pair iteration of a tile of the class, 1..1e6 (the
+ *   weight[36] relative time of one primitive-pair iteration of a tile of the class, 1..1e6 (the
  *              default comes from an operation-count model, largest 1024)
- *   tiles[28]  tiles per work item of each class, 1 <= tiles[c] <= shgo_max_tiles(c) (the LDS of
+ *   tiles[36]  tiles per work item of each class, 1 <= tiles[c] <= shgo_max_tiles(c) (the LDS of
  *              a work item holds per tile (2la+1)(2lb+1) x 65 accumulator doubles and 256 frame
  *              doubles, at most 20448 doubles in all). A new plan's default is the fewest tiles
  *              that give the eight wavefronts eight tasks, from the class's groups and its mean
@@ -264,7 +265,7 @@ shgo_status shgo_execute_graph(shgo_plan* plan, double* out, void* stream);
  * get copies the plan's schedule out; set validates (SHGO_ERR_INVALID_ARG) and installs one, e.g. a
  * schedule saved from an earlier autotune of the same workload. Results do not depend on the
  * schedule beyond rounding. */
-#define SHGO_NUM_CLASSES 28
+#define SHGO_NUM_CLASSES 36
 int32_t shgo_max_tiles(int32_t class_id); /* -1 for an invalid class id */
 shgo_status shgo_plan_get_schedule(const shgo_plan* plan, float* weight, int32_t* tiles);
 shgo_status shgo_plan_set_schedule(shgo_plan* plan, const float* weight, const int32_t* tiles);
@@ -309,7 +310,7 @@ shgo_status shgo_plan_phase_ms(shgo_plan* plan, double* ms, int32_t* count);
 
 /* Boys function F_m(t) = int_0^1 u^{2m} exp(-t u^2) du for m = 0..mmax (the radial factor of
  * Eq. 12), evaluated by the device routine the integral kernels use.  T: device array of n
- * values t >= 0; F: device array [n][mmax+1].  mmax <= 13. */
+ * values t >= 0; F: device array [n][mmax+1].  mmax <= 15 (2 SHGO_LMAX + 1). */
 shgo_status shgo_boys(shgo_context* ctx, int64_t n, const double* T, int32_t mmax, double* F, void* stream);
 
 #ifdef __cplusplus

@@ -24,7 +24,7 @@ SHGO_ERR_NOT_FINITE = 3
 SHGO_ERR_OUT_OF_MEMORY = 4
 SHGO_ERR_DEVICE = 5
 SHGO_ERR_INTERNAL = 6
-SHGO_LMAX = 6
+SHGO_LMAX = 7
 
 EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
@@ -34,7 +34,7 @@ EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_erro
             "shgo_plan_autotune", "shgo_max_tiles", "shgo_options_default", "shgo_check_call",
             "shgo_nuclear_attraction", "shgo_nuclear_attraction_grad", "shgo_plan_get_info", "shgo_plan_set_precision",
             "shgo_nuclear_attraction_noalloc", "shgo_plan_item_profile"]
-SHGO_NUM_CLASSES = 28
+SHGO_NUM_CLASSES = 36
 SHGO_TUNE_CANDIDATES = 5
 SHGO_NUM_PHASES = 2
 SHGO_PREC_FP64 = 0
@@ -389,7 +389,7 @@ def shgo_max_tiles(class_id):
 
 
 def shgo_plan_get_schedule(plan):
-    """(weight[28] float32, tiles[28] int32) of the plan's persistent launch."""
+    """(weight[SHGO_NUM_CLASSES] float32, tiles[SHGO_NUM_CLASSES] int32) of the plan's persistent launch."""
     lib = load_library()
     weight = np.zeros(SHGO_NUM_CLASSES, dtype=np.float32)
     tiles = np.zeros(SHGO_NUM_CLASSES, dtype=np.int32)
@@ -402,7 +402,7 @@ def shgo_plan_set_schedule(plan, weight, tiles):
     weight = np.ascontiguousarray(weight, dtype=np.float32)
     tiles = np.ascontiguousarray(tiles, dtype=np.int32)
     if weight.shape != (SHGO_NUM_CLASSES,) or tiles.shape != (SHGO_NUM_CLASSES,):
-        raise ValueError("weight and tiles need one entry per class (28)")
+        raise ValueError(f"weight and tiles need one entry per class ({SHGO_NUM_CLASSES})")
     _check(lib, plan.ctx, lib.shgo_plan_set_schedule(plan.handle, weight.ctypes.data, tiles.ctypes.data))
 
 

@@ -34,7 +34,7 @@ import sys
 
 import numpy as np
 
-LMAX_SHELL = 6
+LMAX_SHELL = 7
 DEFAULT_CAP = 64          # register budget of one group, in doubles of W
 # Classes up to this la have a binary32 (double-float) coupling for the mixed-precision kernel;
 # above it the mixed kernel keeps the binary64 coupling (the expanded double-float code of the
@@ -185,7 +185,7 @@ _GAUNT = None
 
 
 def real_gaunt_table():
-    """g[i1, i2, I] with S^{l1}_{m1} S^{l2}_{m2} = sum_{L,M} g r^{l1+l2-L} S^L_M, l1, l2 <= 6."""
+    """g[i1, i2, I] with S^{l1}_{m1} S^{l2}_{m2} = sum_{L,M} g r^{l1+l2-L} S^L_M, l1, l2 <= LMAX_SHELL."""
     global _GAUNT
     if _GAUNT is None:
         lm, Lm = LMAX_SHELL, 2 * LMAX_SHELL

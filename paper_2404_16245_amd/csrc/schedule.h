@@ -23,7 +23,7 @@
 
 namespace shgo_sched {
 
-constexpr int kLmax = 6;                                         // highest shell l
+constexpr int kLmax = 7;                                         // highest shell l
 constexpr int kNumClasses = (kLmax + 1) * (kLmax + 2) / 2;       // (la, lb) with la >= lb
 constexpr int kKeysPerClass = 256;
 constexpr int kNumKeys = kNumClasses * kKeysPerClass;

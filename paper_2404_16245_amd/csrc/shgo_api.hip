@@ -800,8 +800,8 @@ shgo_status shgo_plan_phase_ms(shgo_plan* p, double* ms, int32_t* count) {
 
 shgo_status shgo_boys(shgo_context* ctx, int64_t n, const double* T, int32_t mmax, double* F, void* stream) {
   if (!ctx) return SHGO_ERR_INVALID_ARG;
-  if (n < 0 || mmax < 0 || mmax > 13 || (n > 0 && (!T || !F)))
-    return fail(ctx, SHGO_ERR_INVALID_ARG, "bad Boys arguments (0 <= mmax <= 13)");
+  if (n < 0 || mmax < 0 || mmax > kBoysMaxM || (n > 0 && (!T || !F)))
+    return fail(ctx, SHGO_ERR_INVALID_ARG, "bad Boys arguments (0 <= mmax <= " + std::to_string(kBoysMaxM) + ")");
   if (n == 0) return SHGO_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
   const hipError_t e = launch_boys(mmax, n, T, F, ctx->boys_tab, (hipStream_t)stream);

@@ -90,7 +90,7 @@ using namespace shgo_sched;
 // ---------------------------------------------------------------------------------------------
 // Boys table: one row per (order M, grid point t_i = i/16) holding the Taylor coefficients of F_M
 // about t_i, F_{M+k}(t_i)/k! for k < 8, then e^{-t_i} as the sum of two doubles (high, low part).
-constexpr int kBoysMaxM = 13;      // highest order a kernel evaluates (l_a + l_b + 1 for the gradient)
+constexpr int kBoysMaxM = 15;      // highest order a kernel evaluates (l_a + l_b + 1 for the gradient)
 constexpr int kBoysPoints = 1153;  // grid t_i = i/16, i = 0..1152
 constexpr int kBoysRow = 10;       // doubles per row
 constexpr int kBoysRowLoad = 10;   // doubles a kernel reads of a row
@@ -256,11 +256,6 @@ __host__ __device__ constexpr double half_gamma_half(int M) {
   return c;
 }
 
-// The same evaluation for the integral kernel, with the Taylor row F_{M..M+7}(t_i) of the nearest
-// grid point (clamped to the table) already loaded and e = exp(-t), and no divergent branch: F_M
-// is the table's Taylor series below kBoysTcut and the leading asymptotic term
-// Gamma(M+1/2) / (2 t^{M+1/2}) above it (the neglected part is below e^{-t}/t, 1e-17 relative for
-// M <= 12 at t = 72), selected per lane; then the downward recursion, stable for every t.
 // Grid index of t (clamped to the table) and the first double of its row of order M.
 __device__ __forceinline__ int boys_index(double t) { return (int)(fmin(t, kBoysTcut) * 16.0 + 0.5); }
 __device__ __forceinline__ const double* boys_row_ptr(const double* tab, int M, int i) {
@@ -271,8 +266,10 @@ __device__ __forceinline__ const double* boys_row_ptr(const double* tab, int M, 
 // boys_index) and no divergent branch. Below kBoysTcut: the Taylor series of F_M about t_i,
 // F_M(t_i + h) = sum_k F_{M+k}(t_i) (-h)^k / k!, |h| <= 1/32 (the row holds the coefficients with
 // their 1/k!), and e^{-t} = e^{-t_i} e^{-h} with e^{-h} by its Taylor polynomial of degree 7 (the
-// remainder is below 3e-17) and e^{-t_i} carried in two parts (about one rounding in all). Above: the leading asymptotic term Gamma(M+1/2) / (2 t^{M+1/2}) (the
-// neglected part is below e^{-t}/t, 1e-17 relative for M <= 13 at t = 72) and e^{-t} taken as 0.
+// remainder is below 3e-17) and e^{-t_i} carried in two parts (about one rounding in all).
+// Above: the leading asymptotic term Gamma(M+1/2) / (2 t^{M+1/2}) (the neglected part, about
+// e^{-t} t^{M-1/2} / Gamma(M+1/2) relative, is below 2e-16 for M <= 15 at t = 72) and e^{-t}
+// taken as 0.
 // The two are selected per lane; then the downward recursion F_m = (2t F_{m+1} + e^{-t})/(2m+1),
 // stable for every t.
 template <int M>

@@ -26,10 +26,13 @@ __host__ __device__ constexpr double fact_d(int n) {
 }
 
 // Staged stores: the wavefront's 64 blocks (all of one class) leave through LDS a row at a time,
-// consecutive lanes on consecutive entries, then a column at a time for the mirror.
-constexpr int kOvlStage = 64 * (2 * SHGO_LMAX + 1);  // doubles per wavefront
-__shared__ double s_ovl_stage[4][kOvlStage];
-__shared__ int64_t s_ovl_d0[4][64], s_ovl_d1[4][64];
+// consecutive lanes on consecutive entries, then a column at a time for the mirror. Each
+// wavefront has its own stage of 64 (2 l_max + 1) doubles and 64 destination pairs.
+struct OvlStage {
+  double* stg;
+  int64_t* d0;
+  int64_t* d1;
+};
 
 __device__ __forceinline__ void ovl_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -42,7 +45,7 @@ __device__ __forceinline__ void ovl_wave_sync() {
 // active lane stores its own block.
 template <int LA, int LB, bool kStaged>
 __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs& pr, int slot, bool active,
-                                             double* __restrict__ out) {
+                                             const OvlStage& sg, double* __restrict__ out) {
   constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1;
   PairState ps;
   const int s1 = active ? pr.s1[slot] : 0, s2 = active ? pr.s2[slot] : 0;
@@ -130,10 +133,10 @@ __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs&
   }
   const int64_t d0 = active ? pr.dst0[slot] : -1, d1 = active ? pr.dst1[slot] : 0;
   if constexpr (kStaged) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double* const stg = s_ovl_stage[w];
-    s_ovl_d0[w][lane] = d0;
-    s_ovl_d1[w][lane] = d1;
+    const int lane = threadIdx.x & 63;
+    double* const stg = sg.stg;
+    sg.d0[lane] = d0;
+    sg.d1[lane] = d1;
     const int64_t n = bs.nbf;
     // rows i of every block: entry k = p NB + j is block p's (i, j)
 #pragma unroll
@@ -143,7 +146,7 @@ __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs&
       ovl_wave_sync();
       for (int k = lane; k < 64 * NB; k += 64) {
         const int q = k / NB, j = k - q * NB;
-        const int64_t e0 = s_ovl_d0[w][q], e1 = s_ovl_d1[w][q];
+        const int64_t e0 = sg.d0[q], e1 = sg.d1[q];
         if (e0 < 0) continue;
         if (pr.full) {
           if (e0 != e1 || i <= j) out[(e0 + i) * n + e1 + j] = stg[k];
@@ -164,7 +167,7 @@ __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs&
         ovl_wave_sync();
         for (int k = lane; k < 64 * NA; k += 64) {
           const int q = k / NA, i = k - q * NA;
-          const int64_t e0 = s_ovl_d0[w][q], e1 = s_ovl_d1[w][q];
+          const int64_t e0 = sg.d0[q], e1 = sg.d1[q];
           if (e0 < 0) continue;
           if (e0 != e1 || i <= col) out[(e1 + col) * n + e0 + i] = stg[k];
         }
@@ -194,43 +197,60 @@ __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs&
   }
 }
 
-template <int LA, int LB, bool kStaged>
+template <int LA, int LB, bool kStaged, int LMAXK>
 __device__ __forceinline__ void overlap_dispatch(int c, const DevBasis& bs, const DevPairs& pr, int slot, bool active,
-                                                 double* __restrict__ out) {
-  if constexpr (LA <= SHGO_LMAX) {
+                                                 const OvlStage& sg, double* __restrict__ out) {
+  if constexpr (LA <= LMAXK) {
     if (c == class_id(LA, LB)) {
-      overlap_pair<LA, LB, kStaged>(bs, pr, slot, active, out);
+      overlap_pair<LA, LB, kStaged>(bs, pr, slot, active, sg, out);
       return;
     }
     if constexpr (LB < LA)
-      overlap_dispatch<LA, LB + 1, kStaged>(c, bs, pr, slot, active, out);
+      overlap_dispatch<LA, LB + 1, kStaged, LMAXK>(c, bs, pr, slot, active, sg, out);
     else
-      overlap_dispatch<LA + 1, 0, kStaged>(c, bs, pr, slot, active, out);
+      overlap_dispatch<LA + 1, 0, kStaged, LMAXK>(c, bs, pr, slot, active, sg, out);
   }
 }
 
-// One thread per class-sorted shell pair of the plan (slots from k_scatter; s1 has the higher l).
-// A wavefront whose active lanes all hold one class (all but those at class boundaries) stores
-// through LDS; the others store lane by lane.
+// One thread per class-sorted shell pair in the slots [begin, end) (from k_scatter; s1 has the
+// higher l), whose classes all have la <= LMAXK: the kernel is register-allocated for its largest
+// class only. A wavefront whose active lanes all hold one class (all but those at class
+// boundaries) stores through LDS; the others store lane by lane.
+template <int LMAXK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_overlap(DevBasis bs, DevPairs pr, double* __restrict__ out) {
-  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = slot < pr.n_cand;
+k_overlap(DevBasis bs, DevPairs pr, int64_t begin, int64_t end, double* __restrict__ out) {
+  __shared__ double s_stage[4][64 * (2 * LMAXK + 1)];
+  __shared__ int64_t s_d0[4][64], s_d1[4][64];
+  const int w = threadIdx.x >> 6;
+  const OvlStage sg{s_stage[w], s_d0[w], s_d1[w]};
+  const int64_t slot = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = slot < end;
   const int c = active ? class_id(bs.l[pr.s1[slot]], bs.l[pr.s2[slot]]) : -1;
   const int c0 = __shfl(c, 0);  // lanes past the last pair come after the active ones
   if (c0 < 0) return;           // no active lane in this wavefront
   if (__all(!active || c == c0)) {
-    overlap_dispatch<0, 0, true>(c0, bs, pr, (int)(active ? slot : 0), active, out);
+    overlap_dispatch<0, 0, true, LMAXK>(c0, bs, pr, (int)(active ? slot : 0), active, sg, out);
   } else if (active) {
-    overlap_dispatch<0, 0, false>(c, bs, pr, (int)slot, true, out);
+    overlap_dispatch<0, 0, false, LMAXK>(c, bs, pr, (int)slot, true, sg, out);
   }
 }
 
 }  // namespace
 
+// The class-sorted slots fall into three ranges of la (classes are sorted by id, and the ids of
+// la <= 2, la = 3..4 and la = 5..SHGO_LMAX are contiguous): one launch each, so that the small
+// classes are not register-allocated for the largest block.
 void launch_overlap(const shgo_plan* p, double* out, hipStream_t st) {
   const int tb = 256;
-  hipLaunchKernelGGL(k_overlap, dim3((int)((p->n_cand + tb - 1) / tb)), dim3(tb), 0, st, p->bs, p->pr, out);
+  int64_t first[kNumClasses + 1];
+  first[0] = 0;
+  for (int c = 0; c < kNumClasses; ++c) first[c + 1] = first[c] + p->class_cand[c];
+  const int64_t b1 = first[class_id(3, 0)], b2 = first[class_id(5, 0)], b3 = first[kNumClasses];
+  auto grid = [&](int64_t n) { return dim3((unsigned)((n + tb - 1) / tb)); };
+  if (b1 > 0) hipLaunchKernelGGL(k_overlap<2>, grid(b1), dim3(tb), 0, st, p->bs, p->pr, (int64_t)0, b1, out);
+  if (b2 > b1) hipLaunchKernelGGL(k_overlap<4>, grid(b2 - b1), dim3(tb), 0, st, p->bs, p->pr, b1, b2, out);
+  if (b3 > b2)
+    hipLaunchKernelGGL(k_overlap<SHGO_LMAX>, grid(b3 - b2), dim3(tb), 0, st, p->bs, p->pr, b2, b3, out);
 }
 
 }  // namespace shgo_impl

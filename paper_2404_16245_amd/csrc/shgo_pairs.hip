@@ -289,7 +289,7 @@ hipError_t launch_boys(int mmax, int64_t n, const double* T, double* F, const do
   case M: hipLaunchKernelGGL(k_boys<M>, dim3(nb), dim3(tb), 0, st, n, T, F, tab); break;
     SHGO_BOYS_CASE(0) SHGO_BOYS_CASE(1) SHGO_BOYS_CASE(2) SHGO_BOYS_CASE(3) SHGO_BOYS_CASE(4)
     SHGO_BOYS_CASE(5) SHGO_BOYS_CASE(6) SHGO_BOYS_CASE(7) SHGO_BOYS_CASE(8) SHGO_BOYS_CASE(9)
-    SHGO_BOYS_CASE(10) SHGO_BOYS_CASE(11) SHGO_BOYS_CASE(12) SHGO_BOYS_CASE(13)
+    SHGO_BOYS_CASE(10) SHGO_BOYS_CASE(11) SHGO_BOYS_CASE(12) SHGO_BOYS_CASE(13) SHGO_BOYS_CASE(14) SHGO_BOYS_CASE(15)
 #undef SHGO_BOYS_CASE
     default: return hipErrorInvalidValue;
   }

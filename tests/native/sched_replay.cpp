@@ -19,7 +19,7 @@
 //   n_prims, then per primitive: exponent coef
 //   per nucleus: x y z Z
 //   per listed pair (pair plans): a b
-//   n_schedules, then per schedule 28 tiles
+//   n_schedules, then per schedule kNumClasses tiles
 // Output: one line "ok items=... tasks=... writes=..." per schedule; exit status 1 on a failed check.
 #include <cmath>
 #include <cstdio>

@@ -36,9 +36,9 @@ def test_gaunt_table_reproduces_products():
     for _ in range(3):
         v = rng.normal(size=3)
         r2 = float(v @ v)
-        S = gc.solid_real(12, v[None])[0]
-        for l1 in range(7):
-            for l2 in range(7):
+        S = gc.solid_real(2 * gc.LMAX_SHELL, v[None])[0]
+        for l1 in range(gc.LMAX_SHELL + 1):
+            for l2 in range(gc.LMAX_SHELL + 1):
                 for m1 in range(-l1, l1 + 1):
                     for m2 in range(-l2, l2 + 1):
                         i1, i2 = l1 * l1 + m1 + l1, l2 * l2 + m2 + l2
@@ -64,7 +64,7 @@ def test_gaunt_table_against_clebsch_gordan():
             M[-m + l, m + l] = -1j * (-1) ** m * h
         return M
     g = gc.real_gaunt_table()
-    for (l1, l2) in [(2, 3), (6, 6), (4, 1), (5, 5)]:
+    for (l1, l2) in [(2, 3), (6, 6), (4, 1), (5, 5), (7, 7), (7, 2)]:
         for L in range(abs(l1 - l2), l1 + l2 + 1, 2):
             Gc = np.zeros((2 * l1 + 1, 2 * l2 + 1, 2 * L + 1))
             c0 = oracle.cg(l1, 0, l2, 0, L, 0)
@@ -97,16 +97,16 @@ def test_rotation_tables(l):
 def test_shift_along_z_keeps_m():
     rng = np.random.default_rng(3)
     v, t = rng.normal(size=3), 0.83
-    S = gc.solid_real(6, v[None])[0]
-    St = gc.solid_real(6, (v + [0, 0, t])[None])[0]
-    for l in range(7):
+    S = gc.solid_real(gc.LMAX_SHELL, v[None])[0]
+    St = gc.solid_real(gc.LMAX_SHELL, (v + [0, 0, t])[None])[0]
+    for l in range(gc.LMAX_SHELL + 1):
         for m in range(-l, l + 1):
             s = sum(gc.trans_coef(l, l1, m) * t ** (l - l1) * S[l1 * l1 + m + l1] for l1 in range(abs(m), l + 1))
             assert s == pytest.approx(St[l * l + m + l], rel=1e-12, abs=1e-12)
 
 
 def test_groups_partition_families():
-    for LA in range(7):
+    for LA in range(gc.LMAX_SHELL + 1):
         for LB in range(LA + 1):
             groups = gc.class_groups(LA, LB)
             units = sorted(u for g in groups for u in g)

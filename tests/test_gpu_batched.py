@@ -10,6 +10,7 @@ from paper_2404_16245_amd import synth
 pytestmark = pytest.mark.gpu
 
 RTOL, ATOL = 1e-11, 1e-13
+NC = 36  # (la, lb) classes, la >= lb, l <= 7
 
 
 @pytest.fixture(scope="module")
@@ -71,11 +72,11 @@ def test_tiles_per_item_and_weights(shgo, molecule, tiles):
     import torch
     b, n, ref = molecule
     plan, out = _plan(shgo, b, n, 1e-12)
-    tmax = np.array([shgo.shgo_max_tiles(c) for c in range(28)], np.int32)
-    t = {"one": np.ones(28, np.int32), "max": tmax,
-         "mixed": np.minimum(tmax, np.arange(28, dtype=np.int32) % 3 + 1)}[tiles]
+    tmax = np.array([shgo.shgo_max_tiles(c) for c in range(NC)], np.int32)
+    t = {"one": np.ones(NC, np.int32), "max": tmax,
+         "mixed": np.minimum(tmax, np.arange(NC, dtype=np.int32) % 3 + 1)}[tiles]
     # any positive weights give the same integrals; they only order the work items
-    weight = np.random.default_rng(len(tiles)).uniform(1.0, 1e6, 28).astype(np.float32)
+    weight = np.random.default_rng(len(tiles)).uniform(1.0, 1e6, NC).astype(np.float32)
     shgo.shgo_plan_set_schedule(plan, weight, t)
     w2, t2 = shgo.shgo_plan_get_schedule(plan)
     assert np.array_equal(w2, weight) and np.array_equal(t2, t)
@@ -87,16 +88,16 @@ def test_tiles_per_item_and_weights(shgo, molecule, tiles):
 def test_schedule_validation(shgo, molecule):
     b, n, _ = molecule
     plan, _ = _plan(shgo, b, n, 1e-12)
-    ones = np.ones(28, np.float32)
-    for w in (np.zeros(28, np.float32), np.full(28, np.nan, np.float32), np.full(28, 2e6, np.float32)):
+    ones = np.ones(NC, np.float32)
+    for w in (np.zeros(NC, np.float32), np.full(NC, np.nan, np.float32), np.full(NC, 2e6, np.float32)):
         with pytest.raises(shgo.ShgoError) as e:
-            shgo.shgo_plan_set_schedule(plan, w, np.ones(28, np.int32))
+            shgo.shgo_plan_set_schedule(plan, w, np.ones(NC, np.int32))
         assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
     with pytest.raises(shgo.ShgoError) as e:
-        shgo.shgo_plan_set_schedule(plan, ones, np.full(28, 8, np.int32))
+        shgo.shgo_plan_set_schedule(plan, ones, np.full(NC, 8, np.int32))
     assert e.value.status == shgo.SHGO_ERR_INVALID_ARG  # (6,6) blocks allow one tile per item
     with pytest.raises(shgo.ShgoError) as e:
-        shgo.shgo_plan_set_schedule(plan, ones, np.zeros(28, np.int32))
+        shgo.shgo_plan_set_schedule(plan, ones, np.zeros(NC, np.int32))
     assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
 
 
@@ -109,7 +110,7 @@ def test_autotune_keeps_results(shgo, molecule):
     assert ms[chosen] == ms.min()
     # the installed schedule (the kept candidate after the per-class refinement) is a valid one
     w, t = shgo.shgo_plan_get_schedule(plan)
-    tmax = np.array([shgo.shgo_max_tiles(c) for c in range(28)])
+    tmax = np.array([shgo.shgo_max_tiles(c) for c in range(NC)])
     assert np.all((t >= 1) & (t <= tmax)) and np.all((w >= 1.0) & (w <= 1e6))
     out.fill_(float("nan"))
     shgo.shgo_execute_graph(plan, out)

@@ -63,14 +63,15 @@ def test_graph_and_autotune_cache(shgo, molecule, tmp_path):
     # no file: the call autotunes and writes it; the evaluation replays a graph
     assert_parity(call(shgo, b, n, screen=1e-10, use_graph=True, autotune_cache=path), ref, "tuned, graph")
     lines = open(path).read().split("\n")
-    assert lines[0] == "shgo-schedule 28" and len([x for x in lines[1:] if x]) == 28
+    nc = shgo.SHGO_NUM_CLASSES
+    assert lines[0] == f"shgo-schedule {nc}" and len([x for x in lines[1:] if x]) == nc
     w, t = [], []
     for c, line in enumerate(x for x in lines[1:] if x):
         ci, wi, ti = line.split()
         assert int(ci) == c
         w.append(float(wi))
         t.append(int(ti))
-    tmax = [shgo.shgo_max_tiles(c) for c in range(28)]
+    tmax = [shgo.shgo_max_tiles(c) for c in range(shgo.SHGO_NUM_CLASSES)]
     assert all(1 <= ti <= m for ti, m in zip(t, tmax)) and all(1.0 <= wi <= 1e6 for wi in w)
     # a fresh plan (other screen) with the file present: the schedule is read, not tuned again
     mtime = os.path.getmtime(path)

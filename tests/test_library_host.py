@@ -29,12 +29,12 @@ def test_library_exports_every_declared_symbol():
 
 def test_max_tiles_follow_the_accumulator():
     # tiles x ((2la+1)(2lb+1) x 65 + 256) doubles within 20448 (160 KB less 256 bytes), at most 8
-    for la in range(7):
+    for la in range(shgo.SHGO_LMAX + 1):
         for lb in range(la + 1):
             c = la * (la + 1) // 2 + lb
             nab = (2 * la + 1) * (2 * lb + 1)
             assert shgo.shgo_max_tiles(c) == min(8, 20448 // (nab * 65 + 256))
-    assert shgo.shgo_max_tiles(28) == -1 and shgo.shgo_max_tiles(-1) == -1
+    assert shgo.shgo_max_tiles(shgo.SHGO_NUM_CLASSES) == -1 and shgo.shgo_max_tiles(-1) == -1
 
 
 def test_status_strings():
@@ -62,7 +62,7 @@ def test_validation_accepts_good_input():
 
 
 @pytest.mark.parametrize("mutate,status", [
-    (lambda b, n: b.l.__setitem__(2, 7), shgo.SHGO_ERR_UNSUPPORTED_L),
+    (lambda b, n: b.l.__setitem__(2, shgo.SHGO_LMAX + 1), shgo.SHGO_ERR_UNSUPPORTED_L),
     (lambda b, n: b.l.__setitem__(2, -1), shgo.SHGO_ERR_UNSUPPORTED_L),
     (lambda b, n: b.expo.__setitem__(4, 0.0), shgo.SHGO_ERR_INVALID_ARG),
     (lambda b, n: b.expo.__setitem__(4, -1.0), shgo.SHGO_ERR_INVALID_ARG),

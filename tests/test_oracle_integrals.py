@@ -132,7 +132,7 @@ def test_two_center_overlap_against_polynomial_moments(la, lb):
     assert np.allclose(S, ref, rtol=1e-11, atol=1e-14)
 
 
-CLASSES = [(la, lb) for la in range(7) for lb in range(la + 1)] + [(0, 3), (2, 6), (1, 4)]
+CLASSES = [(la, lb) for la in range(8) for lb in range(la + 1)] + [(0, 3), (2, 6), (1, 4), (3, 7)]
 
 
 @pytest.mark.parametrize("la,lb", CLASSES)
@@ -210,7 +210,8 @@ def test_double_oracle_rounding_error():
     assert np.all(np.abs(V - Vq) <= 1e-14 + 1e-12 * np.abs(Vq))
     assert np.abs(V - Vq).max() <= 1e-15 * np.abs(Vq).max()
     # a high-l sample of the sweep workload
-    hb, hn, pa, pb = synth.high_l_sweep(seed=2, pairs_per_class=2, classes=[(6, 6), (5, 3), (0, 6), (4, 4)])
+    hb, hn, pa, pb = synth.high_l_sweep(seed=2, pairs_per_class=2, lmax=7,
+                                        classes=[(6, 6), (5, 3), (0, 6), (4, 4), (7, 7), (7, 4), (2, 7)])
     B = oracle.nuc_blocks(hb, hn, pa, pb)
     Bq = oracle.nuc_blocks(hb, hn, pa, pb, precision=2)
     assert np.all(np.abs(B - Bq) <= 1e-14 + 1e-12 * np.abs(Bq))

@@ -34,8 +34,8 @@ T_GRID = [0.0, 1e-12, 1e-6, 1e-3, 0.05, 0.3, 1.0, 2.5, 7.0, 12.0, 19.9, 25.0, 33
 
 @pytest.mark.parametrize("T", T_GRID)
 def test_boys_against_incomplete_gamma(T):
-    F = oracle.boys(13, T)
-    for m in range(14):
+    F = oracle.boys(15, T)
+    for m in range(16):
         ref = float(boys_ref(m, T))
         assert abs(F[m] - ref) <= 2e-14 * abs(ref), (m, T, F[m], ref)
 
@@ -51,11 +51,11 @@ def test_boys_extended_precision(T, prec):
 
 
 def test_boys_identities():
-    for m in range(14):
-        assert oracle.boys(13, 0.0)[m] == pytest.approx(1.0 / (2 * m + 1), rel=1e-15)
+    for m in range(16):
+        assert oracle.boys(15, 0.0)[m] == pytest.approx(1.0 / (2 * m + 1), rel=1e-15)
     for T in [0.2, 3.0, 30.0, 80.0]:
-        F = oracle.boys(13, T)
-        for m in range(13):
+        F = oracle.boys(15, T)
+        for m in range(15):
             # (2m+1) F_m = 2T F_{m+1} + exp(-T)
             lhs = (2 * m + 1) * F[m]
             rhs = 2 * T * F[m + 1] + math.exp(-T)

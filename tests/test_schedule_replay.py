@@ -9,7 +9,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from paper_2404_16245_amd import synth
+from paper_2404_16245_amd import SHGO_LMAX, SHGO_NUM_CLASSES, synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "native", "sched_replay.cpp")
@@ -32,7 +32,7 @@ def replay(tmp_path_factory):
 
 def _class_max_tiles():
     out = []
-    for la in range(7):
+    for la in range(SHGO_LMAX + 1):
         for lb in range(la + 1):
             nab = (2 * la + 1) * (2 * lb + 1)
             out.append(min(8, 20448 // (nab * 65 + 256)))
@@ -59,7 +59,7 @@ def write_input(path, basis, nuclei, screen, full, pa=None, pb=None, schedules=(
 def schedules(seed):
     mx = _class_max_tiles()
     rng = np.random.default_rng(seed)
-    return [[1] * 28, mx, [int(rng.integers(1, m + 1)) for m in mx]]
+    return [[1] * SHGO_NUM_CLASSES, mx, [int(rng.integers(1, m + 1)) for m in mx]]
 
 
 def run(replay, name, *args, **kw):
@@ -109,3 +109,12 @@ def test_replay_batched_molecule(replay):
     # the 200-atom molecule of the batched form (500,500 candidate pairs, nbf 5000)
     b, n = synth.batched_molecule(seed=3)
     run(replay, "batched", b, n, 1e-12, True, schedules=[])
+
+
+def test_replay_l7_classes(replay):
+    # l = 7 shells: one tile per (7,7) item (225 accumulator rows per pair), ragged tails, swapped
+    # pairs, and a contracted molecule with l up to 7
+    hb, hn, pa, pb = synth.high_l_sweep(seed=78, pairs_per_class=70, classes=[(7, b) for b in range(8)] + [(2, 7)])
+    run(replay, "l7_pairs", hb, hn, 0.0, False, pa, pb, schedules=schedules(6))
+    b, n = synth.molecule(seed=79, n_atoms=4, box=6.0, ls=(0, 2, 5, 7), kmax=4)
+    run(replay, "l7_matrix", b, n, 1e-8, True, schedules=schedules(7))
