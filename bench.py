@@ -343,6 +343,29 @@ def measure_mixed(shgo, synth, torch, steps):
                              "rel_floor": 1e-10, "max_rel_above_1e-6_of_max": rel_large}}
 
 
+def measure_cartesian(shgo, synth, torch, steps):
+    """The same V by the Cartesian (McMurchie-Davidson) route on the same GPU: the batched molecule
+    (l <= 4) and the gradient form's 500-atom molecule (l <= 3), each beside the solid-harmonic
+    route on the same plan (eager launches, the default schedule, and the autotuned one)."""
+    out = {}
+    for name, (basis, nuclei) in (("batched_molecule", synth.batched_molecule(seed=3)),
+                                  ("gradient_molecule", synth.gradient_molecule(seed=5))):
+        ctx = shgo.context(0)
+        plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, 1e-12)
+        v = torch.empty(plan.output_size, dtype=torch.float64, device="cuda")
+        ms_cart = _time_ms(torch, lambda: shgo.shgo_execute_cartesian(plan, v), max(2, steps // 4), 1)
+        vc = v.clone()
+        ms_shgo = _time_ms(torch, lambda: shgo.shgo_execute(plan, v), steps, 2)
+        shgo.shgo_plan_autotune(plan, v, rounds=3)
+        ms_tuned = _time_ms(torch, lambda: shgo.shgo_execute(plan, v), steps, 2)
+        d = (vc - v).abs().max().item() / v.abs().max().item()
+        out[name] = {"nbf": basis.nbf(), "integrals_per_step": plan.integrals, "ms_cartesian": ms_cart,
+                     "ms_solid_harmonic": ms_shgo, "ms_solid_harmonic_tuned": ms_tuned,
+                     "speedup": ms_cart / ms_shgo, "speedup_tuned": ms_cart / ms_tuned,
+                     "max_diff_rel_to_max": d}
+    return out
+
+
 def measure_overlap(shgo, synth, torch, steps):
     """Overlap matrix S of the batched molecule's basis (nbf 5000, K 1..8), full matrix: the plan's
     pair build and the overlap kernel per step. Bound by writing S (8 nbf^2 bytes)."""
@@ -481,6 +504,8 @@ def main():
         res["high_l_sweep"] = measure_sweep(shgo, synth, torch, args.steps)
         log("bench: mixed-precision form")
         res["mixed_precision"] = measure_mixed(shgo, synth, torch, args.steps)
+        log("bench: Cartesian route")
+        res["cartesian_route"] = measure_cartesian(shgo, synth, torch, args.steps)
         log("bench: gradient form")
         res["gradient"] = measure_gradient(shgo, synth, torch, 3)
         log("bench: overlap form")

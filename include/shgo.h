@@ -227,6 +227,15 @@ shgo_status shgo_plan_set_precision(shgo_plan* plan, int32_t precision);
  * part. Runs on `stream`, allocates nothing; SHGO_ERR_INVALID_ARG for a null plan or output. */
 shgo_status shgo_execute_overlap(shgo_plan* plan, double* out, void* stream);
 
+/* The same V as shgo_execute by the Cartesian route the paper compares against (Table 1, the
+ * Cartesian column): McMurchie-Davidson over Cartesian Gaussians -- the Hermite expansion of each
+ * primitive-pair product about P, the Hermite Coulomb integrals R_tuv from the Boys function
+ * summed over nuclei, their contraction -- then the transform to the real solid harmonics of the
+ * plan's basis (Eq. 1 normalisation and contraction, the plan's screening). Provided to compare
+ * the two routes on one GPU; shells up to l = 4 (SHGO_ERR_UNSUPPORTED_L otherwise, before any
+ * device work). Writes the layout shgo_execute writes, on `stream`, allocating nothing; FP64. */
+shgo_status shgo_execute_cartesian(shgo_plan* plan, double* out, void* stream);
+
 /* Gradient of E = sum_ij D_ij V_ij (the nuclear-attraction matrix of Eq. 11, differentiated
  * through Eq. 5, the shift of Eqs. 7-8, the product rule and the Boys function; an adjoint
  * kernel, not finite differences) with respect to the nuclear positions and the shell centers.

@@ -29,7 +29,7 @@ SHGO_LMAX = 7
 EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
             "shgo_plan_integrals", "shgo_execute", "shgo_execute_graph", "shgo_execute_grad", "shgo_boys",
-            "shgo_execute_overlap",
+            "shgo_execute_overlap", "shgo_execute_cartesian",
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
             "shgo_plan_autotune", "shgo_max_tiles", "shgo_options_default", "shgo_check_call",
             "shgo_nuclear_attraction", "shgo_nuclear_attraction_grad", "shgo_plan_get_info", "shgo_plan_set_precision",
@@ -111,6 +111,8 @@ def load_library(path=LIB_PATH):
     lib.shgo_execute_graph.restype = ctypes.c_int
     lib.shgo_execute_overlap.argtypes = [vp, vp, vp]
     lib.shgo_execute_overlap.restype = ctypes.c_int
+    lib.shgo_execute_cartesian.argtypes = [vp, vp, vp]
+    lib.shgo_execute_cartesian.restype = ctypes.c_int
     lib.shgo_plan_get_schedule.argtypes = [vp, vp, vp]
     lib.shgo_plan_get_schedule.restype = ctypes.c_int
     lib.shgo_plan_set_schedule.argtypes = [vp, vp, vp]
@@ -375,6 +377,14 @@ def shgo_execute_graph(plan, out, stream=None):
     return out
 
 
+def shgo_execute_cartesian(plan, out, stream=None):
+    """Enqueue the plan's V by the Cartesian (McMurchie-Davidson) route into ``out``; l <= 4."""
+    lib = load_library()
+    _check(lib, plan.ctx, lib.shgo_execute_cartesian(plan.handle, _f64_device(out, "out", plan.output_size),
+                                                     _stream_handle(stream)))
+    return out
+
+
 def shgo_execute_overlap(plan, out, stream=None):
     """Enqueue the overlap matrix S of the plan's shells into ``out`` (the layout V has)."""
     lib = load_library()
@@ -540,6 +550,27 @@ def _no_nuclei():
         Z = np.zeros(0)
         n = 0
     return _N()
+
+
+def nuclear_attraction_cartesian(basis, nuclei, screen=0.0, device=0):
+    """V by the Cartesian route (shgo_execute_cartesian), full nbf x nbf float64 CUDA tensor."""
+    import torch
+    plan = shgo_plan_matrix(context(device), basis, nuclei, screen)
+    nbf = shgo_nbf(basis)
+    out = torch.empty((nbf, nbf), dtype=torch.float64, device=f"cuda:{device}")
+    shgo_execute_cartesian(plan, out)
+    torch.cuda.current_stream().synchronize()
+    return out
+
+
+def nuclear_attraction_cartesian_pairs(basis, nuclei, pair_a, pair_b, screen=0.0, device=0):
+    """Blocks of the listed shell pairs by the Cartesian route, as a flat float64 CUDA tensor."""
+    import torch
+    plan = shgo_plan_pairs(context(device), basis, nuclei, pair_a, pair_b, screen)
+    out = torch.empty(plan.output_size, dtype=torch.float64, device=f"cuda:{device}")
+    shgo_execute_cartesian(plan, out)
+    torch.cuda.current_stream().synchronize()
+    return out
 
 
 def overlap(basis, device=0):

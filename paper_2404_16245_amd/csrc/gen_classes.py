@@ -926,6 +926,133 @@ def emit_grad(LA, LB):
     return "\n".join(o)
 
 
+# ----------------------------------------------------------------------------------------------
+# Cartesian route (McMurchie-Davidson), the comparison path on the same GPU
+# ----------------------------------------------------------------------------------------------
+CART_LMAX = 4  # shells of the Cartesian route: the product rule reaches L = 8 (165 Hermite integrals)
+
+
+def cart_monomials(l):
+    """Cartesian monomials x^i y^j z^k of degree l, index s(s+1)/2 + k with s = j + k."""
+    return [(l - sj, sj - k, k) for sj in range(l + 1) for k in range(sj + 1)]
+
+
+def tuv_list(L):
+    """Hermite indices (t, u, v), t + u + v <= L, index N(N+1)(N+2)/6 + s(s+1)/2 + v with
+    N = t + u + v and s = u + v."""
+    return [(N - sj, sj - v, v) for N in range(L + 1) for sj in range(N + 1) for v in range(sj + 1)]
+
+
+def hermite_a(t, i):
+    """Coefficient of X^(t-2i) g_(n+t-i) in d^t/dX^t g_n, where d/dX g_n = X g_(n+1):
+    t! / (2^i i! (t-2i)!), the number of ways to pair 2i of t derivatives."""
+    return math.factorial(t) // (2 ** i * math.factorial(i) * math.factorial(t - 2 * i))
+
+
+def solid_real_poly(l):
+    """Coefficients C[m + l][q] of S^l_m(x, y, z) = sum_q C x^i y^j z^k over cart_monomials(l),
+    built with the recurrences of solid_real in exact polynomial arithmetic (float coefficients)."""
+    def mul(a, b):
+        out = {}
+        for ka, va in a.items():
+            for kb, vb in b.items():
+                k = (ka[0] + kb[0], ka[1] + kb[1], ka[2] + kb[2])
+                out[k] = out.get(k, 0.0) + va * vb
+        return out
+
+    def add(a, b, fa=1.0, fb=1.0):
+        out = {k: fa * v for k, v in a.items()}
+        for k, v in b.items():
+            out[k] = out.get(k, 0.0) + fb * v
+        return out
+
+    X, Y, Zp = {(1, 0, 0): 1.0}, {(0, 1, 0): 1.0}, {(0, 0, 1): 1.0}
+    R2 = {(2, 0, 0): 1.0, (0, 2, 0): 1.0, (0, 0, 2): 1.0}
+    S = {(0, 0): {(0, 0, 0): 1.0}}
+    sc, ss = {(0, 0, 0): 1.0}, {}
+    for k in range(l):
+        f = 1.0 if k == 0 else math.sqrt((2 * k + 1) / (2 * k + 2))
+        sc, ss = add(mul(X, sc), mul(Y, ss), f, -f), add(mul(Y, sc), mul(X, ss), f, f)
+        S[(k + 1, k + 1)], S[(k + 1, -(k + 1))] = sc, ss
+    for m in range(l + 1):
+        for sgn in ([1] if m == 0 else [1, -1]):
+            mm = sgn * m
+            prev, cur = {}, S[(m, mm)]
+            for k in range(m, l):
+                den = math.sqrt((k + m + 1) * (k - m + 1))
+                a, b = (2 * k + 1) / den, math.sqrt((k + m) * (k - m)) / den
+                nxt = add(mul(Zp, cur), mul(R2, prev), a, -b)
+                S[(k + 1, mm)] = nxt
+                prev, cur = cur, nxt
+    mono = cart_monomials(l)
+    C = np.zeros((2 * l + 1, len(mono)))
+    for m in range(-l, l + 1):
+        for q, ijk in enumerate(mono):
+            C[m + l, q] = S[(l, m)].get(ijk, 0.0)
+    return C
+
+
+def cart_r_terms(L):
+    """[(index, [(coef, a, b, c, n), ...])] of R_tuv = sum coef X^a Y^b Z^c g_n, in tuv_list order."""
+    out = []
+    for n, (t, u, v) in enumerate(tuv_list(L)):
+        N = t + u + v
+        terms = [(hermite_a(t, i) * hermite_a(u, j) * hermite_a(v, k), t - 2 * i, u - 2 * j, v - 2 * k, N - i - j - k)
+                 for i in range(t // 2 + 1) for j in range(u // 2 + 1) for k in range(v // 2 + 1)]
+        out.append((n, terms))
+    return out
+
+
+def emit_cart_r(L):
+    """W[idx(t,u,v)] += Z R_tuv for t + u + v <= L, with R_tuv = d^t/dX^t d^u/dY^u d^v/dZ^v g_0,
+    g_n = (-2p)^n F_n(p |C|^2) and d/dX g_n = X g_(n+1): the closed form
+    R_tuv = sum_(i,j,k) a_ti a_uj a_vk X^(t-2i) Y^(u-2j) Z^(v-2k) g_(t+u+v-i-j-k)."""
+    tl = tuv_list(L)
+    o = [f"template <> struct CartR<{L}> {{",
+         f"  static constexpr int NT = {len(tl)};",
+         f"  static __device__ __forceinline__ void step(double (&W)[NT], double X, double Y, double Z, double Zc,",
+         f"                                              const double (&g)[{L + 1}]) {{",
+         f"    double px[{L + 1}], py[{L + 1}], pz[{L + 1}];",
+         "    px[0] = 1.0; py[0] = 1.0; pz[0] = 1.0;",
+         "#pragma unroll",
+         f"    for (int k = 1; k <= {L}; ++k) {{ px[k] = px[k - 1] * X; py[k] = py[k - 1] * Y; pz[k] = pz[k - 1] * Z; }}"]
+    for n, tl_terms in cart_r_terms(L):
+        t, u, v = tl[n]
+        terms = []
+        for c, a, b, cc, gn in tl_terms:
+            mono = [f"p{ax}[{e}]" for ax, e in (("x", a), ("y", b), ("z", cc)) if e]
+            if c != 1:
+                mono.append(f"{float(c)!r}")
+            terms.append((" * ".join(mono) if mono else None, gn))
+        expr = None
+        for m, gn in terms:
+            if expr is None:
+                expr = f"g[{gn}]" if m is None else f"{m} * g[{gn}]"
+            else:
+                expr = f"fma({m}, g[{gn}], {expr})" if m is not None else f"g[{gn}] + {expr}"
+        o.append(f"    W[{n}] = fma(Zc, {expr}, W[{n}]);  // R_{t}{u}{v}")
+    o.append("  }")
+    o.append("};")
+    return "\n".join(o)
+
+
+def emit_cart_header(lmax=CART_LMAX):
+    out = ["// Generated by gen_classes.py -- do not edit. The Cartesian (McMurchie-Davidson) route:",
+           "// Hermite Coulomb integrals R_tuv summed over nuclei, and the Cartesian-to-real-harmonic",
+           "// coefficients of each l.",
+           "#pragma once",
+           f"constexpr int kCartLmax = {lmax};",
+           "template <int L> struct CartR;"]
+    for L in range(2 * lmax + 1):
+        out.append(emit_cart_r(L))
+    for l in range(lmax + 1):
+        C = solid_real_poly(l)
+        out.append(f"// S^{l}_m = sum_q kCartSph{l}[m + {l}][q] x^i y^j z^k over the degree-{l} monomials")
+        rows = ["{" + ", ".join(lit(v) for v in row) + "}" for row in C]
+        out.append(f"__device__ const double kCartSph{l}[{2 * l + 1}][{C.shape[1]}] = {{{', '.join(rows)}}};")
+    return "\n".join(out) + "\n"
+
+
 def emit_grad_header(lmax=LMAX_SHELL):
     out = ["// gradient kernel: inverse rotations, gradient matrices of the real solid harmonics, and per class",
            "// the adjoint term tables and the forward-mode nucleus step",
@@ -1027,7 +1154,7 @@ def _write(path, text):
 
 def main(argv):
     """Writes shgo_classes.inc (the path given, default generated/shgo_classes.inc) and, beside it,
-    shgo_rot.inc, shgo_meta.inc and shgo_grad.inc."""
+    shgo_rot.inc, shgo_meta.inc, shgo_grad.inc and shgo_cart.inc."""
     out = argv[1] if len(argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)), "generated",
                                                      "shgo_classes.inc")
     cap = None
@@ -1039,6 +1166,7 @@ def main(argv):
     _write(os.path.join(d, "shgo_rot.inc"), emit_rotations())
     _write(os.path.join(d, "shgo_meta.inc"), emit_meta(cap))
     _write(os.path.join(d, "shgo_grad.inc"), emit_grad_header())
+    _write(os.path.join(d, "shgo_cart.inc"), emit_cart_header())
     return out
 
 

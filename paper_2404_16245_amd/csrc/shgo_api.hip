@@ -553,6 +553,24 @@ shgo_status shgo_execute_overlap(shgo_plan* p, double* out, void* stream) {
   return SHGO_OK;
 }
 
+shgo_status shgo_execute_cartesian(shgo_plan* p, double* out, void* stream) {
+  if (!p) return SHGO_ERR_INVALID_ARG;
+  shgo_context* ctx = p->ctx;
+  if (!out && p->out_size > 0) return fail(ctx, SHGO_ERR_INVALID_ARG, "null output");
+  for (int c = 0; c < kNumClasses; ++c)
+    if (p->class_cand[c] > 0 && class_la(c) > cart_lmax())
+      return fail(ctx, SHGO_ERR_UNSUPPORTED_L,
+                  "the Cartesian route takes shells up to l = " + std::to_string(cart_lmax()));
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+  if (p->n_cand == 0) return SHGO_OK;
+  hipStream_t st = (hipStream_t)stream;
+  launch_pair_build(p, st);
+  hipError_t e = launch_cartesian(p, out, st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+  return SHGO_OK;
+}
+
 shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* stream, double* ms, int32_t* chosen) {
   if (!p || rounds < 1 || rounds > 1000) return SHGO_ERR_INVALID_ARG;
   shgo_context* ctx = p->ctx;

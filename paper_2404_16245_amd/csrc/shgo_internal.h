@@ -441,6 +441,10 @@ hipError_t integrals_setup_mixed(int* per_cu, std::string* why);
 void launch_integrals(const shgo_plan* p, double* out, hipStream_t st);
 // shgo_overlap.hip
 void launch_overlap(const shgo_plan* p, double* out, hipStream_t st);
+// shgo_cart.hip: the Cartesian (McMurchie-Davidson) route, one kernel per class present; shells
+// up to l = cart_lmax()
+int cart_lmax();
+hipError_t launch_cartesian(const shgo_plan* p, double* out, hipStream_t st);
 // shgo_grad.hip: validate (launch = false: LDS limits, occupancy) or launch every class present
 shgo_status grad_classes(shgo_plan* p, const GradArgs& ga, hipStream_t st, bool launch);
 

@@ -223,3 +223,37 @@ def test_emulated_gradient_same_center_and_z_axis():
         assert Ee == pytest.approx(E, rel=1e-12, abs=1e-13)
         assert np.allclose(np.concatenate([dAe, dBe, dCe.reshape(-1)]),
                            np.concatenate([dc[0], dc[1], dn.reshape(-1)]), atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("L", range(2 * gc.CART_LMAX + 1))
+def test_cartesian_route_hermite_closed_form(L):
+    # the closed form the Cartesian kernel's nucleus step is generated from, term by term, against
+    # the McMurchie-Davidson recursion for R_tuv written independently in tests/xcheck.py
+    rng = np.random.default_rng(10 + L)
+    for _ in range(3):
+        p = float(np.exp(rng.uniform(np.log(0.2), np.log(20.0))))
+        PC = rng.normal(0, 0.8, 3)
+        ref = xcheck._hermite_R(L, p, PC)
+        T = p * float(PC @ PC)
+        g = [(-2 * p) ** n * float(xcheck.boys_mp(n, T)) for n in range(L + 1)]
+        tl = gc.tuv_list(L)
+        assert len(tl) == (L + 1) * (L + 2) * (L + 3) // 6
+        for n, terms in gc.cart_r_terms(L):
+            got = sum(c * PC[0] ** a * PC[1] ** b * PC[2] ** cc * g[gn] for c, a, b, cc, gn in terms)
+            want = ref(*tl[n])
+            assert got == pytest.approx(want, rel=1e-11, abs=1e-13 * max(1.0, abs(want)))
+
+
+def test_cartesian_route_real_harmonic_coefficients():
+    # S^l_m as polynomials in the Cartesian monomials, against the recurrences at random points
+    # and against the monomial expansion written independently in tests/xcheck.py
+    pts = np.random.default_rng(4).normal(size=(7, 3))
+    for l in range(gc.CART_LMAX + 1):
+        C = gc.solid_real_poly(l)
+        mono = gc.cart_monomials(l)
+        assert len(mono) == (l + 1) * (l + 2) // 2
+        M = np.array([[x ** i * y ** j * z ** k for (i, j, k) in mono] for (x, y, z) in pts])
+        S = gc.solid_real(l, pts)[:, l * l:(l + 1) ** 2]
+        assert np.allclose(M @ C.T, S, rtol=1e-13, atol=1e-13 * np.abs(S).max())
+        ref = np.array([xcheck.eval_real_solid(l, *pt) for pt in pts])
+        assert np.allclose(M @ C.T, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
