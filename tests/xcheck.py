@@ -297,3 +297,50 @@ def real_wigner_d(l, Q):
     SQx = np.array([eval_real_solid(l, *(Q @ x)) for x in X])
     Dt, *_ = np.linalg.lstsq(Sx, SQx, rcond=None)
     return Dt.T
+
+
+# ----------------------------------------------------------------------------------------------
+# Two-electron integrals by the Gaussian transform 1/r12 = (2/sqrt(pi)) int_0^inf exp(-u^2 r12^2) du
+# ----------------------------------------------------------------------------------------------
+def _eri_dim(i1, j1, i2, j2, A, B, C, D, a, b, c, d, u, nq):
+    """int int (x1-A)^i1 (x1-B)^j1 (x2-C)^i2 (x2-D)^j2 e^{-a(x1-A)^2-b(x1-B)^2-c(x2-C)^2-d(x2-D)^2-u^2(x1-x2)^2}
+    by Gauss-Hermite quadrature in the eigen-coordinates of the 2-D quadratic form (exact: the
+    integrand is a polynomial of degree < 2 nq times the Gaussian)."""
+    # quadratic form x^T M x - 2 g^T x + h
+    M = np.array([[a + b + u * u, -u * u], [-u * u, c + d + u * u]])
+    g = np.array([a * A + b * B, c * C + d * D])
+    h = a * A * A + b * B * B + c * C * C + d * D * D
+    xs = np.linalg.solve(M, g)
+    c0 = h - g @ xs
+    Lc = np.linalg.cholesky(M)                    # M = L L^T
+    T = np.linalg.inv(Lc.T)                       # x = xs + T y, |y|^2 = (x - xs)^T M (x - xs)
+    y, w = np.polynomial.hermite.hermgauss(nq)
+    Y1, Y2 = np.meshgrid(y, y, indexing="ij")
+    W = np.outer(w, w)
+    X1 = xs[0] + T[0, 0] * Y1 + T[0, 1] * Y2
+    X2 = xs[1] + T[1, 0] * Y1 + T[1, 1] * Y2
+    f = (X1 - A) ** i1 * (X1 - B) ** j1 * (X2 - C) ** i2 * (X2 - D) ** j2
+    return float(np.sum(W * f)) * abs(np.linalg.det(T)) * math.exp(-c0)
+
+
+def quad_eri_prim(la, A, a, lb, B, b, lc, C, c, ld, D, d):
+    """Real (2la+1)(2lb+1)(2lc+1)(2ld+1) primitive (ab|cd) block (unnormalised) by the Gaussian
+    transform of 1/r12, Gauss-Hermite quadrature in each dimension and adaptive quadrature in u."""
+    A, B, C, D = (np.asarray(x, float) for x in (A, B, C, D))
+    ma, mb, mc, md = monomials(la), monomials(lb), monomials(lc), monomials(ld)
+    nq = (la + lb + lc + ld) // 2 + 3
+    cart = np.zeros((len(ma), len(mb), len(mc), len(md)))
+    for ia, ea in enumerate(ma):
+        for ib, eb in enumerate(mb):
+            for ic, ec in enumerate(mc):
+                for id_, ed in enumerate(md):
+                    def f(u):
+                        v = 1.0
+                        for x in range(3):
+                            v *= _eri_dim(ea[x], eb[x], ec[x], ed[x], A[x], B[x], C[x], D[x], a, b, c, d, u, nq)
+                        return v
+                    v1, _ = integrate.quad(f, 0.0, 1.0, epsabs=0, epsrel=1e-13, limit=200)
+                    v2, _ = integrate.quad(f, 1.0, np.inf, epsabs=0, epsrel=1e-13, limit=200)
+                    cart[ia, ib, ic, id_] = 2.0 / math.sqrt(math.pi) * (v1 + v2)
+    Ca, Cb, Cc, Cd = real_solid_poly(la), real_solid_poly(lb), real_solid_poly(lc), real_solid_poly(ld)
+    return np.einsum("ai,bj,ck,dl,ijkl->abcd", Ca, Cb, Cc, Cd, cart)
