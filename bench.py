@@ -366,6 +366,56 @@ def measure_cartesian(shgo, synth, torch, steps):
     return out
 
 
+def unique_quartets(n_shells):
+    """Shell quartets (a, b, c, d) with a >= b, c >= d and pair (a, b) >= pair (c, d): one of each
+    set of quartets that the eightfold permutational symmetry of (ab|cd) relates."""
+    a, b = np.tril_indices(n_shells)
+    i, j = np.tril_indices(len(a))
+    return np.stack([a[i], b[i], a[j], b[j]], axis=1).astype(np.int32)
+
+
+def eri_workload(synth):
+    return synth.molecule(seed=7, n_atoms=10, box=8.0, ls=(0, 1, 2), kmax=3)
+
+
+def eri_cpu_baseline(synth, n_sample=200):
+    """The two-electron oracle on one thread over a sample of the same unique quartets."""
+    from oracle import eri as eri_oracle
+    basis, _ = eri_workload(synth)
+    q = unique_quartets(len(basis.l))
+    sel = q[np.random.default_rng(7).choice(len(q), n_sample, replace=False)]
+    t0 = time.perf_counter()
+    for quartet in sel:
+        eri_oracle.eri_block(basis, *quartet)
+    dt = time.perf_counter() - t0
+    n = int(np.prod(2 * np.asarray(basis.l)[sel] + 1, axis=1).sum())
+    return {"value": n / dt, "unit": "integrals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} of the unique quartets of the two-electron workload"}
+
+
+def measure_eri(shgo, synth, torch, steps):
+    """Two-electron blocks (ab|cd) of every unique shell quartet of a 10-atom molecule (shells
+    s, p, d on each atom, K 1..3), one call per step: the upload of the quartet list, the pair
+    weights and the kernel, waited for."""
+    basis, _ = eri_workload(synth)
+    q = unique_quartets(len(basis.l))
+    ls = np.asarray(basis.l)
+    n_int = int(np.prod(2 * ls[q] + 1, axis=1).sum())
+    prim = np.asarray(basis.nprim)
+    n_prim_q = int(np.prod(prim[q], axis=1).sum())
+    shgo.eri_blocks(basis, q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        shgo.eri_blocks(basis, q)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"workload": "every unique quartet of a 10-atom molecule (s, p, d shells, K 1..3), seed 7",
+            "n_shells": int(len(ls)), "quartets": int(len(q)), "primitive_quartets": n_prim_q,
+            "integrals_per_step": n_int, "ms_per_step": ms, "integrals_per_s": n_int / (ms * 1e-3),
+            "primitive_quartets_per_s": n_prim_q / (ms * 1e-3)}
+
+
 def measure_overlap(shgo, synth, torch, steps):
     """Overlap matrix S of the batched molecule's basis (nbf 5000, K 1..8), full matrix: the plan's
     pair build and the overlap kernel per step. Bound by writing S (8 nbf^2 bytes)."""
@@ -510,6 +560,8 @@ def main():
         res["gradient"] = measure_gradient(shgo, synth, torch, 3)
         log("bench: overlap form")
         res["overlap"] = measure_overlap(shgo, synth, torch, 5)
+        log("bench: two-electron blocks")
+        res["two_electron"] = measure_eri(shgo, synth, torch, 3)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         # the host's share of cores (OMP_NUM_THREADS where the launcher sets it, else at most 16)
@@ -519,6 +571,8 @@ def main():
         res["cpu_baseline"] = {"value": v, "unit": "integrals/s", "cores": threads, "kind": "oracle",
                                "sample": desc_s, "cpu_model": cpu_model(), "value_1_thread": v1,
                                "sample_1_thread": desc_1}
+        if "two_electron" in res:
+            res["cpu_baseline"]["two_electron"] = eri_cpu_baseline(synth)
     else:
         res["cpu_baseline"] = None
     print(json.dumps(res), flush=True)

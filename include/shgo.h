@@ -236,6 +236,21 @@ shgo_status shgo_execute_overlap(shgo_plan* plan, double* out, void* stream);
  * device work). Writes the layout shgo_execute writes, on `stream`, allocating nothing; FP64. */
 shgo_status shgo_execute_cartesian(shgo_plan* plan, double* out, void* stream);
 
+/* Two-electron Coulomb integrals (ab|cd) = int int chi_a chi_b (r1) chi_c chi_d (r2) / |r1 - r2| over
+ * the basis (Eq. 1 normalisation and contraction), by the solid-harmonic route of Eqs. 13-15: the
+ * Gaussian product of each pair, the shifts to P and Q (Eq. 7) and the product rule (Supplement
+ * Eq. 4) in the pair frames, and the two-center integral between the pairs' terms in closed form
+ * (Hobson's theorem on the solid-harmonic gradients, the product rule applied to them, the Boys
+ * function of pq/(p+q) |P-Q|^2). No screening.
+ *   quartets   host [n_quartets][4] shell indices (a, b, c, d), any order within each pair
+ *   out        device, the blocks in quartet order, each (2la+1)(2lb+1)(2lc+1)(2ld+1) doubles
+ *              row-major in the listed shell order (a slowest)
+ * Shells up to l = 2 (SHGO_ERR_UNSUPPORTED_L otherwise); SHGO_ERR_INVALID_ARG for a shell index
+ * out of range; both before any device work. Uploads the basis and the quartets to a workspace of
+ * its own, runs on `stream` and waits for it before returning (the workspace is then freed). */
+shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
+                            double* out, void* stream);
+
 /* Gradient of E = sum_ij D_ij V_ij (the nuclear-attraction matrix of Eq. 11, differentiated
  * through Eq. 5, the shift of Eqs. 7-8, the product rule and the Boys function; an adjoint
  * kernel, not finite differences) with respect to the nuclear positions and the shell centers.

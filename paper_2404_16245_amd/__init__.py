@@ -29,7 +29,7 @@ SHGO_LMAX = 7
 EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
             "shgo_plan_integrals", "shgo_execute", "shgo_execute_graph", "shgo_execute_grad", "shgo_boys",
-            "shgo_execute_overlap", "shgo_execute_cartesian",
+            "shgo_execute_overlap", "shgo_execute_cartesian", "shgo_eri_blocks",
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
             "shgo_plan_autotune", "shgo_max_tiles", "shgo_options_default", "shgo_check_call",
             "shgo_nuclear_attraction", "shgo_nuclear_attraction_grad", "shgo_plan_get_info", "shgo_plan_set_precision",
@@ -113,6 +113,8 @@ def load_library(path=LIB_PATH):
     lib.shgo_execute_overlap.restype = ctypes.c_int
     lib.shgo_execute_cartesian.argtypes = [vp, vp, vp]
     lib.shgo_execute_cartesian.restype = ctypes.c_int
+    lib.shgo_eri_blocks.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.shgo_eri_blocks.restype = ctypes.c_int
     lib.shgo_plan_get_schedule.argtypes = [vp, vp, vp]
     lib.shgo_plan_get_schedule.restype = ctypes.c_int
     lib.shgo_plan_set_schedule.argtypes = [vp, vp, vp]
@@ -571,6 +573,24 @@ def nuclear_attraction_cartesian_pairs(basis, nuclei, pair_a, pair_b, screen=0.0
     shgo_execute_cartesian(plan, out)
     torch.cuda.current_stream().synchronize()
     return out
+
+
+def eri_blocks(basis, quartets, device=0, stream=None):
+    """Two-electron blocks (ab|cd) of the quartets [n, 4] of shell indices (shells up to l = 2), as a
+    flat float64 CUDA tensor: each block (2la+1)(2lb+1)(2lc+1)(2ld+1) row-major, in quartet order."""
+    import torch
+    lib = load_library()
+    ctx = context(device)
+    q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
+    hb = _HostBasis(basis)
+    ls = np.asarray(basis.l)
+    # out-of-range indices are left for the library to reject (it writes nothing then)
+    valid = len(q) and q.min() >= 0 and q.max() < len(ls)
+    size = int(np.prod(2 * ls[q] + 1, axis=1).sum()) if valid else 0
+    out = torch.empty(max(size, 1), dtype=torch.float64, device=f"cuda:{device}")
+    _check(lib, ctx, lib.shgo_eri_blocks(ctx, ctypes.byref(hb.struct), int(len(q)), q.ctypes.data,
+                                         out.data_ptr(), _stream_handle(stream)))
+    return out[:size]
 
 
 def overlap(basis, device=0):

@@ -1053,6 +1053,266 @@ def emit_cart_header(lmax=CART_LMAX):
     return "\n".join(out) + "\n"
 
 
+# ----------------------------------------------------------------------------------------------
+# Two-electron integrals (ab|cd) by the solid-harmonic route
+# ----------------------------------------------------------------------------------------------
+# Each pair (a, b) is worked as in the nuclear-attraction kernel: the Gaussian product, the shifts
+# to P in the pair frame (Eq. 7) and the product rule (Supplement Eq. 4) give its charge
+# distribution as sum_{L,M,k} B(L,M,k) |u|^{2k} S^L_M(u) e^{-p u^2}, u = r - P, rotated to the
+# laboratory frame. With S^L(u) e^{-p u^2} = (2p)^{-L} S^L(grad_P) e^{-p u^2} (Hobson's theorem) and
+# |u|^{2k} S^L(u) e^{-p u^2} = (2p)^{-L} sum_j c_{L,k,j}(p) (grad_P^2)^j S^L(grad_P) e^{-p u^2}, the
+# two-center integral of two such terms is a derivative of the s-s-s-s integral
+# c F_0(alpha R^2), c = 2 pi^{5/2} / (p q sqrt(p+q)), alpha = pq/(p+q), R = P - Q:
+#   (-1)^{L2} (grad_R^2)^{j1+j2} S^{L1}(grad_R) S^{L2}(grad_R) c F_0 =
+#   (-1)^{L2} sum_{L,M} g(L1 M1, L2 M2; L M) S^L_M(R) h_{L, j1+j2+kappa}(R^2),  kappa = (L1+L2-L)/2,
+# with the product rule applied to the gradients, h_{L,0} = c (-2 alpha)^L F_L(alpha R^2) (Hobson's
+# theorem again) and h_{L,n+1} = 4 rho h'' + (4L+6) h' (the Laplacian of S^L(R) h(R^2), rho = R^2),
+# which for n >= 1 is c (-2 alpha)^L alpha^n P_{L,n}(T) e^{-T}, T = alpha rho.
+ERI_LMAX = 2  # shells of the two-electron path (pair distributions up to L = 4, L1 + L2 <= 8)
+
+
+def _poly_Q(L, jmax, p):
+    """Q_{L,j}(rho) (ascending coefficients, Fractions) with (grad^2)^j [S^L(u) e^{-p u^2}] =
+    S^L(u) Q_{L,j}(u^2) e^{-p u^2}: Q_0 = 1, Q_{j+1} = 4 rho (Q'' - 2p Q' + p^2 Q) + (4L+6)(Q' - p Q)."""
+    from fractions import Fraction as Fr
+
+    def der(q):
+        return [i * q[i] for i in range(1, len(q))] or [Fr(0)]
+
+    def add(*qs):
+        n = max(len(q) for q in qs)
+        return [sum((q[i] if i < len(q) else Fr(0)) for q in qs) for i in range(n)]
+
+    def scale(q, c):
+        return [c * v for v in q]
+
+    Qs = [[Fr(1)]]
+    for _ in range(jmax):
+        Q = Qs[-1]
+        d1, d2 = der(Q), der(der(Q))
+        inner = add(d2, scale(d1, -2 * p), scale(Q, p * p))
+        Qs.append(add([Fr(0)] + scale(inner, 4), scale(add(d1, scale(Q, -p)), 4 * L + 6)))
+    return Qs
+
+
+def eri_gamma(L, kmax):
+    """gamma[k][j] with c_{L,k,j}(p) = gamma p^{-(k+j)}: rho^k = sum_j c_{L,k,j} Q_{L,j}(rho)."""
+    from fractions import Fraction as Fr
+    n = kmax + 1
+    out = np.zeros((n, n))
+    for pv in (Fr(1), Fr(3, 2)):
+        Qs = _poly_Q(L, kmax, pv)
+        # solve the triangular system exactly: Q_j has degree j and leading coefficient (4p^2)^j
+        c = [[Fr(0)] * n for _ in range(n)]
+        for k in range(n):
+            rem = [Fr(0)] * (k + 1)
+            rem[k] = Fr(1)
+            for j in range(k, -1, -1):
+                coef = rem[j] / Qs[j][j]
+                c[k][j] = coef
+                for i in range(j + 1):
+                    rem[i] -= coef * Qs[j][i]
+        if pv == 1:
+            out = np.array([[float(c[k][j]) for j in range(n)] for k in range(n)])
+        else:  # the p^{-(k+j)} scaling the kernel relies on
+            for k in range(n):
+                for j in range(k + 1):
+                    assert c[k][j] == Fr(out[k][j]).limit_denominator(10 ** 12) * pv ** (-(k + j)) or \
+                        abs(float(c[k][j]) - out[k][j] * float(pv) ** (-(k + j))) <= 1e-15 * abs(out[k][j]) + 1e-300
+    return out
+
+
+def eri_P(L, n):
+    """Integer coefficients of P_{L,n}(T), n >= 1: P_1 = -2, P_{n+1} = 4T(P'' - 2P' + P) + (4L+6)(P' - P)."""
+    P = [-2]
+    for _ in range(n - 1):
+        d1 = [i * P[i] for i in range(1, len(P))] or [0]
+        d2 = [i * d1[i] for i in range(1, len(d1))] or [0]
+        m = max(len(P), len(d1), len(d2))
+        at = lambda q, i: q[i] if i < len(q) else 0  # noqa: E731
+        inner = [at(d2, i) - 2 * at(d1, i) + at(P, i) for i in range(m)]
+        nxt = [0] * (m + 1)
+        for i in range(m):
+            nxt[i + 1] += 4 * inner[i]
+            nxt[i] += (4 * L + 6) * (at(d1, i) - at(P, i))
+        while len(nxt) > 1 and nxt[-1] == 0:
+            nxt.pop()
+        P = nxt
+    return P
+
+
+def eri_class_tables(LA, LB):
+    """(entries [(L, M, k)], terms by entry [[(coef, e, pa, pb)]], rotation blocks [(L, k, [w by M])],
+    (L, M) groups [(L, [w by k])]) of pair class (LA, LB), LA >= LB."""
+    ents = grad_entries(LA, LB)
+    idx = {e: i for i, e in enumerate(ents)}
+    NB = 2 * LB + 1
+    terms = [[] for _ in ents]
+    for (ma, mb, l1, l2, L, M, k, coef) in class_terms(LA, LB):
+        terms[idx[(L, M, k)]].append((coef, (ma + LA) * NB + (mb + LB), LA - l1, LB - l2))
+    blocks = sorted(set((L, k) for (L, M, k) in ents))
+    blk = [(L, k, [idx[(L, M, k)] for M in range(-L, L + 1)]) for (L, k) in blocks]
+    lm = sorted(set((L, M) for (L, M, k) in ents))
+    grp = [(L, [idx[(L, M, k)] for k in range(kmax_of(LA, LB, L) + 1)]) for (L, M) in lm]
+    return ents, terms, blk, grp
+
+
+def emit_eri_header(lmax=ERI_LMAX):
+    classes = [(LA, LB) for LA in range(lmax + 1) for LB in range(LA + 1)]
+    out = ["// Generated by gen_classes.py -- do not edit. Tables of the two-electron kernel: the pair",
+           "// classes' coupling terms, rotation blocks and (L, M) groups, the real Gaunt coefficients of",
+           "// the two-center products, and the coefficients of the Laplacian expansions.",
+           "#pragma once",
+           f"constexpr int kEriLmax = {lmax};",
+           f"constexpr int kEriPairClasses = {len(classes)};",
+           "struct EriTerm { double coef; int e, pa, pb; };",
+           "struct EriGaunt { double g; int I; };"]
+    ent_base, term_off, terms_all, ents_all = [], [0], [], []
+    blk_base, blk_all, grp_base, grp_all = [], [], [], []
+    nw = []
+    for (LA, LB) in classes:
+        ents, terms, blk, grp = eri_class_tables(LA, LB)
+        ent_base.append(len(ents_all))
+        nw.append(len(ents))
+        for e, ts in zip(ents, terms):
+            ents_all.append(e)
+            terms_all += ts
+            term_off.append(len(terms_all))
+        blk_base.append(len(blk_all))
+        blk_all += blk
+        grp_base.append(len(grp_all))
+        grp_all += grp
+    blk_base.append(len(blk_all))
+    grp_base.append(len(grp_all))
+    out.append(f"__device__ const int kEriNW[{len(nw)}] = {{{', '.join(map(str, nw))}}};")
+    out.append(f"__device__ const int kEriEntBase[{len(ent_base)}] = {{{', '.join(map(str, ent_base))}}};")
+    out.append(f"__device__ const int kEriEnt[{len(ents_all)}][3] = {{"
+               + ", ".join(f"{{{L}, {M}, {k}}}" for (L, M, k) in ents_all) + "};")
+    out.append(f"__device__ const int kEriTermOff[{len(term_off)}] = {{{', '.join(map(str, term_off))}}};")
+    out.append(f"__device__ const EriTerm kEriTerm[{len(terms_all)}] = {{"
+               + ", ".join(f"{{{lit(c)}, {e}, {pa}, {pb}}}" for (c, e, pa, pb) in terms_all) + "};")
+    # rotation blocks: (L, k, first index into kEriBlkW); W indices by M = -L..L
+    bw, bhead = [], []
+    for (L, k, ws) in blk_all:
+        bhead.append((L, k, len(bw)))
+        bw += ws
+    out.append(f"__device__ const int kEriBlkBase[{len(blk_base)}] = {{{', '.join(map(str, blk_base))}}};")
+    out.append(f"__device__ const int kEriBlk[{len(bhead)}][3] = {{" + ", ".join(f"{{{a}, {b}, {c}}}" for a, b, c in bhead) + "};")
+    out.append(f"__device__ const int kEriBlkW[{len(bw)}] = {{{', '.join(map(str, bw))}}};")
+    gw, ghead = [], []
+    for (L, ws) in grp_all:
+        ghead.append((L, len(ws), len(gw)))
+        gw += ws
+    out.append(f"__device__ const int kEriGrpBase[{len(grp_base)}] = {{{', '.join(map(str, grp_base))}}};")
+    out.append(f"__device__ const int kEriGrp[{len(ghead)}][3] = {{" + ", ".join(f"{{{a}, {b}, {c}}}" for a, b, c in ghead) + "};")
+    out.append(f"__device__ const int kEriGrpW[{len(gw)}] = {{{', '.join(map(str, gw))}}};")
+    # real Gaunt lists of the two-center products, L1, L2 <= 2 lmax
+    G = real_gaunt_table()
+    L12 = 2 * lmax
+    n12 = (L12 + 1) ** 2
+    goff, gl = [0], []
+    for i1 in range(n12):
+        for i2 in range(n12):
+            for I in range(G.shape[2]):
+                v = G[i1, i2, I]
+                if abs(v) > KEEP:
+                    gl.append((v, I))
+            goff.append(len(gl))
+    out.append(f"constexpr int kEriL12 = {L12};")
+    out.append(f"__device__ const int kEriGOff[{len(goff)}] = {{{', '.join(map(str, goff))}}};")
+    out.append(f"__device__ const EriGaunt kEriG[{len(gl)}] = {{" + ", ".join(f"{{{lit(v)}, {I}}}" for v, I in gl) + "};")
+    kmax = lmax
+    gam = np.zeros((L12 + 1, kmax + 1, kmax + 1))
+    for L in range(L12 + 1):
+        gam[L] = eri_gamma(L, kmax)
+    out.append(f"__device__ const double kEriGamma[{L12 + 1}][{kmax + 1}][{kmax + 1}] = {{"
+               + ", ".join("{" + ", ".join("{" + ", ".join(lit(v) for v in row) + "}" for row in gm) + "}" for gm in gam)
+               + "};")
+    LT = 2 * L12
+    nmax = 2 * kmax + L12
+    Pt = np.zeros((LT + 1, nmax + 1, nmax + 1))
+    for L in range(LT + 1):
+        for n in range(1, nmax + 1):
+            for i, v in enumerate(eri_P(L, n)):
+                Pt[L, n, i] = float(v)
+    out.append(f"constexpr int kEriLT = {LT};")
+    out.append(f"constexpr int kEriNmax = {nmax};")
+    out.append(f"__device__ const double kEriP[{LT + 1}][{nmax + 1}][{nmax + 1}] = {{"
+               + ", ".join("{" + ", ".join("{" + ", ".join(lit(v) for v in row) + "}" for row in pl) + "}" for pl in Pt)
+               + "};")
+    return "\n".join(out) + "\n"
+
+
+def emulate_eri_prim(la, A, a, lb, B, b, lc, C, c, ld, D, d, boys=boys_np):
+    """Unnormalised primitive (ab|cd) block (2la+1, 2lb+1, 2lc+1, 2ld+1) by the tables and steps the
+    two-electron kernel runs, in numpy."""
+    def side(l1, X1, e1, l2, X2, e2):
+        swap = l1 < l2
+        if swap:
+            l1, X1, e1, l2, X2, e2 = l2, X2, e2, l1, X1, e1
+        X1, X2 = np.asarray(X1, float), np.asarray(X2, float)
+        ents, terms, blk, grp = eri_class_tables(l1, l2)
+        ct, st, cp, sp, Rl = frame(X2 - X1)
+        th, ph = math.atan2(st, ct), math.atan2(sp, cp)
+        p = e1 + e2
+        P = (e1 * X1 + e2 * X2) / p
+        K = math.exp(-e1 * e2 / p * Rl * Rl)
+        ta, tb = e2 * Rl / p, -e1 * Rl / p
+        NA, NB = 2 * l1 + 1, 2 * l2 + 1
+        Bx = np.zeros((NA * NB, len(ents)))
+        for w, ts in enumerate(terms):
+            for (coef, e, pa, pb) in ts:
+                Bx[e, w] += coef * ta ** pa * tb ** pb
+
+        def dT(l):
+            c1 = [math.cos(m * th) for m in range(l + 1)]
+            s1 = [math.sin(m * th) for m in range(l + 1)]
+            c2 = [math.cos(m * ph) for m in range(l + 1)]
+            s2 = [math.sin(m * ph) for m in range(l + 1)]
+            J = rot_x90(l)
+            return zrot(l, c2, s2) @ J.T @ zrot(l, c1, s1) @ J
+        for (L, k, ws) in blk:
+            Bx[:, ws] = Bx[:, ws] @ dT(L).T
+        Bx = np.einsum("im,jn,mnw->ijw", dT(l1), dT(l2), Bx.reshape(NA, NB, -1)).reshape(NA * NB, -1)
+        kmax = max(k for (L, M, k) in ents)
+        for (L, ws) in grp:
+            gm = eri_gamma(L, kmax)
+            v = Bx[:, ws].copy()
+            for j in range(len(ws)):
+                Bx[:, ws[j]] = (2 * p) ** (-L) * sum(gm[k][j] * p ** (-(k + j)) * v[:, k] for k in range(j, len(ws)))
+        if swap:
+            Bx = Bx.reshape(NA, NB, -1).transpose(1, 0, 2).reshape(NA * NB, -1)
+        return Bx, ents, p, P, K
+    Bb, eb, p, P, Kab = side(la, A, a, lb, B, b)
+    Bk, ek, q, Q, Kcd = side(lc, C, c, ld, D, d)
+    alpha = p * q / (p + q)
+    R = P - Q
+    T = alpha * float(R @ R)
+    cpre = 2 * math.pi ** 2.5 / (p * q * math.sqrt(p + q))
+    LT = la + lb + lc + ld
+    F = boys(LT, T)
+    S = solid_real(LT, R[None])[0]
+    G = real_gaunt_table()
+    def h(L, n):
+        base = cpre * (-2 * alpha) ** L
+        if n == 0:
+            return base * F[L]
+        return base * alpha ** n * float(np.polyval(np.array(eri_P(L, n), float)[::-1], T)) * math.exp(-T)
+    I = np.zeros((len(eb), len(ek)))
+    for i1, (L1, M1, j1) in enumerate(eb):
+        for i2, (L2, M2, j2) in enumerate(ek):
+            s = 0.0
+            for L in range(abs(L1 - L2), L1 + L2 + 1, 2):
+                kap = (L1 + L2 - L) // 2
+                for M in range(-L, L + 1):
+                    gv = G[L1 * L1 + M1 + L1, L2 * L2 + M2 + L2, L * L + M + L]
+                    if gv != 0.0:
+                        s += gv * S[L * L + M + L] * h(L, j1 + j2 + kap)
+            I[i1, i2] = (-1) ** L2 * s
+    out = Bb @ I @ Bk.T * Kab * Kcd
+    return out.reshape(2 * la + 1, 2 * lb + 1, 2 * lc + 1, 2 * ld + 1)
+
+
 def emit_grad_header(lmax=LMAX_SHELL):
     out = ["// gradient kernel: inverse rotations, gradient matrices of the real solid harmonics, and per class",
            "// the adjoint term tables and the forward-mode nucleus step",
@@ -1154,7 +1414,7 @@ def _write(path, text):
 
 def main(argv):
     """Writes shgo_classes.inc (the path given, default generated/shgo_classes.inc) and, beside it,
-    shgo_rot.inc, shgo_meta.inc, shgo_grad.inc and shgo_cart.inc."""
+    shgo_rot.inc, shgo_meta.inc, shgo_grad.inc, shgo_cart.inc and shgo_eri.inc."""
     out = argv[1] if len(argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)), "generated",
                                                      "shgo_classes.inc")
     cap = None
@@ -1167,6 +1427,7 @@ def main(argv):
     _write(os.path.join(d, "shgo_meta.inc"), emit_meta(cap))
     _write(os.path.join(d, "shgo_grad.inc"), emit_grad_header())
     _write(os.path.join(d, "shgo_cart.inc"), emit_cart_header())
+    _write(os.path.join(d, "shgo_eri.inc"), emit_eri_header())
     return out
 
 

@@ -571,6 +571,58 @@ shgo_status shgo_execute_cartesian(shgo_plan* p, double* out, void* stream) {
   return SHGO_OK;
 }
 
+shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
+                            double* out, void* stream) {
+  if (!ctx) return SHGO_ERR_INVALID_ARG;
+  if (!basis || n_quartets < 0 || (n_quartets > 0 && (!quartets || !out)))
+    return fail(ctx, SHGO_ERR_INVALID_ARG, "null basis, quartets or output, or a negative count");
+  const shgo_nuclei none{0, nullptr, nullptr};
+  std::string err;
+  shgo_status s = shgo_host::validate_inputs(basis, &none, 0.0, &err);
+  if (s != SHGO_OK) return fail(ctx, s, err);
+  std::vector<int64_t> offsets((size_t)n_quartets);
+  int64_t total = 0;
+  for (int64_t q = 0; q < n_quartets; ++q) {
+    int64_t size = 1;
+    for (int i = 0; i < 4; ++i) {
+      const int32_t sh = quartets[4 * q + i];
+      if (sh < 0 || sh >= basis->n_shells) return fail(ctx, SHGO_ERR_INVALID_ARG, "shell index out of range");
+      if (basis->l[sh] > eri_lmax())
+        return fail(ctx, SHGO_ERR_UNSUPPORTED_L,
+                    "the two-electron path takes shells up to l = " + std::to_string(eri_lmax()));
+      size *= 2 * basis->l[sh] + 1;
+    }
+    offsets[(size_t)q] = total;
+    total += size;
+  }
+  if (n_quartets == 0 || basis->n_shells == 0) return SHGO_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
+  // a pair plan of one pair uploads the basis; its pair build computes the primitive weights
+  const int32_t zero = 0;
+  shgo_plan* p = nullptr;
+  s = make_plan(ctx, basis, &none, 0, 1, &zero, &zero, 0.0, 0, &p);
+  if (s != SHGO_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  int32_t* dq = nullptr;
+  int64_t* doff = nullptr;
+  hipError_t e = hipMalloc(&dq, sizeof(int32_t) * 4 * (size_t)n_quartets);
+  if (e == hipSuccess) e = hipMalloc(&doff, sizeof(int64_t) * (size_t)n_quartets);
+  if (e == hipSuccess) e = hipMemcpyAsync(dq, quartets, sizeof(int32_t) * 4 * (size_t)n_quartets, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(doff, offsets.data(), sizeof(int64_t) * (size_t)n_quartets, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    launch_pair_build(p, st);
+    e = launch_eri(p, n_quartets, dq, doff, out, st);
+  }
+  const hipError_t e2 = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = e2;
+  if (dq) (void)hipFree(dq);
+  if (doff) (void)hipFree(doff);
+  shgo_plan_destroy(p);
+  if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("two-electron evaluation failed: ") + hipGetErrorString(e));
+  return SHGO_OK;
+}
+
 shgo_status shgo_plan_autotune(shgo_plan* p, double* out, int32_t rounds, void* stream, double* ms, int32_t* chosen) {
   if (!p || rounds < 1 || rounds > 1000) return SHGO_ERR_INVALID_ARG;
   shgo_context* ctx = p->ctx;

@@ -102,3 +102,20 @@ def test_gradient_model_counts_the_generated_step():
     # the adjoint step does several times the forward step's arithmetic
     gn = bench._gaunt_nnz()
     assert bench.grad_model_flops(3, 3)[0] > 4 * bench.model_flops(3, 3, gn)[0]
+
+
+def test_unique_quartets_cover_each_symmetry_class_once():
+    # eight index permutations relate (ab|cd); the list holds one canonical member of each orbit
+    n = 6
+    q = bench.unique_quartets(n)
+    npair = n * (n + 1) // 2
+    assert len(q) == npair * (npair + 1) // 2
+    canon = set()
+    for a in range(n):
+        for b in range(n):
+            for c in range(n):
+                for d in range(n):
+                    orbit = {(a, b, c, d), (b, a, c, d), (a, b, d, c), (b, a, d, c),
+                             (c, d, a, b), (d, c, a, b), (c, d, b, a), (d, c, b, a)}
+                    canon.add(max(orbit))
+    assert {tuple(map(int, x)) for x in q} == canon

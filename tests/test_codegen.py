@@ -257,3 +257,35 @@ def test_cartesian_route_real_harmonic_coefficients():
         assert np.allclose(M @ C.T, S, rtol=1e-13, atol=1e-13 * np.abs(S).max())
         ref = np.array([xcheck.eval_real_solid(l, *pt) for pt in pts])
         assert np.allclose(M @ C.T, ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+
+
+ERI_LS = [(la, lb, lc, ld) for la in range(3) for lb in range(3) for lc in range(3) for ld in range(3)]
+
+
+@pytest.mark.parametrize("ls", ERI_LS[::3] + [(2, 2, 2, 2), (0, 2, 1, 2)])
+def test_emulated_two_electron_route_against_oracle(ls):
+    # the solid-harmonic two-electron route (pair distributions in the pair frames, rotated to the
+    # lab, the j-transform of |u|^{2k}, Gaunt coupling of the two sides) against the Hermite oracle
+    from oracle import eri
+    rng = np.random.default_rng(sum(l * 3 ** i for i, l in enumerate(ls)))
+    cen = rng.normal(0, 1.0, (4, 3))
+    ex = np.exp(rng.uniform(np.log(0.3), np.log(4.0), 4))
+    args = [x for k in range(4) for x in (ls[k], cen[k], ex[k])]
+    got = gc.emulate_eri_prim(*args)
+    ref = eri.eri_prim_real(*args)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), np.abs(got - ref).max() / np.abs(ref).max()
+
+
+def test_emulated_two_electron_route_degenerate_geometries():
+    # bra pair on one center, ket pair along z, and the two pair centers coinciding (T = 0)
+    from oracle import eri
+    A = np.array([0.3, -0.2, 0.5])
+    C = np.array([0.0, 0.0, -0.4])
+    D = np.array([0.0, 0.0, 0.9])
+    # blocks of odd total l on one center vanish exactly: the scale is the (ss|ss) integral
+    for ls in [(2, 1, 2, 0), (1, 1, 1, 1), (2, 2, 0, 2)]:
+        for cen in ([A, A, C, D], [A, A, A, A]):
+            args = [x for k in range(4) for x in (ls[k], cen[k], (0.9, 1.4, 0.7, 1.1)[k])]
+            got, ref = gc.emulate_eri_prim(*args), eri.eri_prim_real(*args)
+            scale = abs(eri.eri_prim_real(*[0 if i % 3 == 0 else x for i, x in enumerate(args)])[0, 0, 0, 0])
+            assert np.abs(got - ref).max() <= 1e-12 * max(np.abs(ref).max(), scale)
