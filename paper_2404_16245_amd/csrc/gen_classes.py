@@ -1321,10 +1321,7 @@ def emit_grad_header(lmax=LMAX_SHELL):
            "  int16_t src;",
            "  int8_t kind, pa, pb;",
            "};",
-           "template <int L> struct RotInv;",
            "template <int LA, int LB> struct GradClass;"]
-    for l in range(lmax + 1):
-        out.append(emit_rotation_inv(l))
     for l in range(1, lmax + 1):
         g = grad_matrix(l)
         vals = ", ".join(lit(v) for v in g.reshape(-1))
@@ -1345,12 +1342,16 @@ def emit_grad_header(lmax=LMAX_SHELL):
 
 def emit_rotations(lmax=LMAX_SHELL):
     out = ["// Generated by gen_classes.py -- do not edit. Rotation of a real solid-harmonic vector from the",
-           "// pair frame (z along A->B) back to the laboratory frame, D^l(Q)^T = Z(phi) J^T Z(theta) J.",
+           "// pair frame (z along A->B) back to the laboratory frame, D^l(Q)^T = Z(phi) J^T Z(theta) J, and",
+           "// its inverse D^l(Q) (laboratory -> pair frame).",
            "#pragma once",
            "",
-           "template <int L> struct Rot;"]
+           "template <int L> struct Rot;",
+           "template <int L> struct RotInv;"]
     for l in range(lmax + 1):
         out.append(emit_rotation(l))
+    for l in range(lmax + 1):
+        out.append(emit_rotation_inv(l))
     return "\n".join(out) + "\n"
 
 

@@ -3,6 +3,7 @@
 // Boys function (Hobson's theorem, Eq. 3, raises and lowers l).
 #include "shgo_internal.h"
 
+#include "generated/shgo_rot.inc"
 #include "generated/shgo_grad.inc"
 
 namespace shgo_impl {

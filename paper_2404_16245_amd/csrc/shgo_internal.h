@@ -305,6 +305,25 @@ __device__ __forceinline__ bool keep_prim(double a, double b, double R2, double 
   if (!(screen > 0.0)) return true;
   return exp_neg(a * b / (a + b) * R2) > screen;
 }
+// The same decision as keep_prim, without the exponential and the division away from the
+// threshold: with L = -ln(screen), a pair with a b R^2 below (L - d)(a + b) is kept and one above
+// (L + d)(a + b) dropped for certain (d = 1e-9 max(L, 1) is far wider than the rounding of either
+// side); only those in between take keep_prim's own test. lo = L - d, hi = L + d (screen_band).
+struct ScreenBand {
+  double lo, hi;
+};
+__device__ __forceinline__ ScreenBand screen_band(double screen) {
+  if (!(screen > 0.0)) return {0.0, 0.0};
+  const double L = -log(screen), d = 1e-9 * fmax(fabs(L), 1.0);
+  return {L - d, L + d};
+}
+__device__ __forceinline__ bool keep_prim_banded(double a, double b, double R2, double screen, ScreenBand band) {
+  if (!(screen > 0.0)) return true;
+  const double x = a * b * R2, s = a + b;
+  if (x < band.lo * s) return true;
+  if (x > band.hi * s) return false;
+  return keep_prim(a, b, R2, screen);
+}
 
 // Per-lane shell-pair state.
 struct PairState {

@@ -25,28 +25,34 @@ __host__ __device__ constexpr double fact_d(int n) {
   return f;
 }
 
-// Staged stores: the wavefront's 64 blocks (all of one class) leave through LDS a row at a time,
-// consecutive lanes on consecutive entries, then a column at a time for the mirror. Each
-// wavefront has its own stage of 64 (2 l_max + 1) doubles and 64 destination pairs.
-struct OvlStage {
-  double* stg;
-  int64_t* d0;
-  int64_t* d1;
+// The lanes of a pair: lane i of the pair's NA = 2 la + 1 lanes owns row i of its block. With the
+// frame block diagonal, the laboratory block is V = Dt_a S' Dt_b^T (Dt = Rot, the rotation back),
+//   V[i][j] = sum_m Dt_a[i][m + la] S'(m) Dt_b[j][m + lb],
+// so row i is Rot<lb> applied to x[m + lb] = Dt_a[i][m + la] S'(m), and row i of Dt_a is the
+// inverse rotation of the unit vector e_i. The pair's primitive pairs are split over its lanes
+// and summed across them.
+struct OvlSched {
+  int64_t slot_first[kNumClasses + 1];  // class-sorted slots of class c: [slot_first[c], slot_first[c+1])
+  int64_t wave_first[kNumClasses + 1];  // wavefronts of class c: [wave_first[c], wave_first[c+1])
 };
 
-__device__ __forceinline__ void ovl_wave_sync() {
+__host__ __device__ constexpr int ovl_pairs_per_wave(int la) { return 64 / (2 * la + 1); }
+
+__device__ __forceinline__ void stage_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// kStaged: every lane of the wavefront runs this class (inactive lanes, past the last pair, with
-// active = false: no loads, no stores of their own) and the stores go through LDS; otherwise each
-// active lane stores its own block.
-template <int LA, int LB, bool kStaged>
-__device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs& pr, int slot, bool active,
-                                             const OvlStage& sg, double* __restrict__ out) {
-  constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1;
+template <int LA, int LB>
+__device__ __forceinline__ void overlap_rows(const DevBasis& bs, const DevPairs& pr, int64_t slot0, int64_t slot_end,
+                                             double* __restrict__ stg, int64_t* __restrict__ sd,
+                                             double* __restrict__ out) {
+  constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, P = ovl_pairs_per_wave(LA);
+  const int lane = threadIdx.x & 63;
+  const int q = lane / NA, row = lane - q * NA;
+  const int64_t slot = slot0 + q;
+  const bool active = q < P && slot < slot_end;
   PairState ps;
   const int s1 = active ? pr.s1[slot] : 0, s2 = active ? pr.s2[slot] : 0;
 #pragma unroll
@@ -79,178 +85,143 @@ __device__ __forceinline__ void overlap_pair(const DevBasis& bs, const DevPairs&
   for (int m = 0; m <= LB; ++m) sm[m] = 0.0;
   const int64_t o1 = active ? bs.prim_off[s1] : 0, o2 = active ? bs.prim_off[s2] : 0;
   const int K1 = active ? bs.nprim[s1] : 0, K2 = active ? bs.nprim[s2] : 0;
-  for (int i = 0; i < K1; ++i)
-    for (int j = 0; j < K2; ++j) {
-      const double a = bs.expo[o1 + i], b = bs.expo[o2 + j];
-      const double p = a + b, ip = 1.0 / p, mu = a * b * ip;
-      const double pre = bs.w[o1 + i] * bs.w[o2 + j] * exp_neg(mu * R * R) * ip * sqrt(ip);
-      const double ta = b * R * ip, tb = -a * R * ip;
-      double pa[LA + 1], pb[LB + 1], pl[LB + 1];
-      pa[0] = 1.0;
-      pb[0] = 1.0;
-      pl[0] = 1.0;
+  for (int idx = row; idx < K1 * K2; idx += NA) {
+    const int i = idx / K2, j = idx - i * K2;
+    const double a = bs.expo[o1 + i], b = bs.expo[o2 + j];
+    const double p = a + b, ip = 1.0 / p, mu = a * b * ip;
+    const double pre = bs.w[o1 + i] * bs.w[o2 + j] * exp_neg(mu * R * R) * ip * sqrt(ip);
+    const double ta = b * R * ip, tb = -a * R * ip;
+    double pa[LA + 1], pb[LB + 1], pl[LB + 1];
+    pa[0] = 1.0;
+    pb[0] = 1.0;
+    pl[0] = 1.0;
 #pragma unroll
-      for (int k = 1; k <= LA; ++k) pa[k] = pa[k - 1] * ta;
+    for (int k = 1; k <= LA; ++k) pa[k] = pa[k - 1] * ta;
 #pragma unroll
-      for (int k = 1; k <= LB; ++k) {
-        pb[k] = pb[k - 1] * tb;
-        pl[k] = pl[k - 1] * ip;
-      }
-#pragma unroll
-      for (int m = 0; m <= LB; ++m) {
-        double t = 0.0;
-#pragma unroll
-        for (int lam = m; lam <= LB; ++lam) t = fma(cf[m][lam] * pa[LA - lam], pb[LB - lam] * pl[lam], t);
-        sm[m] = fma(pre, t, sm[m]);
-      }
+    for (int k = 1; k <= LB; ++k) {
+      pb[k] = pb[k - 1] * tb;
+      pl[k] = pl[k - 1] * ip;
     }
-  // the frame block (entry (ma + la, mb + lb)), then back to the laboratory frame as for V
-  double V[NA * NB];
 #pragma unroll
-  for (int e = 0; e < NA * NB; ++e) V[e] = 0.0;
+    for (int m = 0; m <= LB; ++m) {
+      double t = 0.0;
 #pragma unroll
-  for (int m = -LB; m <= LB; ++m) V[(m + LA) * NB + (m + LB)] = sm[m < 0 ? -m : m];
+      for (int lam = m; lam <= LB; ++lam) t = fma(cf[m][lam] * pa[LA - lam], pb[LB - lam] * pl[lam], t);
+      sm[m] = fma(pre, t, sm[m]);
+    }
+  }
+  // S'(m) summed over the pair's lanes, in one order on every lane (all lanes take part)
+  double tot[LB + 1];
+#pragma unroll
+  for (int m = 0; m <= LB; ++m) {
+    double t = 0.0;
+    for (int k = 0; k < NA; ++k) t += __shfl(sm[m], (q * NA + k) & 63);
+    tot[m] = t;
+  }
   double cth[LA + 1], sth[LA + 1], cph[LA + 1], sph[LA + 1];
   angles<LA>(ps.ct, ps.st, cth, sth);
   angles<LA>(ps.cp, ps.sp, cph, sph);
+  double y[NA];
 #pragma unroll
-  for (int r = 0; r < NA; ++r) {
-    double v[NB];
+  for (int k = 0; k < NA; ++k) y[k] = k == row ? 1.0 : 0.0;
+  RotInv<LA>::apply(y, cth, sth, cph, sph);  // row `row` of Dt_a
+  double x[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) v[j] = V[r * NB + j];
-    Rot<LB>::apply(v, cth, sth, cph, sph);
+  for (int m = -LB; m <= LB; ++m) x[m + LB] = y[m + LA] * tot[m < 0 ? -m : m];
+  Rot<LB>::apply(x, cth, sth, cph, sph);  // row `row` of the laboratory block
+  // rows through the wavefront's LDS stage: entry (q NA + row) NB + j is pair q's (row, j), so
+  // consecutive lanes then store consecutive columns of one row
+  const int64_t d0 = active ? pr.dst0[slot] : 0, d1 = active ? pr.dst1[slot] : 0;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) V[r * NB + j] = v[j];
+  for (int j = 0; j < NB; ++j) stg[lane * NB + j] = x[j];
+  if (row == 0) {
+    sd[2 * q] = d0;
+    sd[2 * q + 1] = d1;
   }
-#pragma unroll
-  for (int col = 0; col < NB; ++col) {
-    double v[NA];
-#pragma unroll
-    for (int i = 0; i < NA; ++i) v[i] = V[i * NB + col];
-    Rot<LA>::apply(v, cth, sth, cph, sph);
-#pragma unroll
-    for (int i = 0; i < NA; ++i) V[i * NB + col] = v[i];
-  }
-  const int64_t d0 = active ? pr.dst0[slot] : -1, d1 = active ? pr.dst1[slot] : 0;
-  if constexpr (kStaged) {
-    const int lane = threadIdx.x & 63;
-    double* const stg = sg.stg;
-    sg.d0[lane] = d0;
-    sg.d1[lane] = d1;
-    const int64_t n = bs.nbf;
-    // rows i of every block: entry k = p NB + j is block p's (i, j)
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-#pragma unroll
-      for (int j = 0; j < NB; ++j) stg[lane * NB + j] = V[i * NB + j];
-      ovl_wave_sync();
-      for (int k = lane; k < 64 * NB; k += 64) {
-        const int q = k / NB, j = k - q * NB;
-        const int64_t e0 = sg.d0[q], e1 = sg.d1[q];
-        if (e0 < 0) continue;
-        if (pr.full) {
-          if (e0 != e1 || i <= j) out[(e0 + i) * n + e1 + j] = stg[k];
-        } else if (e1 == 0) {
-          out[e0 + i * NB + j] = stg[k];
-        } else {
-          out[e0 + j * NA + i] = stg[k];
-        }
-      }
-      ovl_wave_sync();
-    }
+  stage_sync();
+  const int64_t n = bs.nbf;
+  const int64_t pairs = slot_end - slot0 < P ? slot_end - slot0 : P;
+  for (int k = lane; k < pairs * NA * NB; k += 64) {
+    const int qq = k / (NA * NB), r = (k - qq * NA * NB) / NB, j = k - (qq * NA + r) * NB;
+    const int64_t e0 = sd[2 * qq], e1 = sd[2 * qq + 1];
     if (pr.full) {
-      // the mirror, column col of every block: entry k = p NA + i is block p's (i, col)
-#pragma unroll
-      for (int col = 0; col < NB; ++col) {
-#pragma unroll
-        for (int i = 0; i < NA; ++i) stg[lane * NA + i] = V[i * NB + col];
-        ovl_wave_sync();
-        for (int k = lane; k < 64 * NA; k += 64) {
-          const int q = k / NA, i = k - q * NA;
-          const int64_t e0 = sg.d0[q], e1 = sg.d1[q];
-          if (e0 < 0) continue;
-          if (e0 != e1 || i <= col) out[(e1 + col) * n + e0 + i] = stg[k];
-        }
-        ovl_wave_sync();
-      }
+      if (e0 != e1 || r <= j) out[(e0 + r) * n + e1 + j] = stg[k];
+    } else if (e1 == 0) {
+      out[e0 + r * NB + j] = stg[k];  // the listed orientation (s1, s2), row-major
     }
-    return;
   }
+  stage_sync();
+  if (!active) return;
   if (pr.full) {
-    // the (s1, s2) block and its mirror; a shell with itself writes each entry once per orientation
-    const int64_t n = bs.nbf;
-    for (int i = 0; i < NA; ++i)
-      for (int col = 0; col < NB; ++col)
-        if (d0 != d1 || i <= col) {
-          out[(d0 + i) * n + d1 + col] = V[i * NB + col];
-          out[(d1 + col) * n + d0 + i] = V[i * NB + col];
-        }
-  } else {
-    // the listed orientation: (s1, s2) row-major, or transposed where the listed pair is (s2, s1)
-    for (int i = 0; i < NA; ++i)
-      for (int col = 0; col < NB; ++col) {
-        if (d1 == 0)
-          out[d0 + i * NB + col] = V[i * NB + col];
-        else
-          out[d0 + col * NA + i] = V[i * NB + col];
-      }
+    // the mirror; a shell with itself writes each entry once per orientation
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (d0 != d1 || row <= j) out[(d1 + j) * n + d0 + row] = x[j];
+  } else if (d1 != 0) {
+    // the listed pair is (s2, s1): the transposed block
+#pragma unroll
+    for (int j = 0; j < NB; ++j) out[d0 + j * NA + row] = x[j];
   }
 }
 
-template <int LA, int LB, bool kStaged, int LMAXK>
-__device__ __forceinline__ void overlap_dispatch(int c, const DevBasis& bs, const DevPairs& pr, int slot, bool active,
-                                                 const OvlStage& sg, double* __restrict__ out) {
+template <int LA, int LB, int LMAXK>
+__device__ __forceinline__ void overlap_dispatch(int c, int64_t gw, const DevBasis& bs, const DevPairs& pr,
+                                                 const OvlSched& sc, double* __restrict__ stg, int64_t* __restrict__ sd,
+                                                 double* __restrict__ out) {
   if constexpr (LA <= LMAXK) {
-    if (c == class_id(LA, LB)) {
-      overlap_pair<LA, LB, kStaged>(bs, pr, slot, active, sg, out);
+    constexpr int C = class_id(LA, LB);
+    if (c == C) {
+      const int64_t slot0 = sc.slot_first[C] + (gw - sc.wave_first[C]) * ovl_pairs_per_wave(LA);
+      overlap_rows<LA, LB>(bs, pr, slot0, sc.slot_first[C + 1], stg, sd, out);
       return;
     }
     if constexpr (LB < LA)
-      overlap_dispatch<LA, LB + 1, kStaged, LMAXK>(c, bs, pr, slot, active, sg, out);
+      overlap_dispatch<LA, LB + 1, LMAXK>(c, gw, bs, pr, sc, stg, sd, out);
     else
-      overlap_dispatch<LA + 1, 0, kStaged, LMAXK>(c, bs, pr, slot, active, sg, out);
+      overlap_dispatch<LA + 1, 0, LMAXK>(c, gw, bs, pr, sc, stg, sd, out);
   }
 }
 
-// One thread per class-sorted shell pair in the slots [begin, end) (from k_scatter; s1 has the
-// higher l), whose classes all have la <= LMAXK: the kernel is register-allocated for its largest
-// class only. A wavefront whose active lanes all hold one class (all but those at class
-// boundaries) stores through LDS; the others store lane by lane.
-template <int LMAXK>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_overlap(DevBasis bs, DevPairs pr, int64_t begin, int64_t end, double* __restrict__ out) {
+// The wavefronts of the classes la = LMIN..LMAXK (consecutive class ids), each wavefront on
+// ovl_pairs_per_wave(la) consecutive class-sorted pairs of one class (from k_scatter; s1 has the
+// higher l): the kernel is register-allocated for its largest class only.
+template <int LMIN, int LMAXK>
+__global__ void __launch_bounds__(256) k_overlap(DevBasis bs, DevPairs pr, OvlSched sc, double* __restrict__ out) {
+  constexpr int C0 = class_id(LMIN, 0), C1 = class_id(LMAXK + 1, 0);
   __shared__ double s_stage[4][64 * (2 * LMAXK + 1)];
-  __shared__ int64_t s_d0[4][64], s_d1[4][64];
-  const int w = threadIdx.x >> 6;
-  const OvlStage sg{s_stage[w], s_d0[w], s_d1[w]};
-  const int64_t slot = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = slot < end;
-  const int c = active ? class_id(bs.l[pr.s1[slot]], bs.l[pr.s2[slot]]) : -1;
-  const int c0 = __shfl(c, 0);  // lanes past the last pair come after the active ones
-  if (c0 < 0) return;           // no active lane in this wavefront
-  if (__all(!active || c == c0)) {
-    overlap_dispatch<0, 0, true, LMAXK>(c0, bs, pr, (int)(active ? slot : 0), active, sg, out);
-  } else if (active) {
-    overlap_dispatch<0, 0, false, LMAXK>(c, bs, pr, (int)slot, true, sg, out);
-  }
+  __shared__ int64_t s_dst[4][128];
+  const int64_t gw = sc.wave_first[C0] + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gw >= sc.wave_first[C1]) return;
+  int c = C0;  // the class whose wavefronts hold gw (wave-uniform; static indices only)
+#pragma unroll
+  for (int k = C0 + 1; k < C1; ++k) c += gw >= sc.wave_first[k] ? 1 : 0;
+  overlap_dispatch<LMIN, 0, LMAXK>(c, gw, bs, pr, sc, s_stage[threadIdx.x >> 6], s_dst[threadIdx.x >> 6], out);
 }
 
 }  // namespace
 
-// The class-sorted slots fall into three ranges of la (classes are sorted by id, and the ids of
-// la <= 2, la = 3..4 and la = 5..SHGO_LMAX are contiguous): one launch each, so that the small
-// classes are not register-allocated for the largest block.
+// Three launches over ranges of la (la <= 2, 3..4, 5..SHGO_LMAX), so that the small classes are not
+// register-allocated for the largest block.
 void launch_overlap(const shgo_plan* p, double* out, hipStream_t st) {
-  const int tb = 256;
-  int64_t first[kNumClasses + 1];
-  first[0] = 0;
-  for (int c = 0; c < kNumClasses; ++c) first[c + 1] = first[c] + p->class_cand[c];
-  const int64_t b1 = first[class_id(3, 0)], b2 = first[class_id(5, 0)], b3 = first[kNumClasses];
-  auto grid = [&](int64_t n) { return dim3((unsigned)((n + tb - 1) / tb)); };
-  if (b1 > 0) hipLaunchKernelGGL(k_overlap<2>, grid(b1), dim3(tb), 0, st, p->bs, p->pr, (int64_t)0, b1, out);
-  if (b2 > b1) hipLaunchKernelGGL(k_overlap<4>, grid(b2 - b1), dim3(tb), 0, st, p->bs, p->pr, b1, b2, out);
-  if (b3 > b2)
-    hipLaunchKernelGGL(k_overlap<SHGO_LMAX>, grid(b3 - b2), dim3(tb), 0, st, p->bs, p->pr, b2, b3, out);
+  OvlSched sc;
+  sc.slot_first[0] = 0;
+  sc.wave_first[0] = 0;
+  for (int la = 0, c = 0; la <= SHGO_LMAX; ++la)
+    for (int lb = 0; lb <= la; ++lb, ++c) {
+      const int64_t per = ovl_pairs_per_wave(la);
+      sc.slot_first[c + 1] = sc.slot_first[c] + p->class_cand[c];
+      sc.wave_first[c + 1] = sc.wave_first[c] + (p->class_cand[c] + per - 1) / per;
+    }
+  auto blocks = [&](int c0, int c1) {
+    return dim3((unsigned)((sc.wave_first[c1] - sc.wave_first[c0] + 3) / 4));
+  };
+  constexpr int c3 = class_id(3, 0), c5 = class_id(5, 0);
+  if (sc.wave_first[c3] > 0)
+    hipLaunchKernelGGL((k_overlap<0, 2>), blocks(0, c3), dim3(256), 0, st, p->bs, p->pr, sc, out);
+  if (sc.wave_first[c5] > sc.wave_first[c3])
+    hipLaunchKernelGGL((k_overlap<3, 4>), blocks(c3, c5), dim3(256), 0, st, p->bs, p->pr, sc, out);
+  if (sc.wave_first[kNumClasses] > sc.wave_first[c5])
+    hipLaunchKernelGGL((k_overlap<5, SHGO_LMAX>), blocks(c5, kNumClasses), dim3(256), 0, st, p->bs, p->pr, sc, out);
 }
 
 }  // namespace shgo_impl
