@@ -1166,7 +1166,7 @@ def emit_eri_header(lmax=ERI_LMAX):
            f"constexpr int kEriLmax = {lmax};",
            f"constexpr int kEriPairClasses = {len(classes)};",
            "struct EriTerm { double coef; int e, pa, pb; };",
-           "struct EriGaunt { double g; int I; };"]
+           "struct EriGaunt { double g; int I, h; };  // coefficient, (L, M) index, h-table offset"]
     ent_base, term_off, terms_all, ents_all = [], [0], [], []
     blk_base, blk_all, grp_base, grp_all = [], [], [], []
     nw = []
@@ -1185,6 +1185,8 @@ def emit_eri_header(lmax=ERI_LMAX):
     blk_base.append(len(blk_all))
     grp_base.append(len(grp_all))
     out.append(f"__device__ const int kEriNW[{len(nw)}] = {{{', '.join(map(str, nw))}}};")
+    out.append(f"constexpr int kEriNWHost[{len(nw)}] = {{{', '.join(map(str, nw))}}};  // the same, for the host")
+    out.append(f"constexpr int kEriNwMax = {max(nw)};")
     out.append(f"__device__ const int kEriEntBase[{len(ent_base)}] = {{{', '.join(map(str, ent_base))}}};")
     out.append(f"__device__ const int kEriEnt[{len(ents_all)}][3] = {{"
                + ", ".join(f"{{{L}, {M}, {k}}}" for (L, M, k) in ents_all) + "};")
@@ -1211,16 +1213,20 @@ def emit_eri_header(lmax=ERI_LMAX):
     L12 = 2 * lmax
     n12 = (L12 + 1) ** 2
     goff, gl = [0], []
+    hstride = 2 * lmax + L12 + 1  # orders n = 0..kEriNmax of the h table
     for i1 in range(n12):
         for i2 in range(n12):
+            L1, L2 = math.isqrt(i1), math.isqrt(i2)
             for I in range(G.shape[2]):
                 v = G[i1, i2, I]
                 if abs(v) > KEEP:
-                    gl.append((v, I))
+                    L = math.isqrt(I)
+                    gl.append((v, I, L * hstride + (L1 + L2 - L) // 2))
             goff.append(len(gl))
     out.append(f"constexpr int kEriL12 = {L12};")
     out.append(f"__device__ const int kEriGOff[{len(goff)}] = {{{', '.join(map(str, goff))}}};")
-    out.append(f"__device__ const EriGaunt kEriG[{len(gl)}] = {{" + ", ".join(f"{{{lit(v)}, {I}}}" for v, I in gl) + "};")
+    out.append(f"__device__ const EriGaunt kEriG[{len(gl)}] = {{"
+               + ", ".join(f"{{{lit(v)}, {I}, {h}}}" for v, I, h in gl) + "};")
     kmax = lmax
     gam = np.zeros((L12 + 1, kmax + 1, kmax + 1))
     for L in range(L12 + 1):

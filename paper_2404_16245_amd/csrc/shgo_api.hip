@@ -603,22 +603,10 @@ shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t 
   s = make_plan(ctx, basis, &none, 0, 1, &zero, &zero, 0.0, 0, &p);
   if (s != SHGO_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  int32_t* dq = nullptr;
-  int64_t* doff = nullptr;
-  hipError_t e = hipMalloc(&dq, sizeof(int32_t) * 4 * (size_t)n_quartets);
-  if (e == hipSuccess) e = hipMalloc(&doff, sizeof(int64_t) * (size_t)n_quartets);
-  if (e == hipSuccess) e = hipMemcpyAsync(dq, quartets, sizeof(int32_t) * 4 * (size_t)n_quartets, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(doff, offsets.data(), sizeof(int64_t) * (size_t)n_quartets, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) {
-    launch_pair_build(p, st);
-    e = launch_eri(p, n_quartets, dq, doff, out, st);
-  }
-  const hipError_t e2 = hipStreamSynchronize(st);
-  if (e == hipSuccess) e = e2;
-  if (dq) (void)hipFree(dq);
-  if (doff) (void)hipFree(doff);
+  launch_pair_build(p, st);
+  hipError_t e = run_eri(p, basis, n_quartets, quartets, offsets.data(), out, st);
   shgo_plan_destroy(p);
+  if (e == hipErrorOutOfMemory) return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "no device memory for the two-electron workspace");
   if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("two-electron evaluation failed: ") + hipGetErrorString(e));
   return SHGO_OK;
 }

@@ -15,12 +15,18 @@
 // g the real Gaunt coefficients (the product rule applied to the gradients), and the primitive
 // block is K_ab K_cd B'_bra I B'_ket^T.
 //
-// One wavefront per shell quartet, its lanes over the entries of the LDS matrices; shells up to
-// l = kEriLmax. The tables come from gen_classes.py (generated/shgo_eri.inc).
+// Two launches. k_eri_pairs: one wavefront per distinct shell pair of the quartet list builds B'
+// of each of its primitive pairs once (with p, P and K_ab) into a workspace of pair records.
+// k_eri: one wavefront per shell quartet, its lanes over the entries of the LDS matrices, reads the
+// two pairs' records and forms the two-center matrix and the two products per primitive quartet.
+// Shells up to l = kEriLmax. The tables come from gen_classes.py (generated/shgo_eri.inc).
 #include "shgo_internal.h"
 
 #include "generated/shgo_rot.inc"
 #include "generated/shgo_eri.inc"
+
+#include <unordered_map>
+#include <vector>
 
 namespace shgo_impl {
 namespace {
@@ -28,20 +34,34 @@ namespace {
 constexpr int kEriThreads = 256;
 constexpr int kEriWavesPerGroup = kEriThreads / 64;
 constexpr int kNabMax = (2 * kEriLmax + 1) * (2 * kEriLmax + 1);
-constexpr int kNwMax = 35;  // W entries of the (2, 2) pair class
+constexpr int kNwMax = kEriNwMax;
 constexpr int kNS = (kEriLT + 1) * (kEriLT + 1);
 constexpr int kNH = (kEriLT + 1) * (kEriNmax + 1);
+constexpr int kEriHdr = 8;                                   // p, P (3), K_ab w_a w_b, padding
+constexpr int kNabT = (kNabMax + 1) / 2;                      // 2 x 2 tiles along a block side
+constexpr int kAccPerLane = (kNabT * kNabT + 63) / 64;        // block tiles per lane
+constexpr int kIPerLane = (kNwMax * kNwMax + 63) / 64;        // two-center entries per lane
+static_assert(sizeof(kEriG) / sizeof(kEriG[0]) <= 4096, "Gaunt list offsets take 12 bits");
 
-struct EriLds {  // per-wavefront LDS, in doubles
+struct EriLds {  // per-wavefront LDS of k_eri, in doubles
   static constexpr int BB = 0;
   static constexpr int BK = BB + kNabMax * kNwMax;
   static constexpr int I = BK + kNabMax * kNwMax;
   static constexpr int T = I + kNwMax * kNwMax;
-  static constexpr int ACC = T + kNabMax * kNwMax;
-  static constexpr int SR = ACC + kNabMax * kNabMax;
+  static constexpr int SR = T + kNabMax * kNwMax;
   static constexpr int H = SR + kNS;
   static constexpr int F = H + kNH;
   static constexpr int SIZE = F + kEriLT + 2;
+};
+
+// The distinct pairs of a quartet list and each quartet's pairs; every pointer is device memory.
+struct EriWork {
+  int64_t n_pairs, n_quartets;
+  const int32_t* pairs;     // [n_pairs][2] shells (a, b) of each pair, l_a >= l_b
+  const int64_t* pair_off;  // [n_pairs] first double of the pair's records in rec
+  const int32_t* quart;     // [n_quartets][4] bra pair, ket pair, swaps (1: bra, 2: ket), unused
+  const int64_t* out_off;   // [n_quartets] first double of the quartet's block in out
+  double* rec;              // per primitive pair i Kb + j: kEriHdr doubles, then B' [NAB][NW]
 };
 
 struct Angles {
@@ -70,12 +90,13 @@ __device__ __forceinline__ void rot_dispatch(int L, double* p, const int* idx, i
 }
 
 // Real solid harmonics S^L_M(x, y, z), L <= LM, by the sectoral and vertical recurrences
-// (Racah normalisation), out[L L + M + L].
+// (Racah normalisation), out[L L + M + L]; unrolled, so that the coefficients are constants.
 template <int LM>
-__device__ void solid_harmonics(double x, double y, double z, double* out) {
+__device__ __forceinline__ void solid_harmonics(double x, double y, double z, double* out) {
   const double r2 = x * x + y * y + z * z;
   out[0] = 1.0;
   double sc = 1.0, ss = 0.0;
+#pragma unroll
   for (int l = 0; l < LM; ++l) {
     const double f = l == 0 ? 1.0 : sqrt((2.0 * l + 1.0) / (2.0 * l + 2.0));
     const double nc = f * (x * sc - y * ss), ns = f * (y * sc + x * ss);
@@ -84,10 +105,14 @@ __device__ void solid_harmonics(double x, double y, double z, double* out) {
     out[(l + 1) * (l + 1) + 2 * (l + 1)] = sc;
     out[(l + 1) * (l + 1)] = ss;
   }
+#pragma unroll
   for (int m = 0; m <= LM; ++m)
-    for (int sg = 0; sg < (m == 0 ? 1 : 2); ++sg) {
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+      if (m == 0 && sg == 1) continue;
       const int mm = sg == 0 ? m : -m;
       double prev = 0.0, cur = out[m * m + mm + m];
+#pragma unroll
       for (int l = m; l < LM; ++l) {
         const double den = sqrt((double)((l + m + 1) * (l - m + 1)));
         const double a = (2.0 * l + 1.0) / den, b = sqrt((double)((l + m) * (l - m))) / den;
@@ -97,6 +122,37 @@ __device__ void solid_harmonics(double x, double y, double z, double* out) {
         cur = nxt;
       }
     }
+}
+
+// F_0..F_LT(T), e^{-T} and S^L_M(R), L <= LT, into the wavefront's LDS (one lane)
+template <int LT>
+__device__ __forceinline__ void boys_and_harmonics(double T, const double* R, const double* __restrict__ boys_tab,
+                                                   double* sm) {
+  double row[kBoysRowLoad];
+  const double* __restrict__ r = boys_row_ptr(boys_tab, LT, boys_index(T));
+#pragma unroll
+  for (int u = 0; u < kBoysRowLoad; ++u) row[u] = r[u];
+  double F[LT + 1];
+  boys_row<LT>(T, row, F);
+#pragma unroll
+  for (int u = 0; u <= LT; ++u) sm[EriLds::F + u] = F[u];
+  sm[EriLds::F + kEriLT + 1] = exp_neg(T);
+  solid_harmonics<LT>(R[0], R[1], R[2], sm + EriLds::SR);
+}
+__device__ void boys_and_harmonics_lt(int LT, double T, const double* R, const double* __restrict__ boys_tab,
+                                      double* sm) {
+  static_assert(kEriLT == 8, "the dispatch covers LT = 0..8");
+  switch (LT) {
+    case 0: boys_and_harmonics<0>(T, R, boys_tab, sm); break;
+    case 1: boys_and_harmonics<1>(T, R, boys_tab, sm); break;
+    case 2: boys_and_harmonics<2>(T, R, boys_tab, sm); break;
+    case 3: boys_and_harmonics<3>(T, R, boys_tab, sm); break;
+    case 4: boys_and_harmonics<4>(T, R, boys_tab, sm); break;
+    case 5: boys_and_harmonics<5>(T, R, boys_tab, sm); break;
+    case 6: boys_and_harmonics<6>(T, R, boys_tab, sm); break;
+    case 7: boys_and_harmonics<7>(T, R, boys_tab, sm); break;
+    default: boys_and_harmonics<8>(T, R, boys_tab, sm); break;
+  }
 }
 
 // B' of one primitive pair of class (LA, LB) (LA >= LB) into Bx [NA NB][NW]: coupling terms,
@@ -152,143 +208,209 @@ __device__ void build_side(double* Bx, int cls, int LA, int LB, double ta, doubl
   wave_sync();
 }
 
-__global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, int64_t n_quartets, const int32_t* __restrict__ quartets,
-                                                     const int64_t* __restrict__ offsets,
-                                                     const double* __restrict__ boys_tab, double* __restrict__ out) {
+// One wavefront per distinct pair: B' of each primitive pair, in the pair's records.
+__global__ void __launch_bounds__(kEriThreads) k_eri_pairs(DevBasis bs, EriWork wk) {
+  __shared__ double s_bx[kEriWavesPerGroup][kNabMax * kNwMax];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* const bx = s_bx[wave];
+  for (int64_t u = (int64_t)blockIdx.x * kEriWavesPerGroup + wave; u < wk.n_pairs;
+       u += (int64_t)gridDim.x * kEriWavesPerGroup) {
+    const int sa = wk.pairs[2 * u], sb = wk.pairs[2 * u + 1];
+    const int LA = bs.l[sa], LB = bs.l[sb], cls = class_id(LA, LB);
+    const int n = (2 * LA + 1) * (2 * LB + 1) * kEriNW[cls], stride = kEriHdr + n;
+    PairState ps;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      ps.A[x] = bs.center[3 * sa + x];
+      ps.B[x] = bs.center[3 * sb + x];
+    }
+    frame_of(ps);
+    Angles an;
+    angles<2 * kEriLmax>(ps.ct, ps.st, an.cth, an.sth);
+    angles<2 * kEriLmax>(ps.cp, ps.sp, an.cph, an.sph);
+    const int64_t oa = bs.prim_off[sa], ob = bs.prim_off[sb];
+    const int Ka = bs.nprim[sa], Kb = bs.nprim[sb];
+    for (int i = 0; i < Ka; ++i)
+      for (int j = 0; j < Kb; ++j) {
+        const double a = bs.expo[oa + i], b = bs.expo[ob + j], p = a + b, ip = 1.0 / p;
+        build_side(bx, cls, LA, LB, b * ps.R * ip, -a * ps.R * ip, p, an, lane);
+        double* const rec = wk.rec + wk.pair_off[u] + (int64_t)(i * Kb + j) * stride;
+        if (lane < kEriHdr) {
+          double v = 0.0;
+          if (lane == 0) v = p;
+          else if (lane <= 3) v = (a * ps.A[lane - 1] + b * ps.B[lane - 1]) * ip;
+          else if (lane == 4) v = exp_neg(a * b * ip * ps.R * ps.R) * bs.w[oa + i] * bs.w[ob + j];
+          rec[lane] = v;
+        }
+        for (int t = lane; t < n; t += 64) rec[kEriHdr + t] = bx[t];
+        wave_sync();
+      }
+  }
+}
+
+// One wavefront per quartet: for each bra and ket primitive pair, the Boys values and solid
+// harmonics of P - Q (one lane), the h table, the two-center matrix I, T = B'_bra I and the block
+// K_ab K_cd T B'_ket^T, accumulated in registers (entry lane + 64 k of the pair-ordered block).
+__global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab,
+                                                     double* __restrict__ out) {
   __shared__ double s_lds[kEriWavesPerGroup * EriLds::SIZE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* const sm = s_lds + wave * EriLds::SIZE;
-  const int64_t nw_total = (int64_t)gridDim.x * kEriWavesPerGroup;
-  for (int64_t q = (int64_t)blockIdx.x * kEriWavesPerGroup + wave; q < n_quartets; q += nw_total) {
-    int s[4], l[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      s[i] = quartets[4 * q + i];
-      l[i] = bs.l[s[i]];
-    }
-    // pair classes (higher l first) and whether each listed pair is swapped
-    const bool swb = l[0] < l[1], swk = l[2] < l[3];
-    const int sa = swb ? s[1] : s[0], sb = swb ? s[0] : s[1], sc = swk ? s[3] : s[2], sd = swk ? s[2] : s[3];
+  for (int64_t q = (int64_t)blockIdx.x * kEriWavesPerGroup + wave; q < wk.n_quartets;
+       q += (int64_t)gridDim.x * kEriWavesPerGroup) {
+    const int ub = wk.quart[4 * q], uk = wk.quart[4 * q + 1], fl = wk.quart[4 * q + 2];
+    const int sa = wk.pairs[2 * ub], sb = wk.pairs[2 * ub + 1], sc = wk.pairs[2 * uk], sd = wk.pairs[2 * uk + 1];
     const int LA = bs.l[sa], LB = bs.l[sb], LC = bs.l[sc], LD = bs.l[sd];
     const int cb = class_id(LA, LB), ck = class_id(LC, LD);
     const int NB = 2 * LB + 1, ND = 2 * LD + 1, NAB = (2 * LA + 1) * NB, NCD = (2 * LC + 1) * ND;
     const int NW1 = kEriNW[cb], NW2 = kEriNW[ck], base1 = kEriEntBase[cb], base2 = kEriEntBase[ck];
-    PairState pb, pk;
-#pragma unroll
-    for (int x = 0; x < 3; ++x) {
-      pb.A[x] = bs.center[3 * sa + x];
-      pb.B[x] = bs.center[3 * sb + x];
-      pk.A[x] = bs.center[3 * sc + x];
-      pk.B[x] = bs.center[3 * sd + x];
-    }
-    frame_of(pb);
-    frame_of(pk);
-    Angles anb, ank;
-    angles<2 * kEriLmax>(pb.ct, pb.st, anb.cth, anb.sth);
-    angles<2 * kEriLmax>(pb.cp, pb.sp, anb.cph, anb.sph);
-    angles<2 * kEriLmax>(pk.ct, pk.st, ank.cth, ank.sth);
-    angles<2 * kEriLmax>(pk.cp, pk.sp, ank.cph, ank.sph);
-    for (int i = lane; i < NAB * NCD; i += 64) sm[EriLds::ACC + i] = 0.0;
-    const int64_t oa = bs.prim_off[sa], ob = bs.prim_off[sb], oc = bs.prim_off[sc], od = bs.prim_off[sd];
-    const int Ka = bs.nprim[sa], Kb = bs.nprim[sb], Kc = bs.nprim[sc], Kd = bs.nprim[sd];
+    const int nb = bs.nprim[sa] * bs.nprim[sb], nk = bs.nprim[sc] * bs.nprim[sd];
+    const int strb = kEriHdr + NAB * NW1, strk = kEriHdr + NCD * NW2;
+    const double* const recb = wk.rec + wk.pair_off[ub];
+    const double* const reck = wk.rec + wk.pair_off[uk];
     const int LT = LA + LB + LC + LD;
-    for (int i = 0; i < Ka; ++i)
-      for (int j = 0; j < Kb; ++j) {
-        const double a = bs.expo[oa + i], b = bs.expo[ob + j], p = a + b, ip = 1.0 / p;
-        double P[3];
+    // the lane's two-center entries (class-pair data, the same for every primitive quartet): the
+    // first Gaunt term (12 bits), their count (5), j1 + j2 (3) and the sign (-1)^{L2} (1)
+    uint32_t ient[kIPerLane];
 #pragma unroll
-        for (int x = 0; x < 3; ++x) P[x] = (a * pb.A[x] + b * pb.B[x]) * ip;
-        const double Kab = exp_neg(a * b * ip * pb.R * pb.R) * bs.w[oa + i] * bs.w[ob + j];
-        build_side(sm + EriLds::BB, cb, LA, LB, b * pb.R * ip, -a * pb.R * ip, p, anb, lane);
-        for (int k = 0; k < Kc; ++k)
-          for (int m = 0; m < Kd; ++m) {
-            const double c = bs.expo[oc + k], d = bs.expo[od + m], qq = c + d, iq = 1.0 / qq;
-            double R[3];
-#pragma unroll
-            for (int x = 0; x < 3; ++x) R[x] = P[x] - (c * pk.A[x] + d * pk.B[x]) * iq;
-            const double Kcd = exp_neg(c * d * iq * pk.R * pk.R) * bs.w[oc + k] * bs.w[od + m];
-            build_side(sm + EriLds::BK, ck, LC, LD, d * pk.R * iq, -c * pk.R * iq, qq, ank, lane);
-            const double alpha = p * qq / (p + qq);
-            const double T = alpha * (R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
-            const double cpre = 2.0 * 17.493418327624862846 * ip * iq / sqrt(p + qq);  // 2 pi^{5/2} / (p q sqrt(p+q))
-            if (lane == 0) {
-              double row[kBoysRowLoad];
-              const double* __restrict__ r = boys_row_ptr(boys_tab, kEriLT, boys_index(T));
-#pragma unroll
-              for (int u = 0; u < kBoysRowLoad; ++u) row[u] = r[u];
-              double F[kEriLT + 1];
-              boys_row<kEriLT>(T, row, F);
-#pragma unroll
-              for (int u = 0; u <= kEriLT; ++u) sm[EriLds::F + u] = F[u];
-              sm[EriLds::F + kEriLT + 1] = exp_neg(T);
-              solid_harmonics<kEriLT>(R[0], R[1], R[2], sm + EriLds::SR);
-            }
-            wave_sync();
-            // h[L][n] for L <= LT and the orders n the quartet reaches (at most LT / 2 + LA... <= kEriNmax)
-            for (int it = lane; it < (LT + 1) * (kEriNmax + 1); it += 64) {
-              const int L = it / (kEriNmax + 1), n = it - L * (kEriNmax + 1);
-              double base = cpre;
-              for (int u = 0; u < L; ++u) base *= -2.0 * alpha;
-              double v;
-              if (n == 0) {
-                v = sm[EriLds::F + L];
-              } else {
-                double poly = 0.0;
-                for (int u = n - 1; u >= 0; --u) poly = fma(poly, T, kEriP[L][n][u]);
-                double an = 1.0;
-                for (int u = 0; u < n; ++u) an *= alpha;
-                v = an * poly * sm[EriLds::F + kEriLT + 1];
-              }
-              sm[EriLds::H + it] = base * v;
-            }
-            wave_sync();
-            // two-center matrix I[w1][w2]
-            for (int it = lane; it < NW1 * NW2; it += 64) {
-              const int w1 = it / NW2, w2 = it - w1 * NW2;
-              const int L1 = kEriEnt[base1 + w1][0], M1 = kEriEnt[base1 + w1][1], j1 = kEriEnt[base1 + w1][2];
-              const int L2 = kEriEnt[base2 + w2][0], M2 = kEriEnt[base2 + w2][1], j2 = kEriEnt[base2 + w2][2];
-              const int i12 = (L1 * L1 + M1 + L1) * (kEriL12 + 1) * (kEriL12 + 1) + L2 * L2 + M2 + L2;
-              double sacc = 0.0;
-              for (int t = kEriGOff[i12]; t < kEriGOff[i12 + 1]; ++t) {
-                const EriGaunt G = kEriG[t];
-                int L = 0;
-                while ((L + 1) * (L + 1) <= G.I) ++L;
-                const int n = j1 + j2 + (L1 + L2 - L) / 2;
-                sacc = fma(G.g * sm[EriLds::SR + G.I], sm[EriLds::H + L * (kEriNmax + 1) + n], sacc);
-              }
-              sm[EriLds::I + it] = (L2 & 1) ? -sacc : sacc;
-            }
-            wave_sync();
-            // T = B'_bra I, then ACC += K_ab K_cd T B'_ket^T
-            for (int it = lane; it < NAB * NW2; it += 64) {
-              const int e1 = it / NW2, w2 = it - e1 * NW2;
-              double sacc = 0.0;
-              for (int w1 = 0; w1 < NW1; ++w1)
-                sacc = fma(sm[EriLds::BB + e1 * NW1 + w1], sm[EriLds::I + w1 * NW2 + w2], sacc);
-              sm[EriLds::T + it] = sacc;
-            }
-            wave_sync();
-            const double pre = Kab * Kcd;
-            for (int it = lane; it < NAB * NCD; it += 64) {
-              const int e1 = it / NCD, e2 = it - e1 * NCD;
-              double sacc = 0.0;
-              for (int w2 = 0; w2 < NW2; ++w2)
-                sacc = fma(sm[EriLds::T + e1 * NW2 + w2], sm[EriLds::BK + e2 * NW2 + w2], sacc);
-              sm[EriLds::ACC + it] = fma(pre, sacc, sm[EriLds::ACC + it]);
-            }
-            wave_sync();
-          }
+    for (int k = 0; k < kIPerLane; ++k) {
+      const int it = lane + 64 * k;
+      uint32_t word = 0;
+      if (it < NW1 * NW2) {
+        const int w1 = it / NW2, w2 = it - w1 * NW2;
+        const int L1 = kEriEnt[base1 + w1][0], M1 = kEriEnt[base1 + w1][1], j1 = kEriEnt[base1 + w1][2];
+        const int L2 = kEriEnt[base2 + w2][0], M2 = kEriEnt[base2 + w2][1], j2 = kEriEnt[base2 + w2][2];
+        const int i12 = (L1 * L1 + M1 + L1) * (kEriL12 + 1) * (kEriL12 + 1) + L2 * L2 + M2 + L2;
+        const int g0 = kEriGOff[i12], gn = kEriGOff[i12 + 1] - g0;
+        word = (uint32_t)g0 | (uint32_t)gn << 12 | (uint32_t)(j1 + j2) << 17 | (uint32_t)(L2 & 1) << 20;
       }
-    // the block in the listed order: entry ((i0 N1 + i1) N2 + i2) N3 + i3
-    const int N1 = 2 * l[1] + 1, N2 = 2 * l[2] + 1, N3 = 2 * l[3] + 1;
-    const int64_t o = offsets[q];
-    for (int it = lane; it < NAB * NCD; it += 64) {
-      const int e1 = it / NCD, e2 = it - e1 * NCD;
-      const int ma = e1 / NB, mb = e1 - ma * NB, mc = e2 / ND, md = e2 - mc * ND;
-      const int i0 = swb ? mb : ma, i1 = swb ? ma : mb, i2 = swk ? md : mc, i3 = swk ? mc : md;
-      out[o + ((int64_t)(i0 * N1 + i1) * N2 + i2) * N3 + i3] = sm[EriLds::ACC + it];
+      ient[k] = word;
     }
-    wave_sync();
+    // the block in 2 x 2 tiles (e1, e1 + 1) x (e2, e2 + 1), tile lane + 64 k of nt1 x nt2
+    const int nt1 = (NAB + 1) / 2, nt2 = (NCD + 1) / 2;
+    double acc[kAccPerLane][4];
+#pragma unroll
+    for (int k = 0; k < kAccPerLane; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[k][c] = 0.0;
+    for (int r1 = 0; r1 < nb; ++r1) {
+      const double* const rb = recb + (int64_t)r1 * strb;
+      const double p = rb[0], Kab = rb[4];
+      const double P[3] = {rb[1], rb[2], rb[3]};
+      for (int t = lane; t < NAB * NW1; t += 64) sm[EriLds::BB + t] = rb[kEriHdr + t];
+      for (int r2 = 0; r2 < nk; ++r2) {
+        const double* const rk = reck + (int64_t)r2 * strk;
+        const double qq = rk[0], Kcd = rk[4];
+        const double R[3] = {P[0] - rk[1], P[1] - rk[2], P[2] - rk[3]};
+        for (int t = lane; t < NCD * NW2; t += 64) sm[EriLds::BK + t] = rk[kEriHdr + t];
+        const double alpha = p * qq / (p + qq);
+        const double T = alpha * (R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+        const double cpre = 2.0 * 17.493418327624862846 / (p * qq * sqrt(p + qq));  // 2 pi^{5/2} / (p q sqrt(p+q))
+        if (lane == 0) boys_and_harmonics_lt(LT, T, R, boys_tab, sm);
+        wave_sync();
+        // h[L][n] for L <= LT
+        for (int it = lane; it < (LT + 1) * (kEriNmax + 1); it += 64) {
+          const int L = it / (kEriNmax + 1), n = it - L * (kEriNmax + 1);
+          double base = cpre;
+          for (int u = 0; u < L; ++u) base *= -2.0 * alpha;
+          double v;
+          if (n == 0) {
+            v = sm[EriLds::F + L];
+          } else {
+            double poly = 0.0;
+            for (int u = n - 1; u >= 0; --u) poly = fma(poly, T, kEriP[L][n][u]);
+            double an = 1.0;
+            for (int u = 0; u < n; ++u) an *= alpha;
+            v = an * poly * sm[EriLds::F + kEriLT + 1];
+          }
+          sm[EriLds::H + it] = base * v;
+        }
+        wave_sync();
+        // two-center matrix I[w1][w2]
+#pragma unroll
+        for (int k = 0; k < kIPerLane; ++k) {
+          const int it = lane + 64 * k;
+          if (it < NW1 * NW2) {
+            const uint32_t wd = ient[k];
+            const int g0 = (int)(wd & 4095u), gn = (int)((wd >> 12) & 31u), js = (int)((wd >> 17) & 7u);
+            double sacc = 0.0;
+            for (int t = 0; t < gn; ++t) {
+              const EriGaunt G = kEriG[g0 + t];
+              sacc = fma(G.g * sm[EriLds::SR + G.I], sm[EriLds::H + G.h + js], sacc);
+            }
+            sm[EriLds::I + it] = ((wd >> 20) & 1u) ? -sacc : sacc;
+          }
+        }
+        wave_sync();
+        // T = B'_bra I, in 2 x 2 tiles (rows e1, e1 + 1; columns w2, w2 + 1); reads past the last
+        // row or column stay inside the wavefront's LDS and their results are not stored
+        const int u1 = (NAB + 1) / 2, u2 = (NW2 + 1) / 2;
+        for (int tt = lane; tt < u1 * u2; tt += 64) {
+          const int e1 = 2 * (tt / u2), w2 = 2 * (tt - (tt / u2) * u2);
+          double t00 = 0.0, t01 = 0.0, t10 = 0.0, t11 = 0.0;
+          const double* const b0 = sm + EriLds::BB + e1 * NW1;
+          const double* const ic = sm + EriLds::I + w2;
+          for (int w1 = 0; w1 < NW1; ++w1) {
+            const double x0 = b0[w1], x1 = b0[NW1 + w1], y0 = ic[w1 * NW2], y1 = ic[w1 * NW2 + 1];
+            t00 = fma(x0, y0, t00);
+            t01 = fma(x0, y1, t01);
+            t10 = fma(x1, y0, t10);
+            t11 = fma(x1, y1, t11);
+          }
+          double* const tr = sm + EriLds::T + e1 * NW2 + w2;
+          tr[0] = t00;
+          if (w2 + 1 < NW2) tr[1] = t01;
+          if (e1 + 1 < NAB) {
+            tr[NW2] = t10;
+            if (w2 + 1 < NW2) tr[NW2 + 1] = t11;
+          }
+        }
+        wave_sync();
+        // the block += K_ab K_cd T B'_ket^T
+        const double pre = Kab * Kcd;
+#pragma unroll
+        for (int k = 0; k < kAccPerLane; ++k) {
+          const int tt = lane + 64 * k;
+          if (tt < nt1 * nt2) {
+            const int e1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
+            double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+            const double* const t0 = sm + EriLds::T + e1 * NW2;
+            const double* const k0 = sm + EriLds::BK + e2 * NW2;
+            for (int w2 = 0; w2 < NW2; ++w2) {
+              const double x0 = t0[w2], x1 = t0[NW2 + w2], y0 = k0[w2], y1 = k0[NW2 + w2];
+              s00 = fma(x0, y0, s00);
+              s01 = fma(x0, y1, s01);
+              s10 = fma(x1, y0, s10);
+              s11 = fma(x1, y1, s11);
+            }
+            acc[k][0] = fma(pre, s00, acc[k][0]);
+            acc[k][1] = fma(pre, s01, acc[k][1]);
+            acc[k][2] = fma(pre, s10, acc[k][2]);
+            acc[k][3] = fma(pre, s11, acc[k][3]);
+          }
+        }
+        wave_sync();
+      }
+    }
+    // the block in the listed order: entry ((i0 N1 + i1) N2 + i2) N3 + i3
+    const bool swb = fl & 1, swk = fl & 2;
+    const int N1 = swb ? 2 * LA + 1 : NB, N2 = swk ? ND : 2 * LC + 1, N3 = swk ? 2 * LC + 1 : ND;
+    const int64_t o = wk.out_off[q];
+#pragma unroll
+    for (int k = 0; k < kAccPerLane; ++k) {
+      const int tt = lane + 64 * k;
+      if (tt < nt1 * nt2) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int e1 = 2 * (tt / nt2) + (c >> 1), e2 = 2 * (tt - (tt / nt2) * nt2) + (c & 1);
+          if (e1 < NAB && e2 < NCD) {
+            const int ma = e1 / NB, mb = e1 - ma * NB, mc = e2 / ND, md = e2 - mc * ND;
+            const int i0 = swb ? mb : ma, i1 = swb ? ma : mb, i2 = swk ? md : mc, i3 = swk ? mc : md;
+            out[o + ((int64_t)(i0 * N1 + i1) * N2 + i2) * N3 + i3] = acc[k][c];
+          }
+        }
+      }
+    }
   }
 }
 
@@ -296,14 +418,74 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, int64_t n_quar
 
 int eri_lmax() { return kEriLmax; }
 
-hipError_t launch_eri(const shgo_plan* p, int64_t n_quartets, const int32_t* quartets, const int64_t* offsets,
-                      double* out, hipStream_t st) {
+hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
+                   const int64_t* offsets, double* out, hipStream_t st) {
   if (n_quartets <= 0) return hipSuccess;
-  const int64_t need = (n_quartets + kEriWavesPerGroup - 1) / kEriWavesPerGroup;
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)4 * p->ctx->n_cu));
-  hipLaunchKernelGGL(k_eri, dim3(blocks), dim3(kEriThreads), 0, st, p->bs, n_quartets, quartets, offsets,
-                     p->ctx->boys_tab, out);
-  return hipGetLastError();
+  // the distinct pairs, each with its higher l first (listed order where the l are equal)
+  const int nsh = basis->n_shells;
+  std::unordered_map<int64_t, int32_t> index;
+  std::vector<int32_t> pairs, quart((size_t)4 * n_quartets, 0);
+  std::vector<int64_t> pair_off;
+  int64_t rec_size = 0;
+  auto pair_of = [&](int32_t x, int32_t y, bool& swapped) {
+    swapped = basis->l[x] < basis->l[y];
+    const int32_t a = swapped ? y : x, b = swapped ? x : y;
+    const int64_t key = (int64_t)a * nsh + b;
+    auto it = index.find(key);
+    if (it != index.end()) return it->second;
+    const int32_t u = (int32_t)(pairs.size() / 2);
+    index.emplace(key, u);
+    pairs.push_back(a);
+    pairs.push_back(b);
+    pair_off.push_back(rec_size);
+    const int la = basis->l[a], lb = basis->l[b];
+    rec_size += (int64_t)basis->n_prim[a] * basis->n_prim[b] *
+                (kEriHdr + (2 * la + 1) * (2 * lb + 1) * kEriNWHost[class_id(la, lb)]);
+    return u;
+  };
+  for (int64_t q = 0; q < n_quartets; ++q) {
+    bool sw1 = false, sw2 = false;
+    quart[4 * q] = pair_of(quartets[4 * q], quartets[4 * q + 1], sw1);
+    quart[4 * q + 1] = pair_of(quartets[4 * q + 2], quartets[4 * q + 3], sw2);
+    quart[4 * q + 2] = (sw1 ? 1 : 0) | (sw2 ? 2 : 0);
+  }
+  const int64_t n_pairs = (int64_t)pair_off.size();
+  // one workspace: pairs, pair offsets, quartets, output offsets, records (each 256-byte aligned)
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t b_pairs = up(8 * n_pairs), b_poff = up(8 * n_pairs), b_quart = up(16 * n_quartets),
+                b_ooff = up(8 * n_quartets), b_rec = up(8 * rec_size);
+  char* ws = nullptr;
+  hipError_t e = hipMalloc(&ws, (size_t)(b_pairs + b_poff + b_quart + b_ooff + b_rec));
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);  // the caller's pair build is still in flight
+    return e;
+  }
+  EriWork wk;
+  wk.n_pairs = n_pairs;
+  wk.n_quartets = n_quartets;
+  wk.pairs = (const int32_t*)ws;
+  wk.pair_off = (const int64_t*)(ws + b_pairs);
+  wk.quart = (const int32_t*)(ws + b_pairs + b_poff);
+  wk.out_off = (const int64_t*)(ws + b_pairs + b_poff + b_quart);
+  wk.rec = (double*)(ws + b_pairs + b_poff + b_quart + b_ooff);
+  e = hipMemcpyAsync((void*)wk.pairs, pairs.data(), 8 * n_pairs, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.pair_off, pair_off.data(), 8 * n_pairs, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.quart, quart.data(), 16 * n_quartets, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.out_off, offsets, 8 * n_quartets, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    const int cap = 4 * p->ctx->n_cu;
+    auto grid = [&](int64_t waves) {
+      return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + kEriWavesPerGroup - 1) / kEriWavesPerGroup, cap)));
+    };
+    hipLaunchKernelGGL(k_eri_pairs, grid(n_pairs), dim3(kEriThreads), 0, st, p->bs, wk);
+    hipLaunchKernelGGL(k_eri, grid(n_quartets), dim3(kEriThreads), 0, st, p->bs, wk, p->ctx->boys_tab, out);
+    e = hipGetLastError();
+  }
+  // the host vectors and the workspace live until the stream has finished with them
+  const hipError_t e2 = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = e2;
+  (void)hipFree(ws);
+  return e;
 }
 
 }  // namespace shgo_impl

@@ -464,11 +464,12 @@ void launch_overlap(const shgo_plan* p, double* out, hipStream_t st);
 // up to l = cart_lmax()
 int cart_lmax();
 hipError_t launch_cartesian(const shgo_plan* p, double* out, hipStream_t st);
-// shgo_eri.hip: two-electron blocks of device quartets [n][4] at device offsets; shells up to
-// l = eri_lmax()
+// shgo_eri.hip: two-electron blocks of validated host quartets [n][4] at host offsets into the
+// device buffer out, after the plan's pair build (the primitive weights); allocates its own
+// workspace, waits for the stream and frees it. Shells up to l = eri_lmax()
 int eri_lmax();
-hipError_t launch_eri(const shgo_plan* p, int64_t n_quartets, const int32_t* quartets, const int64_t* offsets,
-                      double* out, hipStream_t st);
+hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
+                   const int64_t* offsets, double* out, hipStream_t st);
 // shgo_grad.hip: validate (launch = false: LDS limits, occupancy) or launch every class present
 shgo_status grad_classes(shgo_plan* p, const GradArgs& ga, hipStream_t st, bool launch);
 
