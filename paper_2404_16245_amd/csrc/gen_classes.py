@@ -1225,8 +1225,12 @@ def emit_eri_header(lmax=ERI_LMAX):
             goff.append(len(gl))
     out.append(f"constexpr int kEriL12 = {L12};")
     out.append(f"__device__ const int kEriGOff[{len(goff)}] = {{{', '.join(map(str, goff))}}};")
-    out.append(f"__device__ const EriGaunt kEriG[{len(gl)}] = {{"
-               + ", ".join(f"{{{lit(v)}, {I}, {h}}}" for v, I, h in gl) + "};")
+    gmax = max(b - a for a, b in zip(goff, goff[1:]))
+    out.append(f"constexpr int kEriGmax = {gmax};  // longest list; kEriG ends with that many zero terms")
+    out.append(f"constexpr int kEriGTerms = {len(gl)};")
+    gl_pad = gl + [(0.0, 0, 0)] * gmax
+    out.append(f"__device__ const EriGaunt kEriG[{len(gl_pad)}] = {{"
+               + ", ".join(f"{{{lit(v)}, {I}, {h}}}" for v, I, h in gl_pad) + "};")
     kmax = lmax
     gam = np.zeros((L12 + 1, kmax + 1, kmax + 1))
     for L in range(L12 + 1):

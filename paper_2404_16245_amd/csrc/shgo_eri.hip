@@ -41,7 +41,8 @@ constexpr int kEriHdr = 8;                                   // p, P (3), K_ab w
 constexpr int kNabT = (kNabMax + 1) / 2;                      // 2 x 2 tiles along a block side
 constexpr int kAccPerLane = (kNabT * kNabT + 63) / 64;        // block tiles per lane
 constexpr int kIPerLane = (kNwMax * kNwMax + 63) / 64;        // two-center entries per lane
-static_assert(sizeof(kEriG) / sizeof(kEriG[0]) <= 4096, "Gaunt list offsets take 12 bits");
+static_assert(kEriGTerms <= 4096 && kEriGmax < 32, "Gaunt list offsets take 12 bits, counts 5");
+static_assert(kNS <= 256 && kNH <= 256, "Gaunt term indices take 8 bits each");
 
 struct EriLds {  // per-wavefront LDS of k_eri, in doubles
   static constexpr int BB = 0;
@@ -127,7 +128,7 @@ __device__ __forceinline__ void solid_harmonics(double x, double y, double z, do
 // F_0..F_LT(T), e^{-T} and S^L_M(R), L <= LT, into the wavefront's LDS (one lane)
 template <int LT>
 __device__ __forceinline__ void boys_and_harmonics(double T, const double* R, const double* __restrict__ boys_tab,
-                                                   double* sm) {
+                                            double* sm) {
   double row[kBoysRowLoad];
   const double* __restrict__ r = boys_row_ptr(boys_tab, LT, boys_index(T));
 #pragma unroll
@@ -139,8 +140,7 @@ __device__ __forceinline__ void boys_and_harmonics(double T, const double* R, co
   sm[EriLds::F + kEriLT + 1] = exp_neg(T);
   solid_harmonics<LT>(R[0], R[1], R[2], sm + EriLds::SR);
 }
-__device__ void boys_and_harmonics_lt(int LT, double T, const double* R, const double* __restrict__ boys_tab,
-                                      double* sm) {
+__device__ void boys_and_harmonics_lt(int LT, double T, const double* R, const double* __restrict__ boys_tab, double* sm) {
   static_assert(kEriLT == 8, "the dispatch covers LT = 0..8");
   switch (LT) {
     case 0: boys_and_harmonics<0>(T, R, boys_tab, sm); break;
@@ -254,6 +254,14 @@ __global__ void __launch_bounds__(kEriThreads) k_eri_pairs(DevBasis bs, EriWork 
 __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab,
                                                      double* __restrict__ out) {
   __shared__ double s_lds[kEriWavesPerGroup * EriLds::SIZE];
+  // the Gaunt terms, shared by the workgroup: coefficient, and (L, M) index | h offset << 8
+  __shared__ double s_gg[kEriGTerms];
+  __shared__ int s_gpk[kEriGTerms];
+  for (int t = threadIdx.x; t < kEriGTerms; t += kEriThreads) {
+    s_gg[t] = kEriG[t].g;
+    s_gpk[t] = kEriG[t].I | kEriG[t].h << 8;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* const sm = s_lds + wave * EriLds::SIZE;
   for (int64_t q = (int64_t)blockIdx.x * kEriWavesPerGroup + wave; q < wk.n_quartets;
@@ -286,6 +294,25 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
       }
       ient[k] = word;
     }
+
+    // the lane's entry of the h table: (L, n) with n <= (LT - L) / 2 (the orders the Gaunt terms
+    // reach), and the coefficients of P_{L,n} (zero above its degree n - 1)
+    int hL = -1, hn = 0;
+    {
+      int it = lane;
+      for (int L = 0; L <= LT && hL < 0; ++L) {
+        const int c = (LT - L) / 2 + 1;
+        if (it < c) {
+          hL = L;
+          hn = it;
+        } else {
+          it -= c;
+        }
+      }
+    }
+    double hp[kEriNmax];
+#pragma unroll
+    for (int u = 0; u < kEriNmax; ++u) hp[u] = hL >= 0 ? kEriP[hL][hn][u] : 0.0;
     // the block in 2 x 2 tiles (e1, e1 + 1) x (e2, e2 + 1), tile lane + 64 k of nt1 x nt2
     const int nt1 = (NAB + 1) / 2, nt2 = (NCD + 1) / 2;
     double acc[kAccPerLane][4];
@@ -308,22 +335,22 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
         const double cpre = 2.0 * 17.493418327624862846 / (p * qq * sqrt(p + qq));  // 2 pi^{5/2} / (p q sqrt(p+q))
         if (lane == 0) boys_and_harmonics_lt(LT, T, R, boys_tab, sm);
         wave_sync();
-        // h[L][n] for L <= LT
-        for (int it = lane; it < (LT + 1) * (kEriNmax + 1); it += 64) {
-          const int L = it / (kEriNmax + 1), n = it - L * (kEriNmax + 1);
+        // h[L][n]: the lane's entry
+        if (hL >= 0) {
           double base = cpre;
-          for (int u = 0; u < L; ++u) base *= -2.0 * alpha;
+          for (int u = 0; u < hL; ++u) base *= -2.0 * alpha;
           double v;
-          if (n == 0) {
-            v = sm[EriLds::F + L];
+          if (hn == 0) {
+            v = sm[EriLds::F + hL];
           } else {
             double poly = 0.0;
-            for (int u = n - 1; u >= 0; --u) poly = fma(poly, T, kEriP[L][n][u]);
+#pragma unroll
+            for (int u = kEriNmax - 1; u >= 0; --u) poly = fma(poly, T, hp[u]);
             double an = 1.0;
-            for (int u = 0; u < n; ++u) an *= alpha;
+            for (int u = 0; u < hn; ++u) an *= alpha;
             v = an * poly * sm[EriLds::F + kEriLT + 1];
           }
-          sm[EriLds::H + it] = base * v;
+          sm[EriLds::H + hL * (kEriNmax + 1) + hn] = base * v;
         }
         wave_sync();
         // two-center matrix I[w1][w2]
@@ -334,9 +361,9 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
             const uint32_t wd = ient[k];
             const int g0 = (int)(wd & 4095u), gn = (int)((wd >> 12) & 31u), js = (int)((wd >> 17) & 7u);
             double sacc = 0.0;
-            for (int t = 0; t < gn; ++t) {
-              const EriGaunt G = kEriG[g0 + t];
-              sacc = fma(G.g * sm[EriLds::SR + G.I], sm[EriLds::H + G.h + js], sacc);
+            for (int t = g0; t < g0 + gn; ++t) {
+              const int pk = s_gpk[t];
+              sacc = fma(s_gg[t] * sm[EriLds::SR + (pk & 255)], sm[EriLds::H + (pk >> 8) + js], sacc);
             }
             sm[EriLds::I + it] = ((wd >> 20) & 1u) ? -sacc : sacc;
           }
