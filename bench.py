@@ -393,6 +393,43 @@ def eri_cpu_baseline(synth, n_sample=200):
             "sample": f"{n_sample} of the unique quartets of the two-electron workload"}
 
 
+def eri_model_flops(basis, quartets):
+    """Model FP64 flops of k_eri over a quartet list, per primitive quartet of pair classes
+    (la, lb), (lc, ld) (each pair with its higher l first): T = B'_bra I (2 NAB NW1 NW2), the block
+    (2 NAB NCD NW2 + 2 NAB NCD), the two-center matrix (3 per Gaunt term of every entry), the h
+    table (per entry L + n + 19), Boys values (16 + 3 LT + 30) and solid harmonics (5 (LT+1)^2),
+    and 30 for the pair geometry. The pair records' build is not counted."""
+    sys.path.insert(0, os.path.join(ROOT, "paper_2404_16245_amd", "csrc"))
+    import gen_classes
+    G = gen_classes.real_gaunt_table()
+    ents = {}
+    for la in range(3):
+        for lb in range(la + 1):
+            ents[(la, lb)] = gen_classes.eri_class_tables(la, lb)[0]
+    gn = (np.abs(G) > gen_classes.KEEP).sum(axis=2)
+    per = {}
+
+    def flops(c1, c2):
+        if (c1, c2) not in per:
+            e1, e2 = ents[c1], ents[c2]
+            nab, ncd = (2 * c1[0] + 1) * (2 * c1[1] + 1), (2 * c2[0] + 1) * (2 * c2[1] + 1)
+            i1 = [L * L + M + L for (L, M, k) in e1]
+            i2 = [L * L + M + L for (L, M, k) in e2]
+            terms = int(gn[np.ix_(i1, i2)].sum())
+            lt = sum(c1) + sum(c2)
+            h = sum(L + n + 19 for L in range(lt + 1) for n in range((lt - L) // 2 + 1))
+            per[(c1, c2)] = (2 * nab * len(e1) * len(e2) + 2 * nab * ncd * len(e2) + 2 * nab * ncd
+                             + 3 * terms + h + 16 + 3 * lt + 30 + 5 * (lt + 1) ** 2 + 30)
+        return per[(c1, c2)]
+    ls, npr = np.asarray(basis.l), np.asarray(basis.nprim)
+    total = 0.0
+    for q in np.asarray(quartets):
+        la, lb, lc, ld = (int(ls[x]) for x in q)
+        c1, c2 = (max(la, lb), min(la, lb)), (max(lc, ld), min(lc, ld))
+        total += float(np.prod(npr[q])) * flops(c1, c2)
+    return total
+
+
 def measure_eri(shgo, synth, torch, steps):
     """Two-electron blocks (ab|cd) of every unique shell quartet of a 10-atom molecule (shells
     s, p, d on each atom, K 1..3), one call per step: the upload of the quartet list, the pair
@@ -403,6 +440,7 @@ def measure_eri(shgo, synth, torch, steps):
     n_int = int(np.prod(2 * ls[q] + 1, axis=1).sum())
     prim = np.asarray(basis.nprim)
     n_prim_q = int(np.prod(prim[q], axis=1).sum())
+    flops = eri_model_flops(basis, q)
     shgo.eri_blocks(basis, q)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -413,7 +451,9 @@ def measure_eri(shgo, synth, torch, steps):
     return {"workload": "every unique quartet of a 10-atom molecule (s, p, d shells, K 1..3), seed 7",
             "n_shells": int(len(ls)), "quartets": int(len(q)), "primitive_quartets": n_prim_q,
             "integrals_per_step": n_int, "ms_per_step": ms, "integrals_per_s": n_int / (ms * 1e-3),
-            "primitive_quartets_per_s": n_prim_q / (ms * 1e-3)}
+            "primitive_quartets_per_s": n_prim_q / (ms * 1e-3), "model_flops_per_step": flops,
+            "fp64_model_tflops": flops / (ms * 1e-3) / 1e12,
+            "fp64_vector_peak_frac": flops / (ms * 1e-3) / FP64_VECTOR_PEAK}
 
 
 def measure_overlap(shgo, synth, torch, steps):
