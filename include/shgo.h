@@ -246,8 +246,10 @@ shgo_status shgo_execute_cartesian(shgo_plan* plan, double* out, void* stream);
  *   out        device, the blocks in quartet order, each (2la+1)(2lb+1)(2lc+1)(2ld+1) doubles
  *              row-major in the listed shell order (a slowest)
  * Shells up to l = 2 (SHGO_ERR_UNSUPPORTED_L otherwise); SHGO_ERR_INVALID_ARG for a shell index
- * out of range; both before any device work. Uploads the basis and the quartets to a workspace of
- * its own, runs on `stream` and waits for it before returning (the workspace is then freed). */
+ * out of range; both before any device work. Uploads the basis, the quartets' distinct shell pairs
+ * and their per-primitive-pair records (the pairs' expansions, built once per pair) to a
+ * workspace of its own (SHGO_ERR_OUT_OF_MEMORY if it cannot be allocated), runs on `stream` and
+ * waits for it before returning (the workspace is then freed). */
 shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
                             double* out, void* stream);
 
