@@ -26,36 +26,41 @@ __device__ __forceinline__ double pow_half_q(double x, int l) {  // x^{(l+3/2)/2
 __device__ __forceinline__ double pow_q(double y, int l) {  // y^{l+3/2}
   return ipow(y, l) * y * sqrt(y);
 }
-// One wavefront per shell: its lanes sum the K^2 terms of the norm (a butterfly leaves the same
-// total on every lane), then lane k writes w_k.
-__device__ void prim_weights_of(const DevBasis& b, int s, int lane) {
-  const int l = b.l[s], K = b.nprim[s];
-  const int64_t o = b.prim_off[s];
-  double dfac = 1.0;
-  for (int i = 2 * l - 1; i > 1; i -= 2) dfac *= i;
-  const double cn = sqrt(ldexp(1.0, l) / (dfac * 5.5683279968317078453));  // pi^{3/2}
+// Eight lanes per shell (eight shells per wavefront): they sum the K^2 terms of the norm (a
+// butterfly inside the group leaves the same total on its eight lanes), then lane k mod 8 writes
+// w_k. Lanes past the last shell take part in the butterfly with nothing to add.
+constexpr int kWeightLanes = 8;
+__device__ void prim_weights_of(const DevBasis& b, int s, int sub) {
+  const bool on = s < b.n_shells;
+  const int l = on ? b.l[s] : 0, K = on ? b.nprim[s] : 0;
+  const int64_t o = on ? b.prim_off[s] : 0;
   double ss = 0.0;
-  for (int t = lane; t < K * K; t += 64) {
+  for (int t = sub; t < K * K; t += kWeightLanes) {
     const int k = t / K, j = t - k * K;
     const double ak = b.expo[o + k], aj = b.expo[o + j];
     ss += b.coef[o + k] * b.coef[o + j] * pow_half_q(2.0 * ak, l) * pow_half_q(2.0 * aj, l) / pow_q(ak + aj, l);
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+  for (int off = kWeightLanes / 2; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+  if (!on) return;
+  double dfac = 1.0;
+  for (int i = 2 * l - 1; i > 1; i -= 2) dfac *= i;
+  const double cn = sqrt(ldexp(1.0, l) / (dfac * 5.5683279968317078453));  // pi^{3/2}
   const double inv = 1.0 / sqrt(ss);
-  for (int k = lane; k < K; k += 64) b.w[o + k] = b.coef[o + k] * cn * pow_half_q(2.0 * b.expo[o + k], l) * inv;
+  for (int k = sub; k < K; k += kWeightLanes) b.w[o + k] = b.coef[o + k] * cn * pow_half_q(2.0 * b.expo[o + k], l) * inv;
 }
 
 
 // Classification in workgroups of 1024 candidates: the key of each candidate, its rank among
 // the workgroup's candidates with the same key (LDS atomics), and one global atomic per
 // (workgroup, key) that reserves the workgroup's range inside the key's bucket. Workgroups from
-// classify_blocks on compute the shells' normalised primitive weights instead, a wavefront per
+// classify_blocks on compute the shells' normalised primitive weights instead, eight lanes per
 // shell (independent work, in the same launch).
 __global__ void __launch_bounds__(kClassifyThreads) k_classify(DevBasis bs, DevPairs pr, int classify_blocks) {
   if ((int)blockIdx.x >= classify_blocks) {
-    const int s = ((int)blockIdx.x - classify_blocks) * (kClassifyThreads / 64) + (int)(threadIdx.x >> 6);
-    if (s < bs.n_shells) prim_weights_of(bs, s, threadIdx.x & 63);
+    const int s = ((int)blockIdx.x - classify_blocks) * (kClassifyThreads / kWeightLanes) +
+                  (int)(threadIdx.x / kWeightLanes);
+    prim_weights_of(bs, s, threadIdx.x % kWeightLanes);
     return;
   }
   __shared__ int hist[kNumKeys];  // counts, then the workgroup's base in each key's bucket
@@ -273,7 +278,7 @@ __global__ void k_fill_f64(double* p, int64_t n) {
 void launch_pair_build(const shgo_plan* p, hipStream_t st) {
   // key_count is zero here: cleared at plan creation and by every k_scan_keys after reading it
   const int cb = (int)((p->n_cand + kClassifyThreads - 1) / kClassifyThreads);
-  const int wb = (int)((p->n_shells + kClassifyThreads / 64 - 1) / (kClassifyThreads / 64));
+  const int wb = (int)((p->n_shells + kClassifyThreads / kWeightLanes - 1) / (kClassifyThreads / kWeightLanes));
   hipLaunchKernelGGL(k_classify, dim3(cb + wb), dim3(kClassifyThreads), 0, st, p->bs, p->pr, cb);
   hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->items, p->queue);
   const int tb = 256;
