@@ -202,6 +202,7 @@ shgo_status plan_host_part(shgo_context* ctx, const shgo_basis* b, const shgo_nu
   p->ctx = ctx;
   p->full = full;
   p->n_shells = b->n_shells;
+  for (int32_t i = 0; i < b->n_shells; ++i) p->max_nprim = std::max(p->max_nprim, b->n_prim[i]);
   p->n_nuc = n->n_nuclei;
   p->screen = screen;
   p->nbf = pc.nbf;

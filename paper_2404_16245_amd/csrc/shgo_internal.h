@@ -404,6 +404,7 @@ struct shgo_plan {
   shgo_context* ctx = nullptr;
   int full = 0;
   int32_t n_shells = 0, n_nuc = 0;
+  int32_t max_nprim = 0;        // the longest contraction of the basis
   int64_t nbf = 0, n_cand = 0, out_size = 0;
   int64_t integrals = 0;        // sum of (2la+1)(2lb+1) over the kept shell pairs
   int64_t kept_pairs = 0;       // shell pairs that keep at least one primitive pair

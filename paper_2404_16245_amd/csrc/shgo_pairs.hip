@@ -26,41 +26,47 @@ __device__ __forceinline__ double pow_half_q(double x, int l) {  // x^{(l+3/2)/2
 __device__ __forceinline__ double pow_q(double y, int l) {  // y^{l+3/2}
   return ipow(y, l) * y * sqrt(y);
 }
-// Eight lanes per shell (eight shells per wavefront): they sum the K^2 terms of the norm (a
-// butterfly inside the group leaves the same total on its eight lanes), then lane k mod 8 writes
-// w_k. Lanes past the last shell take part in the butterfly with nothing to add.
-constexpr int kWeightLanes = 8;
-__device__ void prim_weights_of(const DevBasis& b, int s, int sub) {
+// G lanes per shell (64 / G shells per wavefront; G = 1, 2, 4 or 8 from the plan's longest
+// contraction, so that a lane sums about eight of the K^2 terms of the norm): a butterfly inside
+// the group leaves the same total on its G lanes, then lane k mod G writes w_k. Lanes past the
+// last shell take part in the butterfly with nothing to add.
+constexpr int kWeightLanesMax = 8;
+__host__ __device__ constexpr int weight_lanes(int max_nprim) {
+  return max_nprim * max_nprim <= 8 ? 1 : max_nprim * max_nprim <= 16 ? 2 : max_nprim * max_nprim <= 32 ? 4 : 8;
+}
+__device__ void prim_weights_of(const DevBasis& b, int s, int sub, int G) {
   const bool on = s < b.n_shells;
   const int l = on ? b.l[s] : 0, K = on ? b.nprim[s] : 0;
   const int64_t o = on ? b.prim_off[s] : 0;
   double ss = 0.0;
-  for (int t = sub; t < K * K; t += kWeightLanes) {
+  for (int t = sub; t < K * K; t += G) {
     const int k = t / K, j = t - k * K;
     const double ak = b.expo[o + k], aj = b.expo[o + j];
     ss += b.coef[o + k] * b.coef[o + j] * pow_half_q(2.0 * ak, l) * pow_half_q(2.0 * aj, l) / pow_q(ak + aj, l);
   }
 #pragma unroll
-  for (int off = kWeightLanes / 2; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+  for (int off = kWeightLanesMax / 2; off > 0; off >>= 1)
+    if (off < G) ss += __shfl_xor(ss, off);
   if (!on) return;
   double dfac = 1.0;
   for (int i = 2 * l - 1; i > 1; i -= 2) dfac *= i;
   const double cn = sqrt(ldexp(1.0, l) / (dfac * 5.5683279968317078453));  // pi^{3/2}
   const double inv = 1.0 / sqrt(ss);
-  for (int k = sub; k < K; k += kWeightLanes) b.w[o + k] = b.coef[o + k] * cn * pow_half_q(2.0 * b.expo[o + k], l) * inv;
+  for (int k = sub; k < K; k += G) b.w[o + k] = b.coef[o + k] * cn * pow_half_q(2.0 * b.expo[o + k], l) * inv;
 }
 
 
 // Classification in workgroups of 1024 candidates: the key of each candidate, its rank among
 // the workgroup's candidates with the same key (LDS atomics), and one global atomic per
 // (workgroup, key) that reserves the workgroup's range inside the key's bucket. Workgroups from
-// classify_blocks on compute the shells' normalised primitive weights instead, eight lanes per
-// shell (independent work, in the same launch).
-__global__ void __launch_bounds__(kClassifyThreads) k_classify(DevBasis bs, DevPairs pr, int classify_blocks) {
+// classify_blocks on compute the shells' normalised primitive weights instead, a group of lanes
+// per shell (independent work, in the same launch).
+__global__ void __launch_bounds__(kClassifyThreads) k_classify(DevBasis bs, DevPairs pr, int classify_blocks,
+                                                               int weight_lanes) {
   if ((int)blockIdx.x >= classify_blocks) {
-    const int s = ((int)blockIdx.x - classify_blocks) * (kClassifyThreads / kWeightLanes) +
-                  (int)(threadIdx.x / kWeightLanes);
-    prim_weights_of(bs, s, threadIdx.x % kWeightLanes);
+    const int G = weight_lanes;
+    const int s = ((int)blockIdx.x - classify_blocks) * (kClassifyThreads / G) + (int)(threadIdx.x / G);
+    prim_weights_of(bs, s, threadIdx.x % G, G);
     return;
   }
   __shared__ int hist[kNumKeys];  // counts, then the workgroup's base in each key's bucket
@@ -278,8 +284,9 @@ __global__ void k_fill_f64(double* p, int64_t n) {
 void launch_pair_build(const shgo_plan* p, hipStream_t st) {
   // key_count is zero here: cleared at plan creation and by every k_scan_keys after reading it
   const int cb = (int)((p->n_cand + kClassifyThreads - 1) / kClassifyThreads);
-  const int wb = (int)((p->n_shells + kClassifyThreads / kWeightLanes - 1) / (kClassifyThreads / kWeightLanes));
-  hipLaunchKernelGGL(k_classify, dim3(cb + wb), dim3(kClassifyThreads), 0, st, p->bs, p->pr, cb);
+  const int G = weight_lanes(p->max_nprim);
+  const int wb = (int)((p->n_shells + kClassifyThreads / G - 1) / (kClassifyThreads / G));
+  hipLaunchKernelGGL(k_classify, dim3(cb + wb), dim3(kClassifyThreads), 0, st, p->bs, p->pr, cb, G);
   hipLaunchKernelGGL(k_scan_keys, dim3(1), dim3(1024), 0, st, p->pr, p->meta, p->item_off, p->items, p->queue);
   const int tb = 256;
   hipLaunchKernelGGL(k_scatter, dim3((int)((p->n_cand + tb - 1) / tb)), dim3(tb), 0, st, p->bs, p->pr);
