@@ -38,21 +38,27 @@ constexpr int kNwMax = kEriNwMax;
 constexpr int kNS = (kEriLT + 1) * (kEriLT + 1);
 constexpr int kNH = (kEriLT + 1) * (kEriNmax + 1);
 constexpr int kEriHdr = 8;                                   // p, P (3), K_ab w_a w_b, padding
-constexpr int kNabT = (kNabMax + 1) / 2;                      // 2 x 2 tiles along a block side
-constexpr int kAccPerLane = (kNabT * kNabT + 63) / 64;        // block tiles per lane
-constexpr int kIPerLane = (kNwMax * kNwMax + 63) / 64;        // two-center entries per lane
+// the small instance of k_eri: pair classes up to (2,1), NAB <= 15 and NW <= 20
+constexpr int kNabSmall = 15, kNwSmall = 20;
 static_assert(kEriGTerms <= 4096 && kEriGmax < 32, "Gaunt list offsets take 12 bits, counts 5");
 static_assert(kNS <= 256 && kNH <= 256, "Gaunt term indices take 8 bits each");
 
-struct EriLds {  // per-wavefront LDS of k_eri, in doubles
+// Per-wavefront LDS of k_eri for blocks of at most NABM entries and NWM two-center entries, in
+// doubles. Each region is followed by another of at least NWM doubles (F last, after SR and H),
+// which the 2 x 2 tiles may read past a ragged last row or column without storing the result.
+template <int NABM, int NWM>
+struct EriLds {
   static constexpr int BB = 0;
-  static constexpr int BK = BB + kNabMax * kNwMax;
-  static constexpr int I = BK + kNabMax * kNwMax;
-  static constexpr int T = I + kNwMax * kNwMax;
-  static constexpr int SR = T + kNabMax * kNwMax;
+  static constexpr int BK = BB + NABM * NWM;
+  static constexpr int I = BK + NABM * NWM;
+  static constexpr int T = I + NWM * NWM;
+  static constexpr int SR = T + NABM * NWM;
   static constexpr int H = SR + kNS;
   static constexpr int F = H + kNH;
   static constexpr int SIZE = F + kEriLT + 2;
+  static constexpr int kAccPerLane = (((NABM + 1) / 2) * ((NABM + 1) / 2) + 63) / 64;  // 2 x 2 block tiles per lane
+  static constexpr int kIPerLane = (NWM * NWM + 63) / 64;                               // two-center entries per lane
+  static_assert(kNS + kNH + kEriLT + 2 >= NWM, "room after the T region for the tiles' reads");
 };
 
 // The distinct pairs of a quartet list and each quartet's pairs; every pointer is device memory.
@@ -128,7 +134,7 @@ __device__ __forceinline__ void solid_harmonics(double x, double y, double z, do
 // F_0..F_LT(T), e^{-T} and S^L_M(R), L <= LT, into the wavefront's LDS (one lane)
 template <int LT>
 __device__ __forceinline__ void boys_and_harmonics(double T, const double* R, const double* __restrict__ boys_tab,
-                                            double* sm) {
+                                                   double* fb, double* sr) {
   double row[kBoysRowLoad];
   const double* __restrict__ r = boys_row_ptr(boys_tab, LT, boys_index(T));
 #pragma unroll
@@ -136,22 +142,23 @@ __device__ __forceinline__ void boys_and_harmonics(double T, const double* R, co
   double F[LT + 1];
   boys_row<LT>(T, row, F);
 #pragma unroll
-  for (int u = 0; u <= LT; ++u) sm[EriLds::F + u] = F[u];
-  sm[EriLds::F + kEriLT + 1] = exp_neg(T);
-  solid_harmonics<LT>(R[0], R[1], R[2], sm + EriLds::SR);
+  for (int u = 0; u <= LT; ++u) fb[u] = F[u];
+  fb[kEriLT + 1] = exp_neg(T);
+  solid_harmonics<LT>(R[0], R[1], R[2], sr);
 }
-__device__ void boys_and_harmonics_lt(int LT, double T, const double* R, const double* __restrict__ boys_tab, double* sm) {
+__device__ void boys_and_harmonics_lt(int LT, double T, const double* R, const double* __restrict__ boys_tab, double* fb,
+                                      double* sr) {
   static_assert(kEriLT == 8, "the dispatch covers LT = 0..8");
   switch (LT) {
-    case 0: boys_and_harmonics<0>(T, R, boys_tab, sm); break;
-    case 1: boys_and_harmonics<1>(T, R, boys_tab, sm); break;
-    case 2: boys_and_harmonics<2>(T, R, boys_tab, sm); break;
-    case 3: boys_and_harmonics<3>(T, R, boys_tab, sm); break;
-    case 4: boys_and_harmonics<4>(T, R, boys_tab, sm); break;
-    case 5: boys_and_harmonics<5>(T, R, boys_tab, sm); break;
-    case 6: boys_and_harmonics<6>(T, R, boys_tab, sm); break;
-    case 7: boys_and_harmonics<7>(T, R, boys_tab, sm); break;
-    default: boys_and_harmonics<8>(T, R, boys_tab, sm); break;
+    case 0: boys_and_harmonics<0>(T, R, boys_tab, fb, sr); break;
+    case 1: boys_and_harmonics<1>(T, R, boys_tab, fb, sr); break;
+    case 2: boys_and_harmonics<2>(T, R, boys_tab, fb, sr); break;
+    case 3: boys_and_harmonics<3>(T, R, boys_tab, fb, sr); break;
+    case 4: boys_and_harmonics<4>(T, R, boys_tab, fb, sr); break;
+    case 5: boys_and_harmonics<5>(T, R, boys_tab, fb, sr); break;
+    case 6: boys_and_harmonics<6>(T, R, boys_tab, fb, sr); break;
+    case 7: boys_and_harmonics<7>(T, R, boys_tab, fb, sr); break;
+    default: boys_and_harmonics<8>(T, R, boys_tab, fb, sr); break;
   }
 }
 
@@ -251,9 +258,12 @@ __global__ void __launch_bounds__(kEriThreads) k_eri_pairs(DevBasis bs, EriWork 
 // One wavefront per quartet: for each bra and ket primitive pair, the Boys values and solid
 // harmonics of P - Q (one lane), the h table, the two-center matrix I, T = B'_bra I and the block
 // K_ab K_cd T B'_ket^T, accumulated in registers (entry lane + 64 k of the pair-ordered block).
-__global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab,
-                                                     double* __restrict__ out) {
-  __shared__ double s_lds[kEriWavesPerGroup * EriLds::SIZE];
+template <int NABM, int NWM, int WPE>
+__global__ void __launch_bounds__(kEriThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __restrict__ out) {
+  using Lds = EriLds<NABM, NWM>;
+  constexpr int kAccPerLane = Lds::kAccPerLane, kIPerLane = Lds::kIPerLane;
+  __shared__ double s_lds[kEriWavesPerGroup * Lds::SIZE];
   // the Gaunt terms, shared by the workgroup: coefficient, and (L, M) index | h offset << 8
   __shared__ double s_gg[kEriGTerms];
   __shared__ int s_gpk[kEriGTerms];
@@ -263,7 +273,7 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* const sm = s_lds + wave * EriLds::SIZE;
+  double* const sm = s_lds + wave * Lds::SIZE;
   for (int64_t q = (int64_t)blockIdx.x * kEriWavesPerGroup + wave; q < wk.n_quartets;
        q += (int64_t)gridDim.x * kEriWavesPerGroup) {
     const int ub = wk.quart[4 * q], uk = wk.quart[4 * q + 1], fl = wk.quart[4 * q + 2];
@@ -324,16 +334,16 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
       const double* const rb = recb + (int64_t)r1 * strb;
       const double p = rb[0], Kab = rb[4];
       const double P[3] = {rb[1], rb[2], rb[3]};
-      for (int t = lane; t < NAB * NW1; t += 64) sm[EriLds::BB + t] = rb[kEriHdr + t];
+      for (int t = lane; t < NAB * NW1; t += 64) sm[Lds::BB + t] = rb[kEriHdr + t];
       for (int r2 = 0; r2 < nk; ++r2) {
         const double* const rk = reck + (int64_t)r2 * strk;
         const double qq = rk[0], Kcd = rk[4];
         const double R[3] = {P[0] - rk[1], P[1] - rk[2], P[2] - rk[3]};
-        for (int t = lane; t < NCD * NW2; t += 64) sm[EriLds::BK + t] = rk[kEriHdr + t];
+        for (int t = lane; t < NCD * NW2; t += 64) sm[Lds::BK + t] = rk[kEriHdr + t];
         const double alpha = p * qq / (p + qq);
         const double T = alpha * (R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
         const double cpre = 2.0 * 17.493418327624862846 / (p * qq * sqrt(p + qq));  // 2 pi^{5/2} / (p q sqrt(p+q))
-        if (lane == 0) boys_and_harmonics_lt(LT, T, R, boys_tab, sm);
+        if (lane == 0) boys_and_harmonics_lt(LT, T, R, boys_tab, sm + Lds::F, sm + Lds::SR);
         wave_sync();
         // h[L][n]: the lane's entry
         if (hL >= 0) {
@@ -341,16 +351,16 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
           for (int u = 0; u < hL; ++u) base *= -2.0 * alpha;
           double v;
           if (hn == 0) {
-            v = sm[EriLds::F + hL];
+            v = sm[Lds::F + hL];
           } else {
             double poly = 0.0;
 #pragma unroll
             for (int u = kEriNmax - 1; u >= 0; --u) poly = fma(poly, T, hp[u]);
             double an = 1.0;
             for (int u = 0; u < hn; ++u) an *= alpha;
-            v = an * poly * sm[EriLds::F + kEriLT + 1];
+            v = an * poly * sm[Lds::F + kEriLT + 1];
           }
-          sm[EriLds::H + hL * (kEriNmax + 1) + hn] = base * v;
+          sm[Lds::H + hL * (kEriNmax + 1) + hn] = base * v;
         }
         wave_sync();
         // two-center matrix I[w1][w2]
@@ -363,9 +373,9 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
             double sacc = 0.0;
             for (int t = g0; t < g0 + gn; ++t) {
               const int pk = s_gpk[t];
-              sacc = fma(s_gg[t] * sm[EriLds::SR + (pk & 255)], sm[EriLds::H + (pk >> 8) + js], sacc);
+              sacc = fma(s_gg[t] * sm[Lds::SR + (pk & 255)], sm[Lds::H + (pk >> 8) + js], sacc);
             }
-            sm[EriLds::I + it] = ((wd >> 20) & 1u) ? -sacc : sacc;
+            sm[Lds::I + it] = ((wd >> 20) & 1u) ? -sacc : sacc;
           }
         }
         wave_sync();
@@ -375,8 +385,8 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
         for (int tt = lane; tt < u1 * u2; tt += 64) {
           const int e1 = 2 * (tt / u2), w2 = 2 * (tt - (tt / u2) * u2);
           double t00 = 0.0, t01 = 0.0, t10 = 0.0, t11 = 0.0;
-          const double* const b0 = sm + EriLds::BB + e1 * NW1;
-          const double* const ic = sm + EriLds::I + w2;
+          const double* const b0 = sm + Lds::BB + e1 * NW1;
+          const double* const ic = sm + Lds::I + w2;
           for (int w1 = 0; w1 < NW1; ++w1) {
             const double x0 = b0[w1], x1 = b0[NW1 + w1], y0 = ic[w1 * NW2], y1 = ic[w1 * NW2 + 1];
             t00 = fma(x0, y0, t00);
@@ -384,7 +394,7 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
             t10 = fma(x1, y0, t10);
             t11 = fma(x1, y1, t11);
           }
-          double* const tr = sm + EriLds::T + e1 * NW2 + w2;
+          double* const tr = sm + Lds::T + e1 * NW2 + w2;
           tr[0] = t00;
           if (w2 + 1 < NW2) tr[1] = t01;
           if (e1 + 1 < NAB) {
@@ -401,8 +411,8 @@ __global__ void __launch_bounds__(kEriThreads) k_eri(DevBasis bs, EriWork wk, co
           if (tt < nt1 * nt2) {
             const int e1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
             double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
-            const double* const t0 = sm + EriLds::T + e1 * NW2;
-            const double* const k0 = sm + EriLds::BK + e2 * NW2;
+            const double* const t0 = sm + Lds::T + e1 * NW2;
+            const double* const k0 = sm + Lds::BK + e2 * NW2;
             for (int w2 = 0; w2 < NW2; ++w2) {
               const double x0 = t0[w2], x1 = t0[NW2 + w2], y0 = k0[w2], y1 = k0[NW2 + w2];
               s00 = fma(x0, y0, s00);
@@ -477,6 +487,23 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
     quart[4 * q + 2] = (sw1 ? 1 : 0) | (sw2 ? 2 : 0);
   }
   const int64_t n_pairs = (int64_t)pair_off.size();
+  // the quartets whose two pairs fit the small instance of k_eri first, then the rest
+  auto fits_small = [&](int32_t u) {
+    const int la = basis->l[pairs[2 * u]], lb = basis->l[pairs[2 * u + 1]];
+    return (2 * la + 1) * (2 * lb + 1) <= kNabSmall && kEriNWHost[class_id(la, lb)] <= kNwSmall;
+  };
+  std::vector<int32_t> quart_sorted((size_t)4 * n_quartets);
+  std::vector<int64_t> off_sorted((size_t)n_quartets);
+  int64_t n_small = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int64_t q = 0, k = pass == 0 ? 0 : n_small; q < n_quartets; ++q) {
+      const bool small = fits_small(quart[4 * q]) && fits_small(quart[4 * q + 1]);
+      if (small != (pass == 0)) continue;
+      for (int i = 0; i < 4; ++i) quart_sorted[4 * k + i] = quart[4 * q + i];
+      off_sorted[k] = offsets[q];
+      ++k;
+      if (pass == 0) n_small = k;
+    }
   // one workspace: pairs, pair offsets, quartets, output offsets, records (each 256-byte aligned)
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
   const int64_t b_pairs = up(8 * n_pairs), b_poff = up(8 * n_pairs), b_quart = up(16 * n_quartets),
@@ -497,15 +524,27 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
   wk.rec = (double*)(ws + b_pairs + b_poff + b_quart + b_ooff);
   e = hipMemcpyAsync((void*)wk.pairs, pairs.data(), 8 * n_pairs, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.pair_off, pair_off.data(), 8 * n_pairs, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.quart, quart.data(), 16 * n_quartets, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.out_off, offsets, 8 * n_quartets, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.quart, quart_sorted.data(), 16 * n_quartets, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.out_off, off_sorted.data(), 8 * n_quartets, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
-    const int cap = 4 * p->ctx->n_cu;
-    auto grid = [&](int64_t waves) {
+    auto grid = [&](int64_t waves, int per_cu) {
+      const int64_t cap = (int64_t)4 * per_cu * p->ctx->n_cu;
       return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + kEriWavesPerGroup - 1) / kEriWavesPerGroup, cap)));
     };
-    hipLaunchKernelGGL(k_eri_pairs, grid(n_pairs), dim3(kEriThreads), 0, st, p->bs, wk);
-    hipLaunchKernelGGL(k_eri, grid(n_quartets), dim3(kEriThreads), 0, st, p->bs, wk, p->ctx->boys_tab, out);
+    hipLaunchKernelGGL(k_eri_pairs, grid(n_pairs, 1), dim3(kEriThreads), 0, st, p->bs, wk);
+    // the small instance: 12 KB of matrices per wavefront, two workgroups and wavefronts per SIMD;
+    // the large one (pair class (2,2) on either side): 32 KB, one
+    EriWork ws_small = wk, ws_large = wk;
+    ws_small.n_quartets = n_small;
+    ws_large.n_quartets = n_quartets - n_small;
+    ws_large.quart = wk.quart + 4 * n_small;
+    ws_large.out_off = wk.out_off + n_small;
+    if (ws_small.n_quartets > 0)
+      hipLaunchKernelGGL((k_eri<kNabSmall, kNwSmall, 2>), grid(ws_small.n_quartets, 2), dim3(kEriThreads), 0, st, p->bs,
+                         ws_small, p->ctx->boys_tab, out);
+    if (ws_large.n_quartets > 0)
+      hipLaunchKernelGGL((k_eri<kNabMax, kNwMax, 1>), grid(ws_large.n_quartets, 1), dim3(kEriThreads), 0, st, p->bs,
+                         ws_large, p->ctx->boys_tab, out);
     e = hipGetLastError();
   }
   // the host vectors and the workspace live until the stream has finished with them
