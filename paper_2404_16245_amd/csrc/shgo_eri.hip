@@ -25,6 +25,8 @@
 #include "generated/shgo_rot.inc"
 #include "generated/shgo_eri.inc"
 
+#include <algorithm>
+#include <cmath>
 #include <unordered_map>
 #include <vector>
 
@@ -458,8 +460,11 @@ int eri_lmax() { return kEriLmax; }
 hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
                    const int64_t* offsets, double* out, hipStream_t st) {
   if (n_quartets <= 0) return hipSuccess;
-  // the distinct pairs, each with its higher l first (listed order where the l are equal)
+  // the distinct pairs, each with its higher l first (listed order where the l are equal); a
+  // dense index of the n_shells^2 ordered pairs where that is small, else a hash map
   const int nsh = basis->n_shells;
+  const bool dense = (int64_t)nsh * nsh <= ((int64_t)1 << 22);
+  std::vector<int32_t> dense_index(dense ? (size_t)nsh * nsh : 0, -1);
   std::unordered_map<int64_t, int32_t> index;
   std::vector<int32_t> pairs, quart((size_t)4 * n_quartets, 0);
   std::vector<int64_t> pair_off;
@@ -468,10 +473,17 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
     swapped = basis->l[x] < basis->l[y];
     const int32_t a = swapped ? y : x, b = swapped ? x : y;
     const int64_t key = (int64_t)a * nsh + b;
-    auto it = index.find(key);
-    if (it != index.end()) return it->second;
+    if (dense) {
+      if (dense_index[(size_t)key] >= 0) return dense_index[(size_t)key];
+    } else {
+      auto it = index.find(key);
+      if (it != index.end()) return it->second;
+    }
     const int32_t u = (int32_t)(pairs.size() / 2);
-    index.emplace(key, u);
+    if (dense)
+      dense_index[(size_t)key] = u;
+    else
+      index.emplace(key, u);
     pairs.push_back(a);
     pairs.push_back(b);
     pair_off.push_back(rec_size);
@@ -492,18 +504,37 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
     const int la = basis->l[pairs[2 * u]], lb = basis->l[pairs[2 * u + 1]];
     return (2 * la + 1) * (2 * lb + 1) <= kNabSmall && kEriNWHost[class_id(la, lb)] <= kNwSmall;
   };
+  // and within each, the costliest first (primitive quartets times the two products' sizes, in
+  // buckets of a quarter octave: a counting sort), so that the wavefronts striding over the list
+  // take the long quartets early
+  constexpr int kCostBuckets = 256;
+  auto bucket = [&](int64_t q) {
+    const int32_t ub = quart[4 * q], uk = quart[4 * q + 1];
+    const int a = pairs[2 * ub], b = pairs[2 * ub + 1], c = pairs[2 * uk], d = pairs[2 * uk + 1];
+    const int nab = (2 * basis->l[a] + 1) * (2 * basis->l[b] + 1), ncd = (2 * basis->l[c] + 1) * (2 * basis->l[d] + 1);
+    const int nw1 = kEriNWHost[class_id(basis->l[a], basis->l[b])], nw2 = kEriNWHost[class_id(basis->l[c], basis->l[d])];
+    const double cost = (double)basis->n_prim[a] * basis->n_prim[b] * basis->n_prim[c] * basis->n_prim[d] *
+                        (double)(nw1 * nw2 + nab * nw2 + nab * ncd + 200);
+    const int bk = (int)(4.0 * std::log2(cost));
+    return std::min(kCostBuckets - 1, std::max(0, bk));
+  };
+  std::vector<int32_t> qkey((size_t)n_quartets);  // bin-major: small quartets, then by falling cost
+  std::vector<int64_t> count(2 * kCostBuckets + 1, 0);
+  int64_t n_small = 0;
+  for (int64_t q = 0; q < n_quartets; ++q) {
+    const bool small = fits_small(quart[4 * q]) && fits_small(quart[4 * q + 1]);
+    n_small += small;
+    qkey[(size_t)q] = (small ? 0 : kCostBuckets) + (kCostBuckets - 1 - bucket(q));
+    ++count[(size_t)qkey[(size_t)q] + 1];
+  }
+  for (int k = 0; k < 2 * kCostBuckets; ++k) count[(size_t)k + 1] += count[(size_t)k];
   std::vector<int32_t> quart_sorted((size_t)4 * n_quartets);
   std::vector<int64_t> off_sorted((size_t)n_quartets);
-  int64_t n_small = 0;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int64_t q = 0, k = pass == 0 ? 0 : n_small; q < n_quartets; ++q) {
-      const bool small = fits_small(quart[4 * q]) && fits_small(quart[4 * q + 1]);
-      if (small != (pass == 0)) continue;
-      for (int i = 0; i < 4; ++i) quart_sorted[4 * k + i] = quart[4 * q + i];
-      off_sorted[k] = offsets[q];
-      ++k;
-      if (pass == 0) n_small = k;
-    }
+  for (int64_t q = 0; q < n_quartets; ++q) {
+    const int64_t k = count[(size_t)qkey[(size_t)q]]++;
+    for (int i = 0; i < 4; ++i) quart_sorted[4 * k + i] = quart[4 * q + i];
+    off_sorted[k] = offsets[q];
+  }
   // one workspace: pairs, pair offsets, quartets, output offsets, records (each 256-byte aligned)
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
   const int64_t b_pairs = up(8 * n_pairs), b_poff = up(8 * n_pairs), b_quart = up(16 * n_quartets),
