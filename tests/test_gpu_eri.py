@@ -1,7 +1,8 @@
 """Two-electron blocks (ab|cd) through the C ABI (shgo_eri_blocks) against the Hermite oracle
 (oracle/eri.py), element by element: every ordered combination of s, p and d shells (both orders
 inside each pair, so the kernel's swaps are covered), contracted shells of a synthetic molecule
-with shells on one center, more quartets than the grid has wavefronts, and the error paths.
+with shells on one center, more quartets than the grid has wavefronts, a basis of more than 2048
+shells (the host's hashed pair index), and the error paths.
 Bar as for the nuclear attraction: 1e-13 + 1e-11 |ref|."""
 import itertools
 
@@ -99,3 +100,19 @@ def test_empty_and_errors(shgo):
     with pytest.raises(shgo.ShgoError) as e:
         shgo.eri_blocks(b, np.array([[0, 0, len(b.l), 0]], np.int32))
     assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
+
+
+def test_many_shells_hashed_pair_index(shgo):
+    # more than 2048 shells: the host indexes the distinct pairs with a hash map instead of the
+    # dense n_shells^2 table; a few hundred quartets, some sharing pairs in both orders
+    b, _ = synth.molecule(seed=17, n_atoms=700, box=30.0, ls=(0, 1, 2), kmax=1)
+    assert len(b.l) > 2048
+    rng = np.random.default_rng(18)
+    q = rng.integers(0, len(b.l), (300, 4)).astype(np.int32)
+    q[::7] = q[::7][:, [1, 0, 3, 2]]
+    q = np.vstack([q, q[:20][:, [2, 3, 0, 1]]]).astype(np.int32)
+    got = shgo.eri_blocks(b, q).cpu().numpy()
+    sizes = np.prod(2 * np.asarray(b.l)[q] + 1, axis=1)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    for k in rng.choice(len(q), 40, replace=False):
+        assert_parity(got[offs[k]:offs[k + 1]], eri.eri_block(b, *q[k]).ravel(), f"quartet {k}")
