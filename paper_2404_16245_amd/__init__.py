@@ -583,10 +583,10 @@ def eri_blocks(basis, quartets, device=0, stream=None):
     ctx = context(device)
     q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
     hb = _HostBasis(basis)
-    ls = np.asarray(basis.l)
+    dim = 2 * np.asarray(basis.l, dtype=np.int64) + 1
     # out-of-range indices are left for the library to reject (it writes nothing then)
-    valid = len(q) and q.min() >= 0 and q.max() < len(ls)
-    size = int(np.prod(2 * ls[q] + 1, axis=1).sum()) if valid else 0
+    valid = len(q) and q.min() >= 0 and q.max() < len(dim)
+    size = int((dim[q[:, 0]] * dim[q[:, 1]] * dim[q[:, 2]] * dim[q[:, 3]]).sum()) if valid else 0
     out = torch.empty(max(size, 1), dtype=torch.float64, device=f"cuda:{device}")
     _check(lib, ctx, lib.shgo_eri_blocks(ctx, ctypes.byref(hb.struct), int(len(q)), q.ctypes.data,
                                          out.data_ptr(), _stream_handle(stream)))

@@ -26,7 +26,6 @@
 #include "generated/shgo_eri.inc"
 
 #include <algorithm>
-#include <cmath>
 #include <unordered_map>
 #include <vector>
 
@@ -513,10 +512,11 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
     const int a = pairs[2 * ub], b = pairs[2 * ub + 1], c = pairs[2 * uk], d = pairs[2 * uk + 1];
     const int nab = (2 * basis->l[a] + 1) * (2 * basis->l[b] + 1), ncd = (2 * basis->l[c] + 1) * (2 * basis->l[d] + 1);
     const int nw1 = kEriNWHost[class_id(basis->l[a], basis->l[b])], nw2 = kEriNWHost[class_id(basis->l[c], basis->l[d])];
-    const double cost = (double)basis->n_prim[a] * basis->n_prim[b] * basis->n_prim[c] * basis->n_prim[d] *
-                        (double)(nw1 * nw2 + nab * nw2 + nab * ncd + 200);
-    const int bk = (int)(4.0 * std::log2(cost));
-    return std::min(kCostBuckets - 1, std::max(0, bk));
+    const uint64_t cost = (uint64_t)basis->n_prim[a] * basis->n_prim[b] * basis->n_prim[c] * basis->n_prim[d] *
+                          (uint64_t)(nw1 * nw2 + nab * nw2 + nab * ncd + 200);
+    const int oct = 63 - __builtin_clzll(cost);                                     // floor(log2 cost)
+    const int quarter = oct >= 2 ? (int)((cost >> (oct - 2)) & 3u) : 0;             // the next two bits
+    return std::min(kCostBuckets - 1, 4 * oct + quarter);
   };
   std::vector<int32_t> qkey((size_t)n_quartets);  // bin-major: small quartets, then by falling cost
   std::vector<int64_t> count(2 * kCostBuckets + 1, 0);
