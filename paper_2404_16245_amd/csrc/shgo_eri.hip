@@ -15,11 +15,13 @@
 // g the real Gaunt coefficients (the product rule applied to the gradients), and the primitive
 // block is K_ab K_cd B'_bra I B'_ket^T.
 //
-// Two launches. k_eri_pairs: one wavefront per distinct shell pair of the quartet list builds B'
-// of each of its primitive pairs once (with p, P and K_ab) into a workspace of pair records.
-// k_eri: one wavefront per shell quartet, its lanes over the entries of the LDS matrices, reads the
-// two pairs' records and forms the two-center matrix and the two products per primitive quartet.
-// Shells up to l = kEriLmax. The tables come from gen_classes.py (generated/shgo_eri.inc).
+// k_eri_pairs: one wavefront per distinct shell pair of the quartet list builds B' of each of its
+// primitive pairs once (with p, P and K_ab) into a workspace of pair records. k_eri: one wavefront
+// per shell quartet, its lanes over the entries of the LDS matrices, reads the two pairs' records
+// and forms the two-center matrix and the two products per primitive quartet; it runs as two
+// instances sized for their quartets' matrices (pairs up to (2,1), and the rest), each over its
+// quartets costliest first. Shells up to l = kEriLmax. The tables come from gen_classes.py
+// (generated/shgo_eri.inc).
 #include "shgo_internal.h"
 
 #include "generated/shgo_rot.inc"
@@ -258,7 +260,9 @@ __global__ void __launch_bounds__(kEriThreads) k_eri_pairs(DevBasis bs, EriWork 
 
 // One wavefront per quartet: for each bra and ket primitive pair, the Boys values and solid
 // harmonics of P - Q (one lane), the h table, the two-center matrix I, T = B'_bra I and the block
-// K_ab K_cd T B'_ket^T, accumulated in registers (entry lane + 64 k of the pair-ordered block).
+// K_ab K_cd T B'_ket^T, accumulated in registers (2 x 2 tiles lane + 64 k of the pair-ordered
+// block). NABM and NWM bound the quartet's block and two-center entries per side; WPE is the
+// occupancy (wavefronts per SIMD) the instance is compiled for.
 template <int NABM, int NWM, int WPE>
 __global__ void __launch_bounds__(kEriThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __restrict__ out) {
