@@ -2,7 +2,8 @@
 (oracle/eri.py), element by element: every ordered combination of s, p and d shells (both orders
 inside each pair, so the kernel's swaps are covered), contracted shells of a synthetic molecule
 with shells on one center, more quartets than the grid has wavefronts, a basis of more than 2048
-shells (the host's hashed pair index), and the error paths.
+shells (the host's hashed pair index), the error paths, and the bench's own call (every unique
+quartet of its 10-atom molecule) on a sample.
 Bar as for the nuclear attraction: 1e-13 + 1e-11 |ref|."""
 import itertools
 
@@ -116,3 +117,25 @@ def test_many_shells_hashed_pair_index(shgo):
     offs = np.concatenate([[0], np.cumsum(sizes)])
     for k in rng.choice(len(q), 40, replace=False):
         assert_parity(got[offs[k]:offs[k + 1]], eri.eri_block(b, *q[k]).ravel(), f"quartet {k}")
+
+
+def test_bench_workload_sampled(shgo):
+    # the call bench.py times: every unique quartet of the 10-atom s/p/d molecule (108,345 quartets,
+    # both kernel instances, the cost ordering at scale), checked on a sample: the costliest
+    # quartets, quartets with a (d,d) pair and without, and random ones
+    import bench
+    b, _ = bench.eri_workload(synth)
+    q = bench.unique_quartets(len(b.l))
+    got = shgo.eri_blocks(b, q).cpu().numpy()
+    ls, npr = np.asarray(b.l), np.asarray(b.nprim)
+    dim = 2 * ls + 1
+    sizes = dim[q[:, 0]] * dim[q[:, 1]] * dim[q[:, 2]] * dim[q[:, 3]]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    assert got.shape == (offs[-1],)
+    rng = np.random.default_rng(21)
+    dd = ((ls[q[:, 0]] == 2) & (ls[q[:, 1]] == 2)) | ((ls[q[:, 2]] == 2) & (ls[q[:, 3]] == 2))
+    cost = np.prod(npr[q], axis=1) * sizes
+    pick = np.concatenate([np.argsort(-cost)[:15], rng.choice(np.flatnonzero(dd), 20, replace=False),
+                           rng.choice(np.flatnonzero(~dd), 20, replace=False), rng.choice(len(q), 20, replace=False)])
+    for k in pick:
+        assert_parity(got[offs[k]:offs[k + 1]], eri.eri_block(b, *q[k]).ravel(), f"quartet {k} {q[k]}")
