@@ -244,7 +244,8 @@ hipError_t cart_class(const shgo_plan* p, double* out, hipStream_t st) {
       hipSuccess)
     per_cu = 1;
   const int64_t need = (p->class_cand[c] + kCartWavesPerGroup - 1) / kCartWavesPerGroup;
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)std::max(1, per_cu) * p->ctx->n_cu));
+  // eight rounds of resident workgroups, which the hardware balances over the pairs' uneven costs
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)8 * std::max(1, per_cu) * p->ctx->n_cu));
   hipLaunchKernelGGL((k_cart<LA, LB>), dim3(blocks), dim3(kCartThreads), 0, st, p->bs, p->pr, p->nuc, p->n_nuc,
                      p->ctx->boys_tab, out);
   return hipGetLastError();
