@@ -394,11 +394,12 @@ def eri_cpu_baseline(synth, n_sample=200):
 
 
 def eri_model_flops(basis, quartets):
-    """Model FP64 flops of k_eri over a quartet list, per primitive quartet of pair classes
-    (la, lb), (lc, ld) (each pair with its higher l first): T = B'_bra I (2 NAB NW1 NW2), the block
-    (2 NAB NCD NW2 + 2 NAB NCD), the two-center matrix (3 per Gaunt term of every entry), the h
-    table (per entry L + n + 19), Boys values (16 + 3 LT + 30) and solid harmonics (5 (LT+1)^2),
-    and 30 for the pair geometry. The pair records' build is not counted."""
+    """Model FP64 flops of k_eri over a quartet list of pair classes (la, lb), (lc, ld) (each pair
+    with its higher l first). Per primitive quartet: Y += K_cd I B'_ket^T (2 NW1 NW2 NCD + 2 NW1 NCD),
+    the two-center matrix (3 per Gaunt term of every entry), the h table (per entry L + n + 19),
+    Boys values (16 + 3 LT + 30) and solid harmonics (5 (LT+1)^2), and 30 for the pair geometry.
+    Per bra primitive pair: the block += K_ab B'_bra Y (2 NAB NW1 NCD + 2 NAB NCD). The pair
+    records' build is not counted."""
     sys.path.insert(0, os.path.join(ROOT, "paper_2404_16245_amd", "csrc"))
     import gen_classes
     G = gen_classes.real_gaunt_table()
@@ -418,15 +419,18 @@ def eri_model_flops(basis, quartets):
             terms = int(gn[np.ix_(i1, i2)].sum())
             lt = sum(c1) + sum(c2)
             h = sum(L + n + 19 for L in range(lt + 1) for n in range((lt - L) // 2 + 1))
-            per[(c1, c2)] = (2 * nab * len(e1) * len(e2) + 2 * nab * ncd * len(e2) + 2 * nab * ncd
-                             + 3 * terms + h + 16 + 3 * lt + 30 + 5 * (lt + 1) ** 2 + 30)
+            nw1, nw2 = len(e1), len(e2)
+            per[(c1, c2)] = (2 * nw1 * nw2 * ncd + 2 * nw1 * ncd + 3 * terms + h + 16 + 3 * lt + 30
+                             + 5 * (lt + 1) ** 2 + 30, 2 * nab * nw1 * ncd + 2 * nab * ncd)
         return per[(c1, c2)]
     ls, npr = np.asarray(basis.l), np.asarray(basis.nprim)
     total = 0.0
     for q in np.asarray(quartets):
         la, lb, lc, ld = (int(ls[x]) for x in q)
         c1, c2 = (max(la, lb), min(la, lb)), (max(lc, ld), min(lc, ld))
-        total += float(np.prod(npr[q])) * flops(c1, c2)
+        f_pq, f_bra = flops(c1, c2)
+        nb = float(npr[q[0]] * npr[q[1]])
+        total += nb * float(npr[q[2]] * npr[q[3]]) * f_pq + nb * f_bra
     return total
 
 

@@ -18,9 +18,9 @@
 // k_eri_pairs: one wavefront per distinct shell pair of the quartet list builds B' of each of its
 // primitive pairs once (with p, P and K_ab) into a workspace of pair records. k_eri: one wavefront
 // per shell quartet, its lanes over the entries of the LDS matrices, reads the two pairs' records
-// and forms the two-center matrix and the two products per primitive quartet; it runs as two
-// instances sized for their quartets' matrices (pairs up to (2,1), and the rest), each over its
-// quartets costliest first. Shells up to l = kEriLmax. The tables come from gen_classes.py
+// and forms the two-center matrix and its product with the ket per primitive quartet, the bra's
+// product once per bra primitive pair; it runs as two instances sized for their quartets'
+// matrices (pairs up to (2,1), and the rest), each over its quartets costliest first. Shells up to l = kEriLmax. The tables come from gen_classes.py
 // (generated/shgo_eri.inc).
 #include "shgo_internal.h"
 
@@ -61,6 +61,7 @@ struct EriLds {
   static constexpr int SIZE = F + kEriLT + 2;
   static constexpr int kAccPerLane = (((NABM + 1) / 2) * ((NABM + 1) / 2) + 63) / 64;  // 2 x 2 block tiles per lane
   static constexpr int kIPerLane = (NWM * NWM + 63) / 64;                               // two-center entries per lane
+  static constexpr int kYPerLane = (((NWM + 1) / 2) * ((NABM + 1) / 2) + 63) / 64;    // 2 x 2 tiles of Y per lane
   static_assert(kNS + kNH + kEriLT + 2 >= NWM, "room after the T region for the tiles' reads");
 };
 
@@ -149,10 +150,12 @@ __device__ __forceinline__ void boys_and_harmonics(double T, const double* R, co
   fb[kEriLT + 1] = exp_neg(T);
   solid_harmonics<LT>(R[0], R[1], R[2], sr);
 }
+// LT = LA + LB + LC + LD up to LTMAX (the instance's largest quartet)
+template <int LTMAX>
 __device__ void boys_and_harmonics_lt(int LT, double T, const double* R, const double* __restrict__ boys_tab, double* fb,
                                       double* sr) {
-  static_assert(kEriLT == 8, "the dispatch covers LT = 0..8");
-  switch (LT) {
+  static_assert(LTMAX <= kEriLT && kEriLT == 8, "the dispatch covers LT = 0..8");
+  switch (LT < LTMAX ? LT : LTMAX) {
     case 0: boys_and_harmonics<0>(T, R, boys_tab, fb, sr); break;
     case 1: boys_and_harmonics<1>(T, R, boys_tab, fb, sr); break;
     case 2: boys_and_harmonics<2>(T, R, boys_tab, fb, sr); break;
@@ -160,9 +163,17 @@ __device__ void boys_and_harmonics_lt(int LT, double T, const double* R, const d
     case 4: boys_and_harmonics<4>(T, R, boys_tab, fb, sr); break;
     case 5: boys_and_harmonics<5>(T, R, boys_tab, fb, sr); break;
     case 6: boys_and_harmonics<6>(T, R, boys_tab, fb, sr); break;
-    case 7: boys_and_harmonics<7>(T, R, boys_tab, fb, sr); break;
-    default: boys_and_harmonics<8>(T, R, boys_tab, fb, sr); break;
+    case 7: if constexpr (LTMAX >= 7) boys_and_harmonics<7>(T, R, boys_tab, fb, sr); break;
+    default: if constexpr (LTMAX >= 8) boys_and_harmonics<8>(T, R, boys_tab, fb, sr); break;
   }
+}
+// The largest la + lb of a pair class with at most nabm block entries and shells up to kEriLmax.
+__host__ __device__ constexpr int eri_max_lsum(int nabm) {
+  int best = 0;
+  for (int la = 0; la <= kEriLmax; ++la)
+    for (int lb = 0; lb <= la; ++lb)
+      if ((2 * la + 1) * (2 * lb + 1) <= nabm && la + lb > best) best = la + lb;
+  return best;
 }
 
 // B' of one primitive pair of class (LA, LB) (LA >= LB) into Bx [NA NB][NW]: coupling terms,
@@ -258,16 +269,17 @@ __global__ void __launch_bounds__(kEriThreads) k_eri_pairs(DevBasis bs, EriWork 
   }
 }
 
-// One wavefront per quartet: for each bra and ket primitive pair, the Boys values and solid
-// harmonics of P - Q (one lane), the h table, the two-center matrix I, T = B'_bra I and the block
-// K_ab K_cd T B'_ket^T, accumulated in registers (2 x 2 tiles lane + 64 k of the pair-ordered
-// block). NABM and NWM bound the quartet's block and two-center entries per side; WPE is the
-// occupancy (wavefronts per SIMD) the instance is compiled for.
+// One wavefront per quartet. For each bra primitive pair: for each ket primitive pair, the Boys
+// values and solid harmonics of P - Q (one lane), the h table, the two-center matrix I and
+// Y += K_cd I B'_ket^T (the ket contracted first, in registers); then the block += K_ab B'_bra Y,
+// accumulated in registers (2 x 2 tiles lane + 64 k of the pair-ordered block). NABM and NWM bound
+// the quartet's block and two-center entries per side; WPE is the occupancy (wavefronts per SIMD)
+// the instance is compiled for.
 template <int NABM, int NWM, int WPE>
 __global__ void __launch_bounds__(kEriThreads) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __restrict__ out) {
   using Lds = EriLds<NABM, NWM>;
-  constexpr int kAccPerLane = Lds::kAccPerLane, kIPerLane = Lds::kIPerLane;
+  constexpr int kAccPerLane = Lds::kAccPerLane, kIPerLane = Lds::kIPerLane, kYPerLane = Lds::kYPerLane;
   __shared__ double s_lds[kEriWavesPerGroup * Lds::SIZE];
   // the Gaunt terms, shared by the workgroup: coefficient, and (L, M) index | h offset << 8
   __shared__ double s_gg[kEriGTerms];
@@ -329,12 +341,16 @@ k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __re
 #pragma unroll
     for (int u = 0; u < kEriNmax; ++u) hp[u] = hL >= 0 ? kEriP[hL][hn][u] : 0.0;
     // the block in 2 x 2 tiles (e1, e1 + 1) x (e2, e2 + 1), tile lane + 64 k of nt1 x nt2
-    const int nt1 = (NAB + 1) / 2, nt2 = (NCD + 1) / 2;
-    double acc[kAccPerLane][4];
+    const int nt1 = (NAB + 1) / 2, nt2 = (NCD + 1) / 2, ny1 = (NW1 + 1) / 2;
+    double acc[kAccPerLane][4], y[kYPerLane][4];
 #pragma unroll
     for (int k = 0; k < kAccPerLane; ++k)
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[k][c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kYPerLane; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) y[k][c] = 0.0;
     for (int r1 = 0; r1 < nb; ++r1) {
       const double* const rb = recb + (int64_t)r1 * strb;
       const double p = rb[0], Kab = rb[4];
@@ -348,7 +364,7 @@ k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __re
         const double alpha = p * qq / (p + qq);
         const double T = alpha * (R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
         const double cpre = 2.0 * 17.493418327624862846 / (p * qq * sqrt(p + qq));  // 2 pi^{5/2} / (p q sqrt(p+q))
-        if (lane == 0) boys_and_harmonics_lt(LT, T, R, boys_tab, sm + Lds::F, sm + Lds::SR);
+        if (lane == 0) boys_and_harmonics_lt<2 * eri_max_lsum(NABM)>(LT, T, R, boys_tab, sm + Lds::F, sm + Lds::SR);
         wave_sync();
         // h[L][n]: the lane's entry
         if (hL >= 0) {
@@ -384,55 +400,73 @@ k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __re
           }
         }
         wave_sync();
-        // T = B'_bra I, in 2 x 2 tiles (rows e1, e1 + 1; columns w2, w2 + 1); reads past the last
-        // row or column stay inside the wavefront's LDS and their results are not stored
-        const int u1 = (NAB + 1) / 2, u2 = (NW2 + 1) / 2;
-        for (int tt = lane; tt < u1 * u2; tt += 64) {
-          const int e1 = 2 * (tt / u2), w2 = 2 * (tt - (tt / u2) * u2);
-          double t00 = 0.0, t01 = 0.0, t10 = 0.0, t11 = 0.0;
-          const double* const b0 = sm + Lds::BB + e1 * NW1;
-          const double* const ic = sm + Lds::I + w2;
-          for (int w1 = 0; w1 < NW1; ++w1) {
-            const double x0 = b0[w1], x1 = b0[NW1 + w1], y0 = ic[w1 * NW2], y1 = ic[w1 * NW2 + 1];
-            t00 = fma(x0, y0, t00);
-            t01 = fma(x0, y1, t01);
-            t10 = fma(x1, y0, t10);
-            t11 = fma(x1, y1, t11);
-          }
-          double* const tr = sm + Lds::T + e1 * NW2 + w2;
-          tr[0] = t00;
-          if (w2 + 1 < NW2) tr[1] = t01;
-          if (e1 + 1 < NAB) {
-            tr[NW2] = t10;
-            if (w2 + 1 < NW2) tr[NW2 + 1] = t11;
-          }
-        }
-        wave_sync();
-        // the block += K_ab K_cd T B'_ket^T
-        const double pre = Kab * Kcd;
+        // Y += K_cd I B'_ket^T, in 2 x 2 tiles (rows w1, w1 + 1; columns e2, e2 + 1) held in
+        // registers over the ket's primitive pairs; reads past the last row or column stay inside
+        // the wavefront's LDS and their results are not kept
 #pragma unroll
-        for (int k = 0; k < kAccPerLane; ++k) {
+        for (int k = 0; k < kYPerLane; ++k) {
           const int tt = lane + 64 * k;
-          if (tt < nt1 * nt2) {
-            const int e1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
+          if (tt < ny1 * nt2) {
+            const int w1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
             double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
-            const double* const t0 = sm + Lds::T + e1 * NW2;
+            const double* const i0 = sm + Lds::I + w1 * NW2;
             const double* const k0 = sm + Lds::BK + e2 * NW2;
             for (int w2 = 0; w2 < NW2; ++w2) {
-              const double x0 = t0[w2], x1 = t0[NW2 + w2], y0 = k0[w2], y1 = k0[NW2 + w2];
+              const double x0 = i0[w2], x1 = i0[NW2 + w2], y0 = k0[w2], y1 = k0[NW2 + w2];
               s00 = fma(x0, y0, s00);
               s01 = fma(x0, y1, s01);
               s10 = fma(x1, y0, s10);
               s11 = fma(x1, y1, s11);
             }
-            acc[k][0] = fma(pre, s00, acc[k][0]);
-            acc[k][1] = fma(pre, s01, acc[k][1]);
-            acc[k][2] = fma(pre, s10, acc[k][2]);
-            acc[k][3] = fma(pre, s11, acc[k][3]);
+            y[k][0] = fma(Kcd, s00, y[k][0]);
+            y[k][1] = fma(Kcd, s01, y[k][1]);
+            y[k][2] = fma(Kcd, s10, y[k][2]);
+            y[k][3] = fma(Kcd, s11, y[k][3]);
           }
         }
         wave_sync();
       }
+      // Y^T [e2][w1] into the T region, then the block += K_ab B'_bra Y
+#pragma unroll
+      for (int k = 0; k < kYPerLane; ++k) {
+        const int tt = lane + 64 * k;
+        if (tt < ny1 * nt2) {
+          const int w1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
+          double* const yt = sm + Lds::T + e2 * NW1 + w1;
+          const bool w_in = w1 + 1 < NW1, e_in = e2 + 1 < NCD;
+          yt[0] = y[k][0];
+          if (w_in) yt[1] = y[k][2];
+          if (e_in) {
+            yt[NW1] = y[k][1];
+            if (w_in) yt[NW1 + 1] = y[k][3];
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) y[k][c] = 0.0;
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < kAccPerLane; ++k) {
+        const int tt = lane + 64 * k;
+        if (tt < nt1 * nt2) {
+          const int e1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
+          double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+          const double* const b0 = sm + Lds::BB + e1 * NW1;
+          const double* const y0p = sm + Lds::T + e2 * NW1;
+          for (int w1 = 0; w1 < NW1; ++w1) {
+            const double x0 = b0[w1], x1 = b0[NW1 + w1], y0 = y0p[w1], y1 = y0p[NW1 + w1];
+            s00 = fma(x0, y0, s00);
+            s01 = fma(x0, y1, s01);
+            s10 = fma(x1, y0, s10);
+            s11 = fma(x1, y1, s11);
+          }
+          acc[k][0] = fma(Kab, s00, acc[k][0]);
+          acc[k][1] = fma(Kab, s01, acc[k][1]);
+          acc[k][2] = fma(Kab, s10, acc[k][2]);
+          acc[k][3] = fma(Kab, s11, acc[k][3]);
+        }
+      }
+      wave_sync();
     }
     // the block in the listed order: entry ((i0 N1 + i1) N2 + i2) N3 + i3
     const bool swb = fl & 1, swk = fl & 2;
