@@ -253,6 +253,13 @@ shgo_status shgo_execute_cartesian(shgo_plan* plan, double* out, void* stream);
 shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
                             double* out, void* stream);
 
+/* Doubles that shgo_eri_blocks writes for these quartets: the sum over them of
+ * (2la+1)(2lb+1)(2lc+1)(2ld+1), into *size. Host only (no context, no device). The same checks
+ * as shgo_eri_blocks, in the same order: SHGO_ERR_INVALID_ARG for a null basis or size, a
+ * negative count, null quartets with a positive count or a shell index out of range;
+ * SHGO_ERR_UNSUPPORTED_L for a shell above l = 2. *size is 0 unless SHGO_OK. */
+shgo_status shgo_eri_output_size(const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets, int64_t* size);
+
 /* Gradient of E = sum_ij D_ij V_ij (the nuclear-attraction matrix of Eq. 11, differentiated
  * through Eq. 5, the shift of Eqs. 7-8, the product rule and the Boys function; an adjoint
  * kernel, not finite differences) with respect to the nuclear positions and the shell centers.

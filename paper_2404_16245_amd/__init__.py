@@ -29,7 +29,7 @@ SHGO_LMAX = 7
 EXPORTED = ["shgo_create", "shgo_destroy", "shgo_status_string", "shgo_last_error", "shgo_nbf", "shgo_validate",
             "shgo_plan_matrix", "shgo_plan_pairs", "shgo_plan_destroy", "shgo_plan_output_size",
             "shgo_plan_integrals", "shgo_execute", "shgo_execute_graph", "shgo_execute_grad", "shgo_boys",
-            "shgo_execute_overlap", "shgo_execute_cartesian", "shgo_eri_blocks",
+            "shgo_execute_overlap", "shgo_execute_cartesian", "shgo_eri_blocks", "shgo_eri_output_size",
             "shgo_plan_set_timing", "shgo_plan_phase_ms", "shgo_plan_get_schedule", "shgo_plan_set_schedule",
             "shgo_plan_autotune", "shgo_max_tiles", "shgo_options_default", "shgo_check_call",
             "shgo_nuclear_attraction", "shgo_nuclear_attraction_grad", "shgo_plan_get_info", "shgo_plan_set_precision",
@@ -115,6 +115,8 @@ def load_library(path=LIB_PATH):
     lib.shgo_execute_cartesian.restype = ctypes.c_int
     lib.shgo_eri_blocks.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.shgo_eri_blocks.restype = ctypes.c_int
+    lib.shgo_eri_output_size.argtypes = [vp, i64, vp, ctypes.POINTER(i64)]
+    lib.shgo_eri_output_size.restype = ctypes.c_int
     lib.shgo_plan_get_schedule.argtypes = [vp, vp, vp]
     lib.shgo_plan_get_schedule.restype = ctypes.c_int
     lib.shgo_plan_set_schedule.argtypes = [vp, vp, vp]
@@ -395,6 +397,17 @@ def shgo_execute_overlap(plan, out, stream=None):
     return out
 
 
+def shgo_eri_output_size(basis, quartets):
+    """Doubles shgo_eri_blocks writes for the quartets [n, 4] (host only; the library checks the
+    indices and the shells' l)."""
+    lib = load_library()
+    hb = basis if isinstance(basis, _HostBasis) else _HostBasis(basis)
+    q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
+    n = ctypes.c_int64()
+    _check(lib, None, lib.shgo_eri_output_size(ctypes.byref(hb.struct), int(len(q)), q.ctypes.data, ctypes.byref(n)))
+    return n.value
+
+
 def shgo_max_tiles(class_id):
     """Largest tiles-per-item the LDS accumulator allows for a class (-1 if invalid)."""
     return int(load_library().shgo_max_tiles(int(class_id)))
@@ -583,10 +596,7 @@ def eri_blocks(basis, quartets, device=0, stream=None):
     ctx = context(device)
     q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
     hb = _HostBasis(basis)
-    dim = 2 * np.asarray(basis.l, dtype=np.int64) + 1
-    # out-of-range indices are left for the library to reject (it writes nothing then)
-    valid = len(q) and q.min() >= 0 and q.max() < len(dim)
-    size = int((dim[q[:, 0]] * dim[q[:, 1]] * dim[q[:, 2]] * dim[q[:, 3]]).sum()) if valid else 0
+    size = shgo_eri_output_size(hb, q)
     out = torch.empty(max(size, 1), dtype=torch.float64, device=f"cuda:{device}")
     _check(lib, ctx, lib.shgo_eri_blocks(ctx, ctypes.byref(hb.struct), int(len(q)), q.ctypes.data,
                                          out.data_ptr(), _stream_handle(stream)))

@@ -7,6 +7,7 @@
 
 #include "plan_host.h"
 
+#include <memory>
 #include <mutex>
 
 namespace shgo_impl {
@@ -572,6 +573,50 @@ shgo_status shgo_execute_cartesian(shgo_plan* p, double* out, void* stream) {
   return SHGO_OK;
 }
 
+// The quartets' block sizes, checked: SHGO_ERR_INVALID_ARG for a shell index out of range,
+// SHGO_ERR_UNSUPPORTED_L for a shell above the two-electron path's l, at the first quartet that
+// has one. Each quartet's first double in the output into offsets (when given), the total into
+// *total.
+static shgo_status eri_sizes(const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets, int64_t* offsets,
+                             int64_t* total, std::string* err) {
+  const int32_t nsh = basis->n_shells;
+  std::vector<int32_t> dim((size_t)std::max(nsh, 1));
+  for (int32_t sh = 0; sh < nsh; ++sh) dim[(size_t)sh] = basis->l[sh] > eri_lmax() ? -1 : 2 * basis->l[sh] + 1;
+  int64_t t = 0;
+  for (int64_t q = 0; q < n_quartets; ++q) {
+    int64_t size = 1;
+    for (int i = 0; i < 4; ++i) {
+      const int32_t sh = quartets[4 * q + i];
+      if (sh < 0 || sh >= nsh) {
+        *err = "shell index out of range";
+        return SHGO_ERR_INVALID_ARG;
+      }
+      if (dim[(size_t)sh] < 0) {
+        *err = "the two-electron path takes shells up to l = " + std::to_string(eri_lmax());
+        return SHGO_ERR_UNSUPPORTED_L;
+      }
+      size *= dim[(size_t)sh];
+    }
+    if (offsets) offsets[q] = t;
+    t += size;
+  }
+  *total = t;
+  return SHGO_OK;
+}
+
+shgo_status shgo_eri_output_size(const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets, int64_t* size) {
+  if (size) *size = 0;
+  if (!basis || !size || n_quartets < 0 || (n_quartets > 0 && !quartets)) return SHGO_ERR_INVALID_ARG;
+  const shgo_nuclei none{0, nullptr, nullptr};
+  std::string err;
+  shgo_status s = shgo_host::validate_inputs(basis, &none, 0.0, &err);
+  if (s != SHGO_OK) return s;
+  int64_t total = 0;
+  s = eri_sizes(basis, n_quartets, quartets, nullptr, &total, &err);
+  if (s == SHGO_OK) *size = total;
+  return s;
+}
+
 shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
                             double* out, void* stream) {
   if (!ctx) return SHGO_ERR_INVALID_ARG;
@@ -581,21 +626,10 @@ shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t 
   std::string err;
   shgo_status s = shgo_host::validate_inputs(basis, &none, 0.0, &err);
   if (s != SHGO_OK) return fail(ctx, s, err);
-  std::vector<int64_t> offsets((size_t)n_quartets);
+  std::unique_ptr<int64_t[]> offsets(new int64_t[(size_t)std::max<int64_t>(n_quartets, 1)]);
   int64_t total = 0;
-  for (int64_t q = 0; q < n_quartets; ++q) {
-    int64_t size = 1;
-    for (int i = 0; i < 4; ++i) {
-      const int32_t sh = quartets[4 * q + i];
-      if (sh < 0 || sh >= basis->n_shells) return fail(ctx, SHGO_ERR_INVALID_ARG, "shell index out of range");
-      if (basis->l[sh] > eri_lmax())
-        return fail(ctx, SHGO_ERR_UNSUPPORTED_L,
-                    "the two-electron path takes shells up to l = " + std::to_string(eri_lmax()));
-      size *= 2 * basis->l[sh] + 1;
-    }
-    offsets[(size_t)q] = total;
-    total += size;
-  }
+  s = eri_sizes(basis, n_quartets, quartets, offsets.get(), &total, &err);
+  if (s != SHGO_OK) return fail(ctx, s, err);
   if (n_quartets == 0 || basis->n_shells == 0) return SHGO_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
   // a pair plan of one pair uploads the basis; its pair build computes the primitive weights
@@ -605,7 +639,7 @@ shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t 
   if (s != SHGO_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   launch_pair_build(p, st);
-  hipError_t e = run_eri(p, basis, n_quartets, quartets, offsets.data(), out, st);
+  hipError_t e = run_eri(p, basis, n_quartets, quartets, offsets.get(), out, st);
   shgo_plan_destroy(p);
   if (e == hipErrorOutOfMemory) return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "no device memory for the two-electron workspace");
   if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("two-electron evaluation failed: ") + hipGetErrorString(e));

@@ -28,6 +28,7 @@
 #include "generated/shgo_eri.inc"
 
 #include <algorithm>
+#include <memory>
 #include <unordered_map>
 #include <vector>
 
@@ -46,23 +47,40 @@ constexpr int kNabSmall = 15, kNwSmall = 20;
 static_assert(kEriGTerms <= 4096 && kEriGmax < 32, "Gaunt list offsets take 12 bits, counts 5");
 static_assert(kNS <= 256 && kNH <= 256, "Gaunt term indices take 8 bits each");
 
+// The largest la + lb of a pair class with at most nabm block entries and shells up to kEriLmax.
+__host__ __device__ constexpr int eri_max_lsum(int nabm) {
+  int best = 0;
+  for (int la = 0; la <= kEriLmax; ++la)
+    for (int lb = 0; lb <= la; ++lb)
+      if ((2 * la + 1) * (2 * lb + 1) <= nabm && la + lb > best) best = la + lb;
+  return best;
+}
+
 // Per-wavefront LDS of k_eri for blocks of at most NABM entries and NWM two-center entries, in
-// doubles. Each region is followed by another of at least NWM doubles (F last, after SR and H),
-// which the 2 x 2 tiles may read past a ragged last row or column without storing the result.
+// doubles: the bra's and the ket's B' of the current primitive pairs, the two-center matrix I
+// (after a bra primitive pair's kets, Y^T [NCD][NW1]), the Boys values and solid harmonics of
+// kSlots primitive quartets (one slot each: F_0..F_LTM, e^{-T}, then S^L_M for L <= LTM), and the
+// h table. The 2 x 2 tiles may read past a ragged last row or column without keeping the result:
+// each of BB, BK and I is followed by at least NWM doubles, and Y^T's reads stay inside I and the
+// slots.
 template <int NABM, int NWM>
 struct EriLds {
+  static constexpr int LTM = 2 * eri_max_lsum(NABM);         // the largest LA + LB + LC + LD
+  static constexpr int kFS = LTM + 2;                        // F_0..F_LTM and e^{-T}
+  static constexpr int kSlot = kFS + (LTM + 1) * (LTM + 1);  // and the solid harmonics
+  static constexpr int kSlots = NABM * NWM / kSlot;
   static constexpr int BB = 0;
   static constexpr int BK = BB + NABM * NWM;
   static constexpr int I = BK + NABM * NWM;
-  static constexpr int T = I + NWM * NWM;
-  static constexpr int SR = T + NABM * NWM;
-  static constexpr int H = SR + kNS;
-  static constexpr int F = H + kNH;
-  static constexpr int SIZE = F + kEriLT + 2;
+  static constexpr int STG = I + NWM * NWM;
+  static constexpr int H = STG + kSlots * kSlot;
+  static constexpr int SIZE = H + kNH;
   static constexpr int kAccPerLane = (((NABM + 1) / 2) * ((NABM + 1) / 2) + 63) / 64;  // 2 x 2 block tiles per lane
   static constexpr int kIPerLane = (NWM * NWM + 63) / 64;                               // two-center entries per lane
   static constexpr int kYPerLane = (((NWM + 1) / 2) * ((NABM + 1) / 2) + 63) / 64;    // 2 x 2 tiles of Y per lane
-  static_assert(kNS + kNH + kEriLT + 2 >= NWM, "room after the T region for the tiles' reads");
+  static_assert(kSlots >= 1 && kSlots <= 64 && kSlots * kSlot >= NWM, "room after I for the tiles' reads");
+  static_assert((NABM + 1) * NWM <= NWM * NWM + kSlots * kSlot, "Y^T's tiles read inside I and the slots");
+  static_assert(kNH >= 1 && LTM <= kEriLT, "the h table and the Boys orders");
 };
 
 // The distinct pairs of a quartet list and each quartet's pairs; every pointer is device memory.
@@ -135,10 +153,10 @@ __device__ __forceinline__ void solid_harmonics(double x, double y, double z, do
     }
 }
 
-// F_0..F_LT(T), e^{-T} and S^L_M(R), L <= LT, into the wavefront's LDS (one lane)
+// F_0..F_LT(T) into fb, e^{-T} into *fexp and S^L_M(R), L <= LT, into sr (the lane's slot)
 template <int LT>
 __device__ __forceinline__ void boys_and_harmonics(double T, const double* R, const double* __restrict__ boys_tab,
-                                                   double* fb, double* sr) {
+                                                   double* fb, double* fexp, double* sr) {
   double row[kBoysRowLoad];
   const double* __restrict__ r = boys_row_ptr(boys_tab, LT, boys_index(T));
 #pragma unroll
@@ -147,35 +165,26 @@ __device__ __forceinline__ void boys_and_harmonics(double T, const double* R, co
   boys_row<LT>(T, row, F);
 #pragma unroll
   for (int u = 0; u <= LT; ++u) fb[u] = F[u];
-  fb[kEriLT + 1] = exp_neg(T);
+  *fexp = exp_neg(T);
   solid_harmonics<LT>(R[0], R[1], R[2], sr);
 }
 // LT = LA + LB + LC + LD up to LTMAX (the instance's largest quartet)
 template <int LTMAX>
 __device__ void boys_and_harmonics_lt(int LT, double T, const double* R, const double* __restrict__ boys_tab, double* fb,
-                                      double* sr) {
+                                      double* fexp, double* sr) {
   static_assert(LTMAX <= kEriLT && kEriLT == 8, "the dispatch covers LT = 0..8");
   switch (LT < LTMAX ? LT : LTMAX) {
-    case 0: boys_and_harmonics<0>(T, R, boys_tab, fb, sr); break;
-    case 1: boys_and_harmonics<1>(T, R, boys_tab, fb, sr); break;
-    case 2: boys_and_harmonics<2>(T, R, boys_tab, fb, sr); break;
-    case 3: boys_and_harmonics<3>(T, R, boys_tab, fb, sr); break;
-    case 4: boys_and_harmonics<4>(T, R, boys_tab, fb, sr); break;
-    case 5: boys_and_harmonics<5>(T, R, boys_tab, fb, sr); break;
-    case 6: boys_and_harmonics<6>(T, R, boys_tab, fb, sr); break;
-    case 7: if constexpr (LTMAX >= 7) boys_and_harmonics<7>(T, R, boys_tab, fb, sr); break;
-    default: if constexpr (LTMAX >= 8) boys_and_harmonics<8>(T, R, boys_tab, fb, sr); break;
+    case 0: boys_and_harmonics<0>(T, R, boys_tab, fb, fexp, sr); break;
+    case 1: boys_and_harmonics<1>(T, R, boys_tab, fb, fexp, sr); break;
+    case 2: boys_and_harmonics<2>(T, R, boys_tab, fb, fexp, sr); break;
+    case 3: boys_and_harmonics<3>(T, R, boys_tab, fb, fexp, sr); break;
+    case 4: boys_and_harmonics<4>(T, R, boys_tab, fb, fexp, sr); break;
+    case 5: boys_and_harmonics<5>(T, R, boys_tab, fb, fexp, sr); break;
+    case 6: boys_and_harmonics<6>(T, R, boys_tab, fb, fexp, sr); break;
+    case 7: if constexpr (LTMAX >= 7) boys_and_harmonics<7>(T, R, boys_tab, fb, fexp, sr); break;
+    default: if constexpr (LTMAX >= 8) boys_and_harmonics<8>(T, R, boys_tab, fb, fexp, sr); break;
   }
 }
-// The largest la + lb of a pair class with at most nabm block entries and shells up to kEriLmax.
-__host__ __device__ constexpr int eri_max_lsum(int nabm) {
-  int best = 0;
-  for (int la = 0; la <= kEriLmax; ++la)
-    for (int lb = 0; lb <= la; ++lb)
-      if ((2 * la + 1) * (2 * lb + 1) <= nabm && la + lb > best) best = la + lb;
-  return best;
-}
-
 // B' of one primitive pair of class (LA, LB) (LA >= LB) into Bx [NA NB][NW]: coupling terms,
 // rotation of the W blocks and of the block rows to the laboratory frame, then the gradient form.
 __device__ void build_side(double* Bx, int cls, int LA, int LB, double ta, double tb, double p, const Angles& an,
@@ -269,9 +278,10 @@ __global__ void __launch_bounds__(kEriThreads) k_eri_pairs(DevBasis bs, EriWork 
   }
 }
 
-// One wavefront per quartet. For each bra primitive pair: for each ket primitive pair, the Boys
-// values and solid harmonics of P - Q (one lane), the h table, the two-center matrix I and
-// Y += K_cd I B'_ket^T (the ket contracted first, in registers); then the block += K_ab B'_bra Y,
+// One wavefront per quartet. For each bra primitive pair: the Boys values and solid harmonics of
+// P - Q for up to kSlots ket primitive pairs at once (a lane each), then for each ket primitive
+// pair the h table, the two-center matrix I and Y += K_cd I B'_ket^T (the ket contracted first,
+// in registers); then the block += K_ab B'_bra Y,
 // accumulated in registers (2 x 2 tiles lane + 64 k of the pair-ordered block). NABM and NWM bound
 // the quartet's block and two-center entries per side; WPE is the occupancy (wavefronts per SIMD)
 // the instance is compiled for.
@@ -356,83 +366,94 @@ k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __re
       const double p = rb[0], Kab = rb[4];
       const double P[3] = {rb[1], rb[2], rb[3]};
       for (int t = lane; t < NAB * NW1; t += 64) sm[Lds::BB + t] = rb[kEriHdr + t];
-      for (int r2 = 0; r2 < nk; ++r2) {
-        const double* const rk = reck + (int64_t)r2 * strk;
-        const double qq = rk[0], Kcd = rk[4];
-        const double R[3] = {P[0] - rk[1], P[1] - rk[2], P[2] - rk[3]};
-        for (int t = lane; t < NCD * NW2; t += 64) sm[Lds::BK + t] = rk[kEriHdr + t];
-        const double alpha = p * qq / (p + qq);
-        const double T = alpha * (R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
-        const double cpre = 2.0 * 17.493418327624862846 / (p * qq * sqrt(p + qq));  // 2 pi^{5/2} / (p q sqrt(p+q))
-        if (lane == 0) boys_and_harmonics_lt<2 * eri_max_lsum(NABM)>(LT, T, R, boys_tab, sm + Lds::F, sm + Lds::SR);
-        wave_sync();
-        // h[L][n]: the lane's entry
-        if (hL >= 0) {
-          double base = cpre;
-          for (int u = 0; u < hL; ++u) base *= -2.0 * alpha;
-          double v;
-          if (hn == 0) {
-            v = sm[Lds::F + hL];
-          } else {
-            double poly = 0.0;
-#pragma unroll
-            for (int u = kEriNmax - 1; u >= 0; --u) poly = fma(poly, T, hp[u]);
-            double an = 1.0;
-            for (int u = 0; u < hn; ++u) an *= alpha;
-            v = an * poly * sm[Lds::F + kEriLT + 1];
-          }
-          sm[Lds::H + hL * (kEriNmax + 1) + hn] = base * v;
+      for (int c0 = 0; c0 < nk; c0 += Lds::kSlots) {
+        // the Boys values and solid harmonics of the next kSlots ket primitive pairs, a lane each
+        if (lane < Lds::kSlots && c0 + lane < nk) {
+          const double* const rk = reck + (int64_t)(c0 + lane) * strk;
+          const double qq = rk[0];
+          const double R[3] = {P[0] - rk[1], P[1] - rk[2], P[2] - rk[3]};
+          const double T = p * qq / (p + qq) * (R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+          double* const f = sm + Lds::STG + lane * Lds::kSlot;
+          boys_and_harmonics_lt<Lds::LTM>(LT, T, R, boys_tab, f, f + Lds::LTM + 1, f + Lds::kFS);
         }
         wave_sync();
-        // two-center matrix I[w1][w2]
+        for (int r2 = c0; r2 < nk && r2 < c0 + Lds::kSlots; ++r2) {
+          const double* const rk = reck + (int64_t)r2 * strk;
+          const double qq = rk[0], Kcd = rk[4];
+          const double R[3] = {P[0] - rk[1], P[1] - rk[2], P[2] - rk[3]};
+          for (int t = lane; t < NCD * NW2; t += 64) sm[Lds::BK + t] = rk[kEriHdr + t];
+          const double alpha = p * qq / (p + qq);
+          const double T = alpha * (R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+          const double cpre = 2.0 * 17.493418327624862846 / (p * qq * sqrt(p + qq));  // 2 pi^{5/2} / (p q sqrt(p+q))
+          const double* const f = sm + Lds::STG + (r2 - c0) * Lds::kSlot;
+          // h[L][n]: the lane's entry
+          if (hL >= 0) {
+            double base = cpre;
+            for (int u = 0; u < hL; ++u) base *= -2.0 * alpha;
+            double v;
+            if (hn == 0) {
+              v = f[hL];
+            } else {
+              double poly = 0.0;
 #pragma unroll
-        for (int k = 0; k < kIPerLane; ++k) {
-          const int it = lane + 64 * k;
-          if (it < NW1 * NW2) {
-            const uint32_t wd = ient[k];
-            const int g0 = (int)(wd & 4095u), gn = (int)((wd >> 12) & 31u), js = (int)((wd >> 17) & 7u);
-            double sacc = 0.0;
-            for (int t = g0; t < g0 + gn; ++t) {
-              const int pk = s_gpk[t];
-              sacc = fma(s_gg[t] * sm[Lds::SR + (pk & 255)], sm[Lds::H + (pk >> 8) + js], sacc);
+              for (int u = kEriNmax - 1; u >= 0; --u) poly = fma(poly, T, hp[u]);
+              double an = 1.0;
+              for (int u = 0; u < hn; ++u) an *= alpha;
+              v = an * poly * f[Lds::LTM + 1];
             }
-            sm[Lds::I + it] = ((wd >> 20) & 1u) ? -sacc : sacc;
+            sm[Lds::H + hL * (kEriNmax + 1) + hn] = base * v;
           }
-        }
-        wave_sync();
-        // Y += K_cd I B'_ket^T, in 2 x 2 tiles (rows w1, w1 + 1; columns e2, e2 + 1) held in
-        // registers over the ket's primitive pairs; reads past the last row or column stay inside
-        // the wavefront's LDS and their results are not kept
+          wave_sync();
+          // two-center matrix I[w1][w2]
 #pragma unroll
-        for (int k = 0; k < kYPerLane; ++k) {
-          const int tt = lane + 64 * k;
-          if (tt < ny1 * nt2) {
-            const int w1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
-            double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
-            const double* const i0 = sm + Lds::I + w1 * NW2;
-            const double* const k0 = sm + Lds::BK + e2 * NW2;
-            for (int w2 = 0; w2 < NW2; ++w2) {
-              const double x0 = i0[w2], x1 = i0[NW2 + w2], y0 = k0[w2], y1 = k0[NW2 + w2];
-              s00 = fma(x0, y0, s00);
-              s01 = fma(x0, y1, s01);
-              s10 = fma(x1, y0, s10);
-              s11 = fma(x1, y1, s11);
+          for (int k = 0; k < kIPerLane; ++k) {
+            const int it = lane + 64 * k;
+            if (it < NW1 * NW2) {
+              const uint32_t wd = ient[k];
+              const int g0 = (int)(wd & 4095u), gn = (int)((wd >> 12) & 31u), js = (int)((wd >> 17) & 7u);
+              double sacc = 0.0;
+              for (int t = g0; t < g0 + gn; ++t) {
+                const int pk = s_gpk[t];
+                sacc = fma(s_gg[t] * f[Lds::kFS + (pk & 255)], sm[Lds::H + (pk >> 8) + js], sacc);
+              }
+              sm[Lds::I + it] = ((wd >> 20) & 1u) ? -sacc : sacc;
             }
-            y[k][0] = fma(Kcd, s00, y[k][0]);
-            y[k][1] = fma(Kcd, s01, y[k][1]);
-            y[k][2] = fma(Kcd, s10, y[k][2]);
-            y[k][3] = fma(Kcd, s11, y[k][3]);
           }
+          wave_sync();
+          // Y += K_cd I B'_ket^T, in 2 x 2 tiles (rows w1, w1 + 1; columns e2, e2 + 1) held in
+          // registers over the ket's primitive pairs; reads past the last row or column stay inside
+          // the wavefront's LDS and their results are not kept
+#pragma unroll
+          for (int k = 0; k < kYPerLane; ++k) {
+            const int tt = lane + 64 * k;
+            if (tt < ny1 * nt2) {
+              const int w1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
+              double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+              const double* const i0 = sm + Lds::I + w1 * NW2;
+              const double* const k0 = sm + Lds::BK + e2 * NW2;
+              for (int w2 = 0; w2 < NW2; ++w2) {
+                const double x0 = i0[w2], x1 = i0[NW2 + w2], y0 = k0[w2], y1 = k0[NW2 + w2];
+                s00 = fma(x0, y0, s00);
+                s01 = fma(x0, y1, s01);
+                s10 = fma(x1, y0, s10);
+                s11 = fma(x1, y1, s11);
+              }
+              y[k][0] = fma(Kcd, s00, y[k][0]);
+              y[k][1] = fma(Kcd, s01, y[k][1]);
+              y[k][2] = fma(Kcd, s10, y[k][2]);
+              y[k][3] = fma(Kcd, s11, y[k][3]);
+            }
+          }
+          wave_sync();
         }
-        wave_sync();
       }
-      // Y^T [e2][w1] into the T region, then the block += K_ab B'_bra Y
+      // Y^T [e2][w1] into the I region, then the block += K_ab B'_bra Y
 #pragma unroll
       for (int k = 0; k < kYPerLane; ++k) {
         const int tt = lane + 64 * k;
         if (tt < ny1 * nt2) {
           const int w1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
-          double* const yt = sm + Lds::T + e2 * NW1 + w1;
+          double* const yt = sm + Lds::I + e2 * NW1 + w1;
           const bool w_in = w1 + 1 < NW1, e_in = e2 + 1 < NCD;
           yt[0] = y[k][0];
           if (w_in) yt[1] = y[k][2];
@@ -452,7 +473,7 @@ k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __re
           const int e1 = 2 * (tt / nt2), e2 = 2 * (tt - (tt / nt2) * nt2);
           double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
           const double* const b0 = sm + Lds::BB + e1 * NW1;
-          const double* const y0p = sm + Lds::T + e2 * NW1;
+          const double* const y0p = sm + Lds::I + e2 * NW1;
           for (int w1 = 0; w1 < NW1; ++w1) {
             const double x0 = b0[w1], x1 = b0[NW1 + w1], y0 = y0p[w1], y1 = y0p[NW1 + w1];
             s00 = fma(x0, y0, s00);
@@ -503,8 +524,15 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
   const bool dense = (int64_t)nsh * nsh <= ((int64_t)1 << 22);
   std::vector<int32_t> dense_index(dense ? (size_t)nsh * nsh : 0, -1);
   std::unordered_map<int64_t, int32_t> index;
-  std::vector<int32_t> pairs, quart((size_t)4 * n_quartets, 0);
+  std::vector<int32_t> pairs;
   std::vector<int64_t> pair_off;
+  // per distinct pair: primitive pairs, block entries, two-center entries, and whether it fits the
+  // small instance of k_eri
+  struct PairSize {
+    int32_t k, nab, nw;
+    bool small;
+  };
+  std::vector<PairSize> psize;
   int64_t rec_size = 0;
   auto pair_of = [&](int32_t x, int32_t y, bool& swapped) {
     swapped = basis->l[x] < basis->l[y];
@@ -525,51 +553,47 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
     pairs.push_back(b);
     pair_off.push_back(rec_size);
     const int la = basis->l[a], lb = basis->l[b];
-    rec_size += (int64_t)basis->n_prim[a] * basis->n_prim[b] *
-                (kEriHdr + (2 * la + 1) * (2 * lb + 1) * kEriNWHost[class_id(la, lb)]);
+    const int nab = (2 * la + 1) * (2 * lb + 1), nw = kEriNWHost[class_id(la, lb)];
+    const int32_t k = basis->n_prim[a] * basis->n_prim[b];
+    psize.push_back({k, nab, nw, nab <= kNabSmall && nw <= kNwSmall});
+    rec_size += (int64_t)k * (kEriHdr + nab * nw);
     return u;
   };
-  for (int64_t q = 0; q < n_quartets; ++q) {
-    bool sw1 = false, sw2 = false;
-    quart[4 * q] = pair_of(quartets[4 * q], quartets[4 * q + 1], sw1);
-    quart[4 * q + 1] = pair_of(quartets[4 * q + 2], quartets[4 * q + 3], sw2);
-    quart[4 * q + 2] = (sw1 ? 1 : 0) | (sw2 ? 2 : 0);
-  }
-  const int64_t n_pairs = (int64_t)pair_off.size();
-  // the quartets whose two pairs fit the small instance of k_eri first, then the rest
-  auto fits_small = [&](int32_t u) {
-    const int la = basis->l[pairs[2 * u]], lb = basis->l[pairs[2 * u + 1]];
-    return (2 * la + 1) * (2 * lb + 1) <= kNabSmall && kEriNWHost[class_id(la, lb)] <= kNwSmall;
-  };
-  // and within each, the costliest first (primitive quartets times the two products' sizes, in
-  // buckets of a quarter octave: a counting sort), so that the wavefronts striding over the list
-  // take the long quartets early
+  // One pass over the quartets: their pairs and swaps, and the sort key: the quartets whose two
+  // pairs fit the small instance of k_eri first, then the rest, and within each the costliest
+  // first (primitive quartets times the matrices' sizes, in buckets of a quarter octave: a
+  // counting sort), so that the wavefronts striding over the list take the long quartets early.
   constexpr int kCostBuckets = 256;
-  auto bucket = [&](int64_t q) {
-    const int32_t ub = quart[4 * q], uk = quart[4 * q + 1];
-    const int a = pairs[2 * ub], b = pairs[2 * ub + 1], c = pairs[2 * uk], d = pairs[2 * uk + 1];
-    const int nab = (2 * basis->l[a] + 1) * (2 * basis->l[b] + 1), ncd = (2 * basis->l[c] + 1) * (2 * basis->l[d] + 1);
-    const int nw1 = kEriNWHost[class_id(basis->l[a], basis->l[b])], nw2 = kEriNWHost[class_id(basis->l[c], basis->l[d])];
-    const uint64_t cost = (uint64_t)basis->n_prim[a] * basis->n_prim[b] * basis->n_prim[c] * basis->n_prim[d] *
-                          (uint64_t)(nw1 * nw2 + nab * nw2 + nab * ncd + 200);
-    const int oct = 63 - __builtin_clzll(cost);                                     // floor(log2 cost)
-    const int quarter = oct >= 2 ? (int)((cost >> (oct - 2)) & 3u) : 0;             // the next two bits
-    return std::min(kCostBuckets - 1, 4 * oct + quarter);
-  };
-  std::vector<int32_t> qkey((size_t)n_quartets);  // bin-major: small quartets, then by falling cost
+  std::unique_ptr<int32_t[]> quart(new int32_t[(size_t)4 * n_quartets]);
+  std::unique_ptr<int32_t[]> qkey(new int32_t[(size_t)n_quartets]);
   std::vector<int64_t> count(2 * kCostBuckets + 1, 0);
   int64_t n_small = 0;
   for (int64_t q = 0; q < n_quartets; ++q) {
-    const bool small = fits_small(quart[4 * q]) && fits_small(quart[4 * q + 1]);
+    bool sw1 = false, sw2 = false;
+    const int32_t ub = pair_of(quartets[4 * q], quartets[4 * q + 1], sw1);
+    const int32_t uk = pair_of(quartets[4 * q + 2], quartets[4 * q + 3], sw2);
+    quart[4 * q] = ub;
+    quart[4 * q + 1] = uk;
+    quart[4 * q + 2] = (sw1 ? 1 : 0) | (sw2 ? 2 : 0);
+    quart[4 * q + 3] = 0;
+    const PairSize &pb = psize[(size_t)ub], &pk = psize[(size_t)uk];
+    const uint64_t cost = (uint64_t)pb.k * (uint64_t)pk.k *
+                          (uint64_t)(pb.nw * pk.nw + pb.nab * pk.nw + pb.nab * pk.nab + 200);
+    const int oct = 63 - __builtin_clzll(cost);                          // floor(log2 cost)
+    const int quarter = oct >= 2 ? (int)((cost >> (oct - 2)) & 3u) : 0;  // the next two bits
+    const int bucket = std::min(kCostBuckets - 1, 4 * oct + quarter);
+    const bool small = pb.small && pk.small;
     n_small += small;
-    qkey[(size_t)q] = (small ? 0 : kCostBuckets) + (kCostBuckets - 1 - bucket(q));
-    ++count[(size_t)qkey[(size_t)q] + 1];
+    const int32_t key = (small ? 0 : kCostBuckets) + (kCostBuckets - 1 - bucket);
+    qkey[q] = key;
+    ++count[(size_t)key + 1];
   }
+  const int64_t n_pairs = (int64_t)pair_off.size();
   for (int k = 0; k < 2 * kCostBuckets; ++k) count[(size_t)k + 1] += count[(size_t)k];
-  std::vector<int32_t> quart_sorted((size_t)4 * n_quartets);
-  std::vector<int64_t> off_sorted((size_t)n_quartets);
+  std::unique_ptr<int32_t[]> quart_sorted(new int32_t[(size_t)4 * n_quartets]);
+  std::unique_ptr<int64_t[]> off_sorted(new int64_t[(size_t)n_quartets]);
   for (int64_t q = 0; q < n_quartets; ++q) {
-    const int64_t k = count[(size_t)qkey[(size_t)q]]++;
+    const int64_t k = count[(size_t)qkey[q]]++;
     for (int i = 0; i < 4; ++i) quart_sorted[4 * k + i] = quart[4 * q + i];
     off_sorted[k] = offsets[q];
   }
@@ -593,16 +617,16 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
   wk.rec = (double*)(ws + b_pairs + b_poff + b_quart + b_ooff);
   e = hipMemcpyAsync((void*)wk.pairs, pairs.data(), 8 * n_pairs, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.pair_off, pair_off.data(), 8 * n_pairs, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.quart, quart_sorted.data(), 16 * n_quartets, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.out_off, off_sorted.data(), 8 * n_quartets, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.quart, quart_sorted.get(), 16 * n_quartets, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.out_off, off_sorted.get(), 8 * n_quartets, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
     auto grid = [&](int64_t waves, int per_cu) {
       const int64_t cap = (int64_t)4 * per_cu * p->ctx->n_cu;
       return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + kEriWavesPerGroup - 1) / kEriWavesPerGroup, cap)));
     };
     hipLaunchKernelGGL(k_eri_pairs, grid(n_pairs, 1), dim3(kEriThreads), 0, st, p->bs, wk);
-    // the small instance: 12 KB of matrices per wavefront, two workgroups and wavefronts per SIMD;
-    // the large one (pair class (2,2) on either side): 32 KB, one
+    // the small instance: 11 KB of matrices per wavefront, two workgroups and wavefronts per SIMD;
+    // the large one (pair class (2,2) on either side): 31 KB, one
     EriWork ws_small = wk, ws_large = wk;
     ws_small.n_quartets = n_small;
     ws_large.n_quartets = n_quartets - n_small;

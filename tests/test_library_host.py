@@ -176,3 +176,25 @@ def test_single_call_without_gpu_fails_cleanly():
     import ctypes
     assert lib.shgo_nuclear_attraction(None, ctypes.byref(hb.struct), ctypes.byref(hn.struct), None, None,
                                        None) == shgo.SHGO_ERR_INVALID_ARG
+
+
+def test_eri_output_size_and_its_checks():
+    # the doubles shgo_eri_blocks writes: sum of (2la+1)(2lb+1)(2lc+1)(2ld+1), counted here from the
+    # basis's l; the index and l checks, host only
+    b, _ = synth.molecule(seed=16, n_atoms=3, box=3.0, ls=(0, 1, 2), kmax=2)
+    rng = np.random.default_rng(5)
+    q = rng.integers(0, len(b.l), (500, 4)).astype(np.int32)
+    dim = 2 * np.asarray(b.l, dtype=np.int64) + 1
+    assert shgo.shgo_eri_output_size(b, q) == int(np.prod(dim[q], axis=1).sum())
+    assert shgo.shgo_eri_output_size(b, np.zeros((0, 4), np.int32)) == 0
+    for bad in (-1, len(b.l)):
+        qq = q.copy()
+        qq[7, 2] = bad
+        with pytest.raises(shgo.ShgoError) as e:
+            shgo.shgo_eri_output_size(b, qq)
+        assert e.value.status == shgo.SHGO_ERR_INVALID_ARG
+    bf, _ = synth.molecule(seed=16, n_atoms=2, box=3.0, ls=(0, 1, 2, 3), kmax=1)
+    f = int(np.flatnonzero(np.asarray(bf.l) == 3)[0])
+    with pytest.raises(shgo.ShgoError) as e:
+        shgo.shgo_eri_output_size(bf, np.array([[0, 0, f, 0]], np.int32))
+    assert e.value.status == shgo.SHGO_ERR_UNSUPPORTED_L
