@@ -80,42 +80,45 @@ __device__ __forceinline__ void overlap_rows(const DevBasis& bs, const DevPairs&
       const double gam = dfac * 1.7724538509055160273 / ldexp(1.0, lam + 1);  // Gamma(lam + 3/2)
       cf[m][lam] = aa * ab * (12.566370614359172954 / (2 * lam + 1)) * 0.5 * gam;
     }
-  double sm[LB + 1];
+  // G[lam] = sum over the primitive pairs of w_a w_b e^{-mu R^2} p^{-3/2} t_a^(la-lam) t_b^(lb-lam) p^{-lam};
+  // since t_a t_b p = -mu R^2, each step down in lam multiplies the term by -mu R^2
+  double g[LB + 1];
 #pragma unroll
-  for (int m = 0; m <= LB; ++m) sm[m] = 0.0;
+  for (int lam = 0; lam <= LB; ++lam) g[lam] = 0.0;
   const int64_t o1 = active ? bs.prim_off[s1] : 0, o2 = active ? bs.prim_off[s2] : 0;
   const int K1 = active ? bs.nprim[s1] : 0, K2 = active ? bs.nprim[s2] : 0;
   for (int idx = row; idx < K1 * K2; idx += NA) {
     const int i = idx / K2, j = idx - i * K2;
     const double a = bs.expo[o1 + i], b = bs.expo[o2 + j];
-    const double p = a + b, ip = 1.0 / p, mu = a * b * ip;
-    const double pre = bs.w[o1 + i] * bs.w[o2 + j] * exp_neg(mu * R * R) * ip * sqrt(ip);
-    const double ta = b * R * ip, tb = -a * R * ip;
-    double pa[LA + 1], pb[LB + 1], pl[LB + 1];
-    pa[0] = 1.0;
-    pb[0] = 1.0;
-    pl[0] = 1.0;
+    const double p = a + b, ip = 1.0 / p, mr2 = a * b * ip * R * R;
+    double u = bs.w[o1 + i] * bs.w[o2 + j] * exp_neg(mr2) * ip * sqrt(ip);
+    const double ta = b * R * ip;
 #pragma unroll
-    for (int k = 1; k <= LA; ++k) pa[k] = pa[k - 1] * ta;
+    for (int k = 0; k < LA - LB; ++k) u *= ta;
 #pragma unroll
-    for (int k = 1; k <= LB; ++k) {
-      pb[k] = pb[k - 1] * tb;
-      pl[k] = pl[k - 1] * ip;
-    }
+    for (int k = 0; k < LB; ++k) u *= ip;
+    g[LB] += u;
 #pragma unroll
-    for (int m = 0; m <= LB; ++m) {
-      double t = 0.0;
-#pragma unroll
-      for (int lam = m; lam <= LB; ++lam) t = fma(cf[m][lam] * pa[LA - lam], pb[LB - lam] * pl[lam], t);
-      sm[m] = fma(pre, t, sm[m]);
+    for (int lam = LB - 1; lam >= 0; --lam) {
+      u *= -mr2;
+      g[lam] += u;
     }
   }
-  // S'(m) summed over the pair's lanes, in one order on every lane (all lanes take part)
+  // G summed over the pair's lanes, in one order on every lane (all lanes take part), then
+  // S'(m) = sum_lam cf[m][lam] G[lam]
+  double gt[LB + 1];
+#pragma unroll
+  for (int lam = 0; lam <= LB; ++lam) {
+    double t = 0.0;
+    for (int k = 0; k < NA; ++k) t += __shfl(g[lam], (q * NA + k) & 63);
+    gt[lam] = t;
+  }
   double tot[LB + 1];
 #pragma unroll
   for (int m = 0; m <= LB; ++m) {
     double t = 0.0;
-    for (int k = 0; k < NA; ++k) t += __shfl(sm[m], (q * NA + k) & 63);
+#pragma unroll
+    for (int lam = m; lam <= LB; ++lam) t = fma(cf[m][lam], gt[lam], t);
     tot[m] = t;
   }
   double cth[LA + 1], sth[LA + 1], cph[LA + 1], sph[LA + 1];
