@@ -451,6 +451,8 @@ void shgo_destroy(shgo_context* ctx) {
     shgo_plan_destroy(ctx->call_plan);
   }
   if (ctx->boys_tab) (void)hipFree(ctx->boys_tab);
+  if (ctx->eri_dev) (void)hipFree(ctx->eri_dev);
+  if (ctx->eri_pin) (void)hipHostFree(ctx->eri_pin);
   delete ctx;
 }
 

@@ -28,7 +28,7 @@
 #include "generated/shgo_eri.inc"
 
 #include <algorithm>
-#include <memory>
+#include <cstring>
 #include <unordered_map>
 #include <vector>
 
@@ -515,6 +515,23 @@ k_eri(DevBasis bs, EriWork wk, const double* __restrict__ boys_tab, double* __re
 
 int eri_lmax() { return kEriLmax; }
 
+// Make *buf at least `need` bytes (device memory, or pinned host memory), in whole MiB; the old
+// contents are not kept. No stream may still use the old buffer.
+static hipError_t grow_buffer(void** buf, size_t* have, size_t need, bool pinned_host) {
+  if (*have >= need && *buf) return hipSuccess;
+  if (*buf) (void)(pinned_host ? hipHostFree(*buf) : hipFree(*buf));
+  *buf = nullptr;
+  *have = 0;
+  const size_t mib = (size_t)1 << 20, bytes = std::max(mib, (need + mib - 1) / mib * mib);
+  const hipError_t e = pinned_host ? hipHostMalloc(buf, bytes, hipHostMallocDefault) : hipMalloc(buf, bytes);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    return e;
+  }
+  *have = bytes;
+  return hipSuccess;
+}
+
 hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
                    const int64_t* offsets, double* out, hipStream_t st) {
   if (n_quartets <= 0) return hipSuccess;
@@ -564,8 +581,10 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
   // first (primitive quartets times the matrices' sizes, in buckets of a quarter octave: a
   // counting sort), so that the wavefronts striding over the list take the long quartets early.
   constexpr int kCostBuckets = 256;
-  std::unique_ptr<int32_t[]> quart(new int32_t[(size_t)4 * n_quartets]);
-  std::unique_ptr<int32_t[]> qkey(new int32_t[(size_t)n_quartets]);
+  shgo_context* const ctx = p->ctx;
+  if (ctx->eri_tmp.size() < (size_t)5 * n_quartets) ctx->eri_tmp.resize((size_t)5 * n_quartets);
+  int32_t* const quart = ctx->eri_tmp.data();
+  int32_t* const qkey = quart + (size_t)4 * n_quartets;
   std::vector<int64_t> count(2 * kCostBuckets + 1, 0);
   int64_t n_small = 0;
   for (int64_t q = 0; q < n_quartets; ++q) {
@@ -590,22 +609,28 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
   }
   const int64_t n_pairs = (int64_t)pair_off.size();
   for (int k = 0; k < 2 * kCostBuckets; ++k) count[(size_t)k + 1] += count[(size_t)k];
-  std::unique_ptr<int32_t[]> quart_sorted(new int32_t[(size_t)4 * n_quartets]);
-  std::unique_ptr<int64_t[]> off_sorted(new int64_t[(size_t)n_quartets]);
+  // one workspace: pairs, pair offsets, quartets, output offsets (the index part, staged in
+  // pinned host memory and uploaded by one copy), then the records; each 256-byte aligned
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  const int64_t b_pairs = up(8 * n_pairs), b_poff = up(8 * n_pairs), b_quart = up(16 * n_quartets),
+                b_ooff = up(8 * n_quartets), b_rec = up(8 * rec_size);
+  const int64_t b_index = b_pairs + b_poff + b_quart + b_ooff;
+  hipError_t e = grow_buffer(&ctx->eri_dev, &ctx->eri_dev_bytes, (size_t)(b_index + b_rec), false);
+  if (e == hipSuccess) e = grow_buffer(&ctx->eri_pin, &ctx->eri_pin_bytes, (size_t)b_index, true);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);  // the caller's pair build is still in flight
+    return e;
+  }
+  char* const ws = (char*)ctx->eri_dev;
+  char* const hs = (char*)ctx->eri_pin;
+  std::memcpy(hs, pairs.data(), (size_t)8 * n_pairs);
+  std::memcpy(hs + b_pairs, pair_off.data(), (size_t)8 * n_pairs);
+  int32_t* const quart_sorted = (int32_t*)(hs + b_pairs + b_poff);
+  int64_t* const off_sorted = (int64_t*)(hs + b_pairs + b_poff + b_quart);
   for (int64_t q = 0; q < n_quartets; ++q) {
     const int64_t k = count[(size_t)qkey[q]]++;
     for (int i = 0; i < 4; ++i) quart_sorted[4 * k + i] = quart[4 * q + i];
     off_sorted[k] = offsets[q];
-  }
-  // one workspace: pairs, pair offsets, quartets, output offsets, records (each 256-byte aligned)
-  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
-  const int64_t b_pairs = up(8 * n_pairs), b_poff = up(8 * n_pairs), b_quart = up(16 * n_quartets),
-                b_ooff = up(8 * n_quartets), b_rec = up(8 * rec_size);
-  char* ws = nullptr;
-  hipError_t e = hipMalloc(&ws, (size_t)(b_pairs + b_poff + b_quart + b_ooff + b_rec));
-  if (e != hipSuccess) {
-    (void)hipStreamSynchronize(st);  // the caller's pair build is still in flight
-    return e;
   }
   EriWork wk;
   wk.n_pairs = n_pairs;
@@ -614,11 +639,8 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
   wk.pair_off = (const int64_t*)(ws + b_pairs);
   wk.quart = (const int32_t*)(ws + b_pairs + b_poff);
   wk.out_off = (const int64_t*)(ws + b_pairs + b_poff + b_quart);
-  wk.rec = (double*)(ws + b_pairs + b_poff + b_quart + b_ooff);
-  e = hipMemcpyAsync((void*)wk.pairs, pairs.data(), 8 * n_pairs, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.pair_off, pair_off.data(), 8 * n_pairs, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.quart, quart_sorted.get(), 16 * n_quartets, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync((void*)wk.out_off, off_sorted.get(), 8 * n_quartets, hipMemcpyHostToDevice, st);
+  wk.rec = (double*)(ws + b_index);
+  e = hipMemcpyAsync(ws, hs, (size_t)b_index, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
     auto grid = [&](int64_t waves, int per_cu) {
       const int64_t cap = (int64_t)4 * per_cu * p->ctx->n_cu;
@@ -640,10 +662,9 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
                          ws_large, p->ctx->boys_tab, out);
     e = hipGetLastError();
   }
-  // the host vectors and the workspace live until the stream has finished with them
+  // the staged host copy and the workspace are reused by the next call: wait for the stream
   const hipError_t e2 = hipStreamSynchronize(st);
   if (e == hipSuccess) e = e2;
-  (void)hipFree(ws);
   return e;
 }
 

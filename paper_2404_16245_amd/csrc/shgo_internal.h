@@ -398,6 +398,14 @@ struct shgo_context {
   std::vector<char> call_key;
   // this device's address of the library's static scratch array (shgo_nuclear_attraction_noalloc)
   void* scratch = nullptr;
+  // the two-electron call's buffers, kept for the next call and grown as needed (freed by
+  // shgo_destroy): its device workspace, a pinned host copy of the workspace's index part, and
+  // host scratch for the quartets' pairs and sort keys
+  void* eri_dev = nullptr;
+  size_t eri_dev_bytes = 0;
+  void* eri_pin = nullptr;
+  size_t eri_pin_bytes = 0;
+  std::vector<int32_t> eri_tmp;
 };
 
 struct shgo_plan {
