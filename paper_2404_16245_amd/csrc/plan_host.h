@@ -84,6 +84,7 @@ struct PlanCounts {
   int64_t integrals = 0;        // sum of (2la+1)(2lb+1) over the kept shell pairs
   int64_t class_cand[kNumClasses] = {0};
   std::vector<int64_t> bf_off;  // first basis function of each shell
+  std::vector<int32_t> by_l;    // [kLmax + 2] first entry of each l, then the shells by l, then primitive count
   std::vector<int64_t> blk_off; // output offset of each listed pair (pair plans)
 };
 
@@ -113,6 +114,18 @@ inline PlanCounts plan_counts(const shgo_basis* b, int full, int64_t n_pairs, co
     pc.bf_off[(size_t)s] = pc.nbf;
     pc.nbf += 2 * b->l[s] + 1;
     pc.n_prims = std::max<int64_t>(pc.n_prims, b->prim_offset[s] + b->n_prim[s]);
+  }
+  // the shells of each l, by primitive count and then index (so that neighbouring pairs of a
+  // class have alike contraction lengths), after the kLmax + 2 offsets of the l
+  pc.by_l.assign((size_t)b->n_shells + kLmax + 2, 0);
+  for (int s = 0; s < b->n_shells; ++s) pc.by_l[(size_t)b->l[s] + 1]++;
+  for (int l = 0; l <= kLmax; ++l) pc.by_l[(size_t)l + 1] += pc.by_l[(size_t)l];
+  {
+    std::vector<int32_t> next(pc.by_l.begin(), pc.by_l.begin() + kLmax + 1);
+    for (int s = 0; s < b->n_shells; ++s) pc.by_l[(size_t)kLmax + 2 + next[(size_t)b->l[s]]++] = s;
+    for (int l = 0; l <= kLmax; ++l)
+      std::stable_sort(pc.by_l.begin() + kLmax + 2 + pc.by_l[(size_t)l], pc.by_l.begin() + kLmax + 2 + pc.by_l[(size_t)l + 1],
+                       [&](int32_t x, int32_t y) { return b->n_prim[x] < b->n_prim[y]; });
   }
   auto cls = [](int la, int lb) { return class_id(std::max(la, lb), std::min(la, lb)); };
   if (full) {
@@ -149,7 +162,7 @@ inline shgo_status check_class_sizes(const PlanCounts& pc, std::string* msg) {
 // The plan's device workspace: one block carved into every array the kernels use, each at a
 // 256-byte boundary. Offsets in bytes from the block's start.
 enum Buf {
-  kCenter, kL, kNprim, kPoff, kBfOff, kExpo, kCoef, kW, kNuc, kPa, kPb, kBlk, kKey, kS1, kS2, kOrig, kNsurv, kRank,
+  kCenter, kL, kNprim, kPoff, kBfOff, kByL, kExpo, kCoef, kW, kNuc, kPa, kPb, kBlk, kKey, kS1, kS2, kOrig, kNsurv, kRank,
   kKeyCount, kKeyOff, kDst0, kDst1, kQueue, kItemOff, kItems, kArgs, kEnergy, kNumBufs
 };
 struct PlanLayout {
@@ -177,6 +190,7 @@ inline PlanLayout plan_layout(const PlanCounts& pc, int32_t n_shells, int32_t n_
   L.bytes[kNprim] = 4 * ns;
   L.bytes[kPoff] = 8 * ns;
   L.bytes[kBfOff] = 8 * ns;
+  L.bytes[kByL] = 4 * (ns + kLmax + 2);
   L.bytes[kExpo] = 8 * np;
   L.bytes[kCoef] = 8 * np;
   L.bytes[kW] = 8 * np;

@@ -154,6 +154,7 @@ void carve(shgo_plan* p, const shgo_host::PlanLayout& L, char* base, int full) {
   p->bs.nprim = (const int32_t*)at(kNprim);
   p->bs.prim_off = (const int64_t*)at(kPoff);
   p->bs.bf_off = (const int64_t*)at(kBfOff);
+  p->bs.by_l = (const int32_t*)at(kByL);
   p->bs.expo = (const double*)at(kExpo);
   p->bs.coef = (const double*)at(kCoef);
   p->bs.w = (double*)at(kW);
@@ -204,6 +205,7 @@ shgo_status plan_host_part(shgo_context* ctx, const shgo_basis* b, const shgo_nu
   p->full = full;
   p->n_shells = b->n_shells;
   for (int32_t i = 0; i < b->n_shells; ++i) p->max_nprim = std::max(p->max_nprim, b->n_prim[i]);
+  for (int l = 0; l < SHGO_LMAX + 2; ++l) p->l_first[l] = pc.by_l[(size_t)l];
   p->n_nuc = n->n_nuclei;
   p->screen = screen;
   p->nbf = pc.nbf;
@@ -241,6 +243,7 @@ hipError_t upload_inputs(shgo_plan* p, const shgo_basis* b, const shgo_nuclei* n
   up(p->bs.nprim, b->n_prim, 4 * ns);
   up(p->bs.prim_off, b->prim_offset, 8 * ns);
   up(p->bs.bf_off, pc.bf_off.data(), 8 * ns);
+  up(p->bs.by_l, pc.by_l.data(), 4 * pc.by_l.size());
   up(p->bs.expo, b->exponent, 8 * np);
   up(p->bs.coef, b->coef, 8 * np);
   // nuclei {x, y, z, Z}: positions and charges strided into the 32-byte records
@@ -258,6 +261,9 @@ hipError_t upload_inputs(shgo_plan* p, const shgo_basis* b, const shgo_nuclei* n
   }
   // the key counters start at zero; every k_scan_keys clears them again after reading
   if (e == hipSuccess) launch_fill((double*)p->pr.key_count, (int64_t)kNumKeys / 2, st);
+  // the primitive weights depend on the basis alone: computed here once (every pair build
+  // computes them again, to the same values)
+  if (e == hipSuccess) launch_weights(p, st);
   if (e == hipSuccess) e = hipGetLastError();
   return e;
 }
@@ -549,8 +555,10 @@ shgo_status shgo_execute_overlap(shgo_plan* p, double* out, void* stream) {
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
   if (p->n_cand == 0) return SHGO_OK;
   hipStream_t st = (hipStream_t)stream;
-  // the plan's pair build (primitive weights, class-sorted pairs, output destinations), as for V
-  launch_pair_build(p, st);
+  // a matrix plan's pairs are enumerated by class from the shells ordered by l and the primitive
+  // weights were computed with the plan, so the kernels alone run; a pair plan's pairs come from
+  // its pair build, as for V
+  if (!p->full) launch_pair_build(p, st);
   launch_overlap(p, out, st);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("launch failed: ") + hipGetErrorString(e));
@@ -634,13 +642,12 @@ shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t 
   if (s != SHGO_OK) return fail(ctx, s, err);
   if (n_quartets == 0 || basis->n_shells == 0) return SHGO_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
-  // a pair plan of one pair uploads the basis; its pair build computes the primitive weights
+  // a pair plan of one pair uploads the basis and computes its primitive weights
   const int32_t zero = 0;
   shgo_plan* p = nullptr;
   s = make_plan(ctx, basis, &none, 0, 1, &zero, &zero, 0.0, 0, &p);
   if (s != SHGO_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  launch_pair_build(p, st);
   hipError_t e = run_eri(p, basis, n_quartets, quartets, offsets.get(), out, st);
   shgo_plan_destroy(p);
   if (e == hipErrorOutOfMemory) return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "no device memory for the two-electron workspace");

@@ -617,10 +617,7 @@ hipError_t run_eri(const shgo_plan* p, const shgo_basis* basis, int64_t n_quarte
   const int64_t b_index = b_pairs + b_poff + b_quart + b_ooff;
   hipError_t e = grow_buffer(&ctx->eri_dev, &ctx->eri_dev_bytes, (size_t)(b_index + b_rec), false);
   if (e == hipSuccess) e = grow_buffer(&ctx->eri_pin, &ctx->eri_pin_bytes, (size_t)b_index, true);
-  if (e != hipSuccess) {
-    (void)hipStreamSynchronize(st);  // the caller's pair build is still in flight
-    return e;
-  }
+  if (e != hipSuccess) return e;  // nothing of this call is on the stream yet
   char* const ws = (char*)ctx->eri_dev;
   char* const hs = (char*)ctx->eri_pin;
   std::memcpy(hs, pairs.data(), (size_t)8 * n_pairs);

@@ -122,6 +122,7 @@ struct DevBasis {
   const double* coef;      // [nprim total]
   double* w;               // [nprim total] normalised weights (written by k_classify)
   const int64_t* bf_off;   // [n] first basis function of each shell
+  const int32_t* by_l;     // [SHGO_LMAX + 2] first entry of each l, then [n] the shells by l, then primitive count
   int32_t n_shells;
   int64_t nbf;
 };
@@ -413,6 +414,7 @@ struct shgo_plan {
   int full = 0;
   int32_t n_shells = 0, n_nuc = 0;
   int32_t max_nprim = 0;        // the longest contraction of the basis
+  int32_t l_first[SHGO_LMAX + 2] = {0};  // host copy of the first SHGO_LMAX + 2 entries of bs.by_l
   int64_t nbf = 0, n_cand = 0, out_size = 0;
   int64_t integrals = 0;        // sum of (2la+1)(2lb+1) over the kept shell pairs
   int64_t kept_pairs = 0;       // shell pairs that keep at least one primitive pair
@@ -457,6 +459,8 @@ namespace shgo_impl {
 // ---------------------------------------------------------------------------------------------
 // shgo_pairs.hip
 void launch_pair_build(const shgo_plan* p, hipStream_t st);
+// the pair build's primitive weights alone (k_classify's weight workgroups)
+void launch_weights(const shgo_plan* p, hipStream_t st);
 void launch_fill(double* ptr, int64_t n, hipStream_t st);
 hipError_t launch_boys(int mmax, int64_t n, const double* T, double* F, const double* tab, hipStream_t st);
 // shgo_integrals.hip and shgo_integrals_mixed.hip: the two forms of the integral kernel; the

@@ -34,6 +34,7 @@ __host__ __device__ constexpr double fact_d(int n) {
 struct OvlSched {
   int64_t slot_first[kNumClasses + 1];  // class-sorted slots of class c: [slot_first[c], slot_first[c+1])
   int64_t wave_first[kNumClasses + 1];  // wavefronts of class c: [wave_first[c], wave_first[c+1])
+  int32_t l_first[SHGO_LMAX + 2];       // a matrix plan's shells of l: entries [l_first[l], l_first[l+1]) of by_l
 };
 
 __host__ __device__ constexpr int ovl_pairs_per_wave(int la) { return 64 / (2 * la + 1); }
@@ -45,16 +46,45 @@ __device__ __forceinline__ void stage_sync() {
 }
 
 template <int LA, int LB>
-__device__ __forceinline__ void overlap_rows(const DevBasis& bs, const DevPairs& pr, int64_t slot0, int64_t slot_end,
+__device__ __forceinline__ void overlap_rows(const DevBasis& bs, const DevPairs& pr, const OvlSched& sc, int64_t slot0,
                                              double* __restrict__ stg, int64_t* __restrict__ sd,
                                              double* __restrict__ out) {
+  constexpr int C = class_id(LA, LB);
+  const int64_t slot_end = sc.slot_first[C + 1];
   constexpr int NA = 2 * LA + 1, NB = 2 * LB + 1, P = ovl_pairs_per_wave(LA);
   const int lane = threadIdx.x & 63;
   const int q = lane / NA, row = lane - q * NA;
   const int64_t slot = slot0 + q;
   const bool active = q < P && slot < slot_end;
+  // the pair: a matrix plan's k-th pair of the class from the shells ordered by l and primitive
+  // count (every shell of l = LA with every shell of l = LB; for LA = LB the pairs i <= j of the
+  // list, each written with its mirror), else the pair build's slot
+  int s1 = 0, s2 = 0;
+  int64_t d0 = 0, d1 = 0;
+  if (active) {
+    if (pr.full) {
+      const int32_t* const list = bs.by_l + SHGO_LMAX + 2;
+      const int fa = sc.l_first[LA], fb = sc.l_first[LB], nb = sc.l_first[LB + 1] - fb;
+      const int k = (int)(slot - sc.slot_first[C]);
+      int i, j;
+      if (LA == LB) {
+        tri_pair(k, nb, i, j);
+      } else {
+        i = k / nb;
+        j = k - i * nb;
+      }
+      s1 = list[fa + i];
+      s2 = list[fb + j];
+      d0 = bs.bf_off[s1];
+      d1 = bs.bf_off[s2];
+    } else {
+      s1 = pr.s1[slot];
+      s2 = pr.s2[slot];
+      d0 = pr.dst0[slot];
+      d1 = pr.dst1[slot];
+    }
+  }
   PairState ps;
-  const int s1 = active ? pr.s1[slot] : 0, s2 = active ? pr.s2[slot] : 0;
 #pragma unroll
   for (int x = 0; x < 3; ++x) {
     ps.A[x] = active ? bs.center[3 * s1 + x] : 0.0;
@@ -134,7 +164,6 @@ __device__ __forceinline__ void overlap_rows(const DevBasis& bs, const DevPairs&
   Rot<LB>::apply(x, cth, sth, cph, sph);  // row `row` of the laboratory block
   // rows through the wavefront's LDS stage: entry (q NA + row) NB + j is pair q's (row, j), so
   // consecutive lanes then store consecutive columns of one row
-  const int64_t d0 = active ? pr.dst0[slot] : 0, d1 = active ? pr.dst1[slot] : 0;
 #pragma unroll
   for (int j = 0; j < NB; ++j) stg[lane * NB + j] = x[j];
   if (row == 0) {
@@ -175,7 +204,7 @@ __device__ __forceinline__ void overlap_dispatch(int c, int64_t gw, const DevBas
     constexpr int C = class_id(LA, LB);
     if (c == C) {
       const int64_t slot0 = sc.slot_first[C] + (gw - sc.wave_first[C]) * ovl_pairs_per_wave(LA);
-      overlap_rows<LA, LB>(bs, pr, slot0, sc.slot_first[C + 1], stg, sd, out);
+      overlap_rows<LA, LB>(bs, pr, sc, slot0, stg, sd, out);
       return;
     }
     if constexpr (LB < LA)
@@ -207,6 +236,7 @@ __global__ void __launch_bounds__(256) k_overlap(DevBasis bs, DevPairs pr, OvlSc
 // register-allocated for the largest block.
 void launch_overlap(const shgo_plan* p, double* out, hipStream_t st) {
   OvlSched sc;
+  for (int l = 0; l < SHGO_LMAX + 2; ++l) sc.l_first[l] = p->l_first[l];
   sc.slot_first[0] = 0;
   sc.wave_first[0] = 0;
   for (int la = 0, c = 0; la <= SHGO_LMAX; ++la)

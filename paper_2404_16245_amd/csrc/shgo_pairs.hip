@@ -292,6 +292,12 @@ void launch_pair_build(const shgo_plan* p, hipStream_t st) {
   hipLaunchKernelGGL(k_scatter, dim3((int)((p->n_cand + tb - 1) / tb)), dim3(tb), 0, st, p->bs, p->pr);
 }
 
+void launch_weights(const shgo_plan* p, hipStream_t st) {
+  const int G = weight_lanes(p->max_nprim);
+  const int wb = (int)((p->n_shells + kClassifyThreads / G - 1) / (kClassifyThreads / G));
+  if (wb > 0) hipLaunchKernelGGL(k_classify, dim3(wb), dim3(kClassifyThreads), 0, st, p->bs, p->pr, 0, G);
+}
+
 void launch_fill(double* ptr, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   const int tb = 256;
