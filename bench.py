@@ -461,8 +461,9 @@ def measure_eri(shgo, synth, torch, steps):
 
 
 def measure_overlap(shgo, synth, torch, steps):
-    """Overlap matrix S of the batched molecule's basis (nbf 5000, K 1..8), full matrix: the plan's
-    pair build and the overlap kernel per step. Bound by writing S (8 nbf^2 bytes)."""
+    """Overlap matrix S of the batched molecule's basis (nbf 5000, K 1..8), full matrix: the overlap
+    kernels per step (a matrix plan's overlap enumerates its pairs without the pair build; the
+    contraction weights are computed when the plan is made). Bound by writing S (8 nbf^2 bytes)."""
     basis, nuclei = synth.batched_molecule(seed=3)
     ctx = shgo.context(0)
     plan = shgo.shgo_plan_matrix(ctx, basis, nuclei, 0.0)
