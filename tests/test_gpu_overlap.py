@@ -109,3 +109,30 @@ def test_single_class_wavefronts_pair_list(shgo):
     assert 50 < flip.sum() < 90
     got = shgo.overlap_pairs(b, pa, pb).cpu().numpy()
     assert_parity(got, oracle.overlap_blocks(b, pa, pb), "140 (3,2) pairs, half swapped")
+
+
+def test_bench_basis_sampled(shgo):
+    # the S that bench.py times: the 200-atom batched basis (nbf 5000, l = 0..4, K 1..8), whose
+    # matrix plan enumerates each class's pairs from the shells ordered by l and primitive count;
+    # checked on 40 sampled shell pairs of every (la, lb) class (both orientations in the matrix),
+    # the unit diagonal of every shell's block with itself, and exact symmetry
+    b, _ = synth.batched_molecule(seed=3)
+    S = shgo.overlap(b).cpu().numpy()
+    assert np.isfinite(S).all()
+    assert np.array_equal(S, S.T)
+    ls = np.asarray(b.l)
+    off = np.asarray(b.shell_offsets())
+    rng = np.random.default_rng(41)
+    pa, pb = [], []
+    for la in range(5):
+        for lb in range(la + 1):
+            sa, sb = np.flatnonzero(ls == la), np.flatnonzero(ls == lb)
+            pa += list(rng.choice(sa, 40))
+            pb += list(rng.choice(sb, 40))
+    pa, pb = np.array(pa, np.int32), np.array(pb, np.int32)
+    blocks = oracle.split_blocks(oracle.overlap_blocks(b, pa, pb), b, pa, pb)
+    for k, (a, c) in enumerate(zip(pa, pb)):
+        na, nc = 2 * ls[a] + 1, 2 * ls[c] + 1
+        assert_parity(S[off[a]:off[a] + na, off[c]:off[c] + nc], blocks[k], f"pair ({a}, {c})")
+    diag = np.concatenate([np.diag(S[o:o + 2 * l + 1, o:o + 2 * l + 1]) for o, l in zip(off, ls)])
+    assert np.abs(diag - 1.0).max() < 1e-12
