@@ -246,11 +246,12 @@ shgo_status shgo_execute_cartesian(shgo_plan* plan, double* out, void* stream);
  *   out        device, the blocks in quartet order, each (2la+1)(2lb+1)(2lc+1)(2ld+1) doubles
  *              row-major in the listed shell order (a slowest)
  * Shells up to l = 2 (SHGO_ERR_UNSUPPORTED_L otherwise); SHGO_ERR_INVALID_ARG for a shell index
- * out of range; both before any device work. Uploads the basis, the quartets' distinct shell pairs
- * and their per-primitive-pair records (the pairs' expansions, built once per pair) to a device
- * workspace that the context keeps for its next call, with a pinned host copy of its index part
- * (each grown when a call needs more, freed by shgo_destroy; SHGO_ERR_OUT_OF_MEMORY if it cannot
- * be allocated), runs on `stream` and waits for it before returning. */
+ * out of range; both before any device work. Uploads the basis (kept by the context for the next
+ * call with a byte-identical basis), the quartets' distinct shell pairs and their
+ * per-primitive-pair records (the pairs' expansions, built once per pair) to a device workspace
+ * that the context keeps for its next call, with a pinned host copy of its index part (each grown
+ * when a call needs more, freed by shgo_destroy; SHGO_ERR_OUT_OF_MEMORY if it cannot be
+ * allocated), runs on `stream` and waits for it before returning. */
 shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t n_quartets, const int32_t* quartets,
                             double* out, void* stream);
 

@@ -457,6 +457,7 @@ void shgo_destroy(shgo_context* ctx) {
     shgo_plan_destroy(ctx->call_plan);
   }
   if (ctx->boys_tab) (void)hipFree(ctx->boys_tab);
+  if (ctx->eri_plan) shgo_plan_destroy(ctx->eri_plan);
   if (ctx->eri_dev) (void)hipFree(ctx->eri_dev);
   if (ctx->eri_pin) (void)hipHostFree(ctx->eri_pin);
   delete ctx;
@@ -642,14 +643,23 @@ shgo_status shgo_eri_blocks(shgo_context* ctx, const shgo_basis* basis, int64_t 
   if (s != SHGO_OK) return fail(ctx, s, err);
   if (n_quartets == 0 || basis->n_shells == 0) return SHGO_OK;
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, "hipSetDevice failed");
-  // a pair plan of one pair uploads the basis and computes its primitive weights
-  const int32_t zero = 0;
-  shgo_plan* p = nullptr;
-  s = make_plan(ctx, basis, &none, 0, 1, &zero, &zero, 0.0, 0, &p);
-  if (s != SHGO_OK) return s;
+  // a pair plan of one pair uploads the basis and computes its primitive weights; the context
+  // keeps it for the next call with a byte-identical basis
+  std::vector<char> key = call_key(basis, &none, 0.0);
+  if (!ctx->eri_plan || key != ctx->eri_key) {
+    if (ctx->eri_plan) {
+      shgo_plan_destroy(ctx->eri_plan);  // the last call waited for its stream
+      ctx->eri_plan = nullptr;
+    }
+    const int32_t zero = 0;
+    shgo_plan* np = nullptr;
+    s = make_plan(ctx, basis, &none, 0, 1, &zero, &zero, 0.0, 0, &np);
+    if (s != SHGO_OK) return s;
+    ctx->eri_plan = np;
+    ctx->eri_key = std::move(key);
+  }
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = run_eri(p, basis, n_quartets, quartets, offsets.get(), out, st);
-  shgo_plan_destroy(p);
+  hipError_t e = run_eri(ctx->eri_plan, basis, n_quartets, quartets, offsets.get(), out, st);
   if (e == hipErrorOutOfMemory) return fail(ctx, SHGO_ERR_OUT_OF_MEMORY, "no device memory for the two-electron workspace");
   if (e != hipSuccess) return fail(ctx, SHGO_ERR_DEVICE, std::string("two-electron evaluation failed: ") + hipGetErrorString(e));
   return SHGO_OK;

@@ -402,6 +402,8 @@ struct shgo_context {
   // the two-electron call's buffers, kept for the next call and grown as needed (freed by
   // shgo_destroy): its device workspace, a pinned host copy of the workspace's index part, and
   // host scratch for the quartets' pairs and sort keys
+  shgo_plan* eri_plan = nullptr;  // the pair plan of the last call's basis (uploaded basis, weights)
+  std::vector<char> eri_key;      // and the bytes of that basis
   void* eri_dev = nullptr;
   size_t eri_dev_bytes = 0;
   void* eri_pin = nullptr;
