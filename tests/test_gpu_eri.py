@@ -2,8 +2,8 @@
 (oracle/eri.py), element by element: every ordered combination of s, p and d shells (both orders
 inside each pair, so the kernel's swaps are covered), contracted shells of a synthetic molecule
 with shells on one center, more quartets than the grid has wavefronts, a basis of more than 2048
-shells (the host's hashed pair index), the error paths, and the bench's own call (every unique
-quartet of its 10-atom molecule) on a sample.
+shells (the host's hashed pair index), the error paths, the bench's own call (every unique
+quartet of its 10-atom molecule) on a sample, and long contractions (several staging rounds).
 Bar as for the nuclear attraction: 1e-13 + 1e-11 |ref|."""
 import itertools
 
@@ -139,3 +139,20 @@ def test_bench_workload_sampled(shgo):
                            rng.choice(np.flatnonzero(~dd), 20, replace=False), rng.choice(len(q), 20, replace=False)])
     for k in pick:
         assert_parity(got[offs[k]:offs[k + 1]], eri.eri_block(b, *q[k]).ravel(), f"quartet {k} {q[k]}")
+
+
+def test_long_contractions_span_several_staging_rounds(shgo):
+    # contractions of 4 and 5 primitives: 16 to 25 ket primitive pairs, so the kernel stages the
+    # Boys values and harmonics in several rounds (5 slots in the small instance, 9 in the large);
+    # (pp|pp) and (dp|ps) in the small instance, (dd|dd), (dd|ss) and (dd|pd) (ket swapped) in the
+    # large one
+    rng = np.random.default_rng(23)
+    cen = rng.normal(0, 1.2, (3, 3))
+
+    def shell(l, c, K):
+        e = np.sort(np.exp(rng.uniform(np.log(0.15), np.log(12.0), K)))[::-1]
+        return (l, cen[c], list(e), list(rng.uniform(0.2, 1.0, K)))
+
+    b = _basis([shell(0, 0, 5), shell(1, 1, 4), shell(2, 2, 4), shell(2, 0, 4), shell(1, 2, 5)])
+    q = np.array([[1, 4, 1, 4], [2, 1, 4, 0], [2, 3, 2, 3], [3, 2, 0, 0], [2, 3, 4, 2]], np.int32)
+    assert_parity(shgo.eri_blocks(b, q).cpu().numpy(), eri.eri_blocks(b, q), "long contractions")
